@@ -1,0 +1,87 @@
+"""Strength of the oracle's pins: each plausible mistake below is planted into a
+temporary copy of oracle.c (never into the committed file), compiled, and must
+be caught by at least one of the pins (rigid-body modes, homogeneous patch
+energy, the brute-force tensor-form integral, the classical rotation formulas)."""
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1905_05417_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(os.path.dirname(HERE), "oracle", "oracle.c")
+
+MUTATIONS = {
+    # the printed third column of B (d3 where d2 belongs in the gamma_23 row)
+    "strain_matrix_as_printed": ("B[5][1] = g[2]; B[5][2] = g[1];", "B[5][1] = g[2]; B[5][2] = g[2];"),
+    # clockwise instead of counterclockwise ply rotation
+    "rotation_sign": ("double r[3][3] = {{c, -s, 0.0}, {s, c, 0.0}", "double r[3][3] = {{c, s, 0.0}, {-s, c, 0.0}"),
+    # DF^{-1} instead of DF^{-T} in the pull-back
+    "pullback_transposed": ("grad[a][k] = c->Ji[0 * 3 + k] * gh[0] + c->Ji[1 * 3 + k] * gh[1] + c->Ji[2 * 3 + k] * gh[2];",
+                            "grad[a][k] = c->Ji[k * 3 + 0] * gh[0] + c->Ji[k * 3 + 1] * gh[1] + c->Ji[k * 3 + 2] * gh[2];"),
+    # dropped Jacobian determinant
+    "dropped_jacobian": ("h1 * h2 * h3 * fabs(c->detJ);", "h1 * h2 * h3;"),
+    # tensor shear convention: 13 and 23 swapped in the Voigt map
+    "voigt_order": ("if (a == 0 && b == 2) return 4;\n  return 5;", "if (a == 0 && b == 2) return 5;\n  return 4;"),
+    # whole instead of half interval length in the thickness Gauss map
+    "z_map_length": ("h3 = 0.5 * (cl->zb - cl->za);", "h3 = (cl->zb - cl->za);"),
+}
+
+
+def _build(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    path = tmp_path / ("m_%s.c" % name)
+    path.write_text(src.replace(old, new))
+    lib = tmp_path / ("libm_%s.so" % name)
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-fopenmp", "-fPIC", "-shared", str(path), "-o", str(lib), "-lm"])
+    return str(lib)
+
+
+def _pins_pass(o):
+    rng = np.random.default_rng(99)
+    lam = W.random_small(rng, max_ply=2, n_mat=1)
+    lam.theta[:] = 0.7
+    rp, ci, v = o.assemble(lam)
+    K = o.to_scipy(rp, ci, v, lam.n_rows).toarray()
+    nrm = np.linalg.norm(v)
+    X = W.control_points(lam)
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = 1
+        for r in (np.tile(e, (X.shape[0], 1)), np.cross(e[None, :], X)):
+            r = r.ravel() / np.linalg.norm(r)
+            if np.linalg.norm(K @ r) / nrm > 1e-13:
+                return False
+    A = rng.standard_normal((3, 3))
+    u = (X @ A.T).ravel()
+    eps = np.array([A[0, 0], A[1, 1], A[2, 2], A[0, 1] + A[1, 0], A[0, 2] + A[2, 0], A[1, 2] + A[2, 1]])
+    D = o.rotate(lam.C[0], 0.7)
+    E = math.fsum(u * (K @ u))
+    if abs(E - abs(np.linalg.det(lam.jac)) * eps @ D @ eps) > 1e-12 * abs(E):
+        return False
+    C = W.material(W.CARBON)
+    th = 0.6
+    c, s = np.cos(th), np.sin(th)
+    Dr = o.rotate(C, th)
+    q16 = (C[0, 0] - C[0, 1] - 2 * C[3, 3]) * s * c**3 + (C[0, 1] - C[1, 1] + 2 * C[3, 3]) * s**3 * c
+    if abs(Dr[0, 3] - q16) > 1e-12 * abs(C).max():
+        return False
+    if abs(Dr[4, 4] - (C[4, 4] * c * c + C[5, 5] * s * s)) > 1e-12 * abs(C).max():
+        return False
+    return True
+
+
+def test_unmutated_oracle_passes_the_pins(oracle):
+    assert _pins_pass(oracle)
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(oracle, tmp_path, name):
+    old, new = MUTATIONS[name]
+    path = _build(tmp_path, name, old, new)
+    with oracle.using_library(path):
+        assert not _pins_pass(oracle), "mutation %s slipped through the pins" % name
