@@ -1,0 +1,156 @@
+/*
+ * lamasm.h -- C ABI of the fast layered-stiffness assembly library (liblamasm.so).
+ *
+ * The library assembles the 3D Galerkin stiffness matrix K of a laminated
+ * solid (Antolin, arXiv 1905.05417) on one gfx950 GPU:
+ *
+ *   K^{ij} = sum_l sum_{a,b in {1,2}} P_{l,ab}^{is js} Q_{l,ab}^{it jt}        (Sec. 3, eq. Km_2)
+ *
+ * P are 2D in-plane integrals (eq. P), computed once per set of plies sharing
+ * a material and an orientation (or once per material and angular harmonic,
+ * Remark 3), and Q are 1D through-thickness integrals per ply (eq. Q).  The
+ * result is written into a preallocated CSR pattern.  A standard 3D
+ * element-by-element assembly (Sec. 2.4) writes the same CSR for comparison,
+ * and an adjoint maps dL/dK to dL/dC (materials) and dL/dtheta (plies).
+ *
+ * Conventions
+ *  - Basis (Assumption 1): B^i = S^{is}(xi1,xi2) T^{it}(xi3), in-plane
+ *    is = i1 + n1*i2 (tensor-product B-splines of degrees p1, p2), thickness
+ *    functions it (B-splines of degree q).  Global function i = it*ns + is,
+ *    degree of freedom 3*i + r (r = displacement component x,y,z), eq. a_0.
+ *  - Geometry (Assumption 2, eq. extrusion): x = DF xi with a constant 3x3 map
+ *    gradient DF (an affine extrusion; a box plate is diag(Lx, Ly, H)).
+ *  - Plies (Sec. 2.3): ply l occupies xi3 in [iface[l], iface[l+1]],
+ *    iface[0] = 0 < ... < iface[n_ply] = 1, ply 0 at the bottom.
+ *  - Materials: 6x6 matrices in material axes, Voigt order
+ *    (11,22,33,12,13,23) with engineering shears (eq. D), row-major, used as
+ *    given (no symmetrisation).  Ply l uses material ply_mat[l] rotated by
+ *    theta[l] radians counterclockwise about +e3 (fibre axis (cos, sin, 0)).
+ *  - CSR: int64 row pointers, int32 column indices, FP64 values; columns of a
+ *    row ascending; the pattern is structural (all pairs of functions whose
+ *    supports share a cell, times dense 3x3 blocks) and keeps explicit zeros.
+ *
+ * Ownership and streams
+ *  - The caller owns every device buffer: the workspace, C, theta, vals,
+ *    rowptr, colind, gradients.  A plan owns host memory only.
+ *  - Device entry points are asynchronous on the given stream (a hipStream_t
+ *    passed as void*; NULL is the default stream), never allocate device
+ *    memory and never synchronise.  Errors of earlier asynchronous work may
+ *    surface as LAM_EHIP on a later call.
+ *  - One workspace per stream that uses it concurrently.
+ */
+#ifndef LAMASM_H
+#define LAMASM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define LAM_API __attribute__((visibility("default")))
+#else
+#define LAM_API
+#endif
+
+typedef int32_t lam_status;
+#define LAM_OK 0
+#define LAM_EINVAL (-1)  /* null pointer, bad enum, bad count */
+#define LAM_EKNOT (-2)   /* knot vector not open on [0,1], decreasing, or degree out of range */
+#define LAM_EPLY (-3)    /* interfaces not strictly increasing from 0 to 1, bad ply/material index */
+#define LAM_EMAT (-4)    /* non-finite material or angle, singular map gradient */
+#define LAM_ESIZE (-5)   /* workspace or output length does not match the plan */
+#define LAM_EHIP (-6)    /* HIP runtime error (launch or an earlier asynchronous fault) */
+#define LAM_EUNSUP (-7)  /* supported by the method but not by this build (limits below) */
+
+/* How plies are grouped into the sets that share one 2D operator P.
+ *  BUCKET:     one set per distinct (material, angle) pair, the grouping read
+ *              from desc.ply_theta at plan time (Sec. 3, reuse per distinct
+ *              orientation).  The angles passed at assembly must agree within
+ *              each set; the set's angle is that of its first ply.
+ *  HARMONIC5:  one set per (material, harmonic), harmonics {1, cos 2t,
+ *              sin 2t, cos 4t, sin 4t}: exact for any angles when each
+ *              material has no coupling between {11,22,33,12} and {13,23}
+ *              (orthotropic or monoclinic about the ply plane), Remark 3.
+ *  HARMONIC9:  harmonics up to order 4 including odd ones: exact for any 6x6.
+ */
+#define LAM_SETS_BUCKET 0
+#define LAM_SETS_HARMONIC5 1
+#define LAM_SETS_HARMONIC9 2
+
+/* Limits of this build: 1 <= p1, p2 <= 4, 1 <= q <= 4, Gauss points per
+ * direction 1..8, n_ply <= 4096, n_mat <= 64, nnz < 2^62, columns < 2^31. */
+
+typedef struct {
+  int32_t p1, nk1;          /* in-plane degree and open knot vector (nk1 knots) along xi1 */
+  const double *k1;
+  int32_t p2, nk2;          /* same along xi2 */
+  const double *k2;
+  int32_t q, nk3;           /* thickness degree and knot vector along xi3 */
+  const double *k3;
+  double jac[9];            /* DF, row-major: jac[3*a+b] = d x_a / d xi_b */
+  int32_t n_ply;
+  const double *iface;      /* n_ply+1 interfaces */
+  const int32_t *ply_mat;   /* n_ply material indices in [0, n_mat) */
+  int32_t n_mat;
+  const double *ply_theta;  /* n_ply angles (radians), host; required for BUCKET, ignored otherwise */
+  int32_t ng1, ng2, ngz;    /* Gauss points per in-plane element direction and per thickness
+                               cell (ply x thickness knot span); 0 selects degree+1 */
+  int32_t set_mode;         /* LAM_SETS_* */
+} lam_laminate_desc;
+
+typedef struct lam_plan lam_plan;
+
+/* Validates the descriptor and builds the host tables (knot spans, basis
+ * values at Gauss points, in-plane / thickness / Kronecker patterns, set
+ * grouping).  Host only; copies everything it needs from desc. */
+LAM_API lam_status lam_plan_create(const lam_laminate_desc *desc, lam_plan **out);
+LAM_API void lam_plan_destroy(lam_plan *plan);
+
+/* Sizes: rows of K (3*n), nonzeros, workspace bytes, number of sets, and the
+ * number of plies and materials the device arrays must hold.  Any pointer may be NULL. */
+LAM_API lam_status lam_plan_info(const lam_plan *plan, int64_t *n_rows, int64_t *nnz, int64_t *ws_bytes,
+                                 int32_t *n_sets, int32_t *n_ply, int32_t *n_mat);
+
+/* Copies the plan's constant tables into the device workspace `ws`
+ * (ws_bytes from lam_plan_info, 256-byte aligned).  Must precede every other
+ * device call on that workspace; asynchronous on `stream`. */
+LAM_API lam_status lam_plan_upload(const lam_plan *plan, void *ws, int64_t ws_bytes, void *stream);
+
+/* Writes the CSR pattern: rowptr[n_rows+1] (int64) and colind[nnz] (int32). */
+LAM_API lam_status lam_pattern(const lam_plan *plan, const void *ws, int64_t ws_bytes, int64_t *rowptr,
+                               int32_t *colind, void *stream);
+
+/* Fast 2D x 1D assembly (Sec. 3): vals[nnz] in the order of lam_pattern.
+ * C: device, n_mat*36 doubles; theta: device, n_ply doubles (radians).
+ * Every value of vals is overwritten. */
+LAM_API lam_status lam_assemble(const lam_plan *plan, void *ws, int64_t ws_bytes, const double *C,
+                                const double *theta, double *vals, int64_t nnz, void *stream);
+
+/* Standard 3D assembly (Sec. 2.4): element by element over every
+ * (in-plane element x ply x thickness knot span) cell with the tensor Gauss
+ * rule, element matrices added into the same CSR (colour by colour, no
+ * atomics).  Same arguments and output as lam_assemble. */
+LAM_API lam_status lam_assemble_standard(const lam_plan *plan, void *ws, int64_t ws_bytes, const double *C,
+                                         const double *theta, double *vals, int64_t nnz, void *stream);
+
+/* Adjoint of lam_assemble: given G = dL/dvals (device, nnz doubles in the
+ * order of lam_pattern), writes grad_C = dL/dC (device, n_mat*36, each of the
+ * 36 entries treated as independent) and grad_theta = dL/dtheta (device,
+ * n_ply, per radian).  K is linear in each ply's rotated tensor D_l (eq. Km_0),
+ * so dL/dD_l is a contraction of G with the thickness operators Q_l and the
+ * in-plane moments of the basis; dK is never formed. */
+LAM_API lam_status lam_adjoint(const lam_plan *plan, void *ws, int64_t ws_bytes, const double *C,
+                               const double *theta, const double *grad_vals, int64_t nnz, double *grad_C,
+                               double *grad_theta, void *stream);
+
+LAM_API const char *lam_status_string(lam_status s);
+
+/* Library version, for diagnostics. */
+LAM_API const char *lam_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LAMASM_H */

@@ -1,0 +1,64 @@
+// internal.h -- plan structure and workspace layout shared by the host plan
+// (plan.cpp) and the device code (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "lamasm.h"
+
+namespace lam {
+
+constexpr int MAXP = 4;      // largest supported degree (in-plane and thickness)
+constexpr int MAXG = 8;      // largest Gauss rule per direction
+constexpr int NHARM_MAX = 9; // harmonics of D(theta) for a general 6x6
+
+// A byte range of the device workspace.
+struct Region {
+  int64_t off = 0, bytes = 0;
+};
+
+// Device workspace layout.  The "constant" part (tables) is written once by
+// lam_plan_upload; the rest is scratch overwritten by every assembly.
+struct Layout {
+  // in-plane basis, per direction: tab[e][g][a] = (N, dN/dxi), w[e][g] = Gauss weight * half span
+  Region tab1, w1, tab2, w2;
+  // first function index of every in-plane element (knot span - degree)
+  Region e1first, e2first;
+  // per 1D overlap pair (i,j) of each direction: first shared element and count
+  Region pe1, pe2;
+  // in-plane pattern: srow[ns+1]; per in-plane nonzero k: row is, column js, 1D pair indices
+  Region srow, krow, kcol, kp1, kp2;
+  // thickness cells (ply x knot span): first function, ply, basis table, weights
+  Region zfirst, zply, ztab, zw;
+  // thickness pattern: zrow[nt+1], zcol[nnzz], zkrow[nnzz]; cells shared by each pair
+  Region zrow, zcol, zkrow, zcptr, zcell;
+  // sets active on each thickness row: zaptr[nt+1], zaset[]
+  Region zaptr, zaset;
+  // sets: material and (bucket) representative ply or (harmonic) harmonic index
+  Region set_mat, set_aux, ply_mat, ply_set;
+  // Kronecker scatter tiles: first in-plane nonzero of each tile
+  Region tiles;
+  int64_t const_bytes = 0;  // end of the constant part
+  // scratch
+  Region D, Ec, P, Qc, M;
+  int64_t total = 0;
+};
+
+}  // namespace lam
+
+struct lam_plan {
+  // sizes
+  int p1 = 0, p2 = 0, q = 0;
+  int n1 = 0, n2 = 0, nt = 0, ns = 0;
+  int ne1 = 0, ne2 = 0, nzc = 0;  // in-plane elements per direction, thickness cells
+  int ng1 = 0, ng2 = 0, ngz = 0;
+  int n_ply = 0, n_mat = 0, n_sets = 0, set_mode = 0, n_harm = 0, maxact = 0;
+  int64_t nnz1 = 0, nnz2 = 0, nnzz = 0, nnz = 0, nrows = 0;
+  int n_tiles = 0, tile_k = 0;
+  double jit[9] = {0};  // DF^{-T}, row-major
+  double detj = 0.0;    // |det DF|
+
+  lam::Layout L;
+  std::vector<uint8_t> image;  // host image of the constant part of the workspace
+};

@@ -1,0 +1,505 @@
+// kernels.hip -- gfx950 kernels of the fast 2D x 1D assembly and the device
+// entry points of the C ABI.
+//
+// Path of lam_assemble (all kernels on the caller's stream, FP64):
+//   k_rotate   per set: rotated 6x6 D_s (bucket) or its angular harmonic
+//              (harmonic mode), and the 81 coefficients
+//              E_s[k][l][r][t] = [B(e_k)^T D_s B(e_l)]_{rt}   (eq. B_1, eq. D)
+//   k_p2d      per in-plane nonzero: 2D Gauss quadrature of the geometric
+//              moments of grad V and W, contracted with every set's E_s:
+//              P_{s,ab}^{is js}                                     (eq. P)
+//   k_q1d      per thickness nonzero and active set: the 1D integrals Q_l
+//              summed over the set's plies with their weights      (eq. Q)
+//   k_kron     every nonzero of K written once, in CSR order:
+//              sum_sets sum_ab Qbar ⊗ P                          (eq. Km_2)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "internal.h"
+
+namespace {
+
+using lam::Region;
+
+struct Dev {
+  // sizes
+  int p1, p2, q, n1, n2, nt, ns, ng1, ng2, ngz;
+  int n_ply, n_mat, n_sets, set_mode, n_harm, maxact, n_tiles, tile_k;
+  int64_t nnz2, nnzz, nnz, nrows;
+  double jit[9], detj;
+  // constant tables
+  const double *tab1, *w1, *tab2, *w2;
+  const int *e1first, *e2first;
+  const int2 *pe1, *pe2;
+  const int *srow, *krow, *kcol, *kp1, *kp2;
+  const int *zfirst, *zply;
+  const double *ztab, *zw;
+  const int *zrow, *zcol, *zkrow, *zcptr, *zcell, *zaptr, *zaset;
+  const int *set_mat, *set_aux, *ply_mat, *ply_set, *tiles;
+  // scratch
+  double *D, *Ec, *P, *Qc, *M;
+};
+
+template <class T>
+T *at(void *ws, const Region &r) {
+  return reinterpret_cast<T *>(static_cast<char *>(ws) + r.off);
+}
+
+Dev make_dev(const lam_plan *p, void *ws) {
+  Dev d;
+  d.p1 = p->p1; d.p2 = p->p2; d.q = p->q;
+  d.n1 = p->n1; d.n2 = p->n2; d.nt = p->nt; d.ns = p->ns;
+  d.ng1 = p->ng1; d.ng2 = p->ng2; d.ngz = p->ngz;
+  d.n_ply = p->n_ply; d.n_mat = p->n_mat; d.n_sets = p->n_sets; d.set_mode = p->set_mode;
+  d.n_harm = p->n_harm; d.maxact = p->maxact; d.n_tiles = p->n_tiles; d.tile_k = p->tile_k;
+  d.nnz2 = p->nnz2; d.nnzz = p->nnzz; d.nnz = p->nnz; d.nrows = p->nrows;
+  for (int a = 0; a < 9; ++a) d.jit[a] = p->jit[a];
+  d.detj = p->detj;
+  const lam::Layout &L = p->L;
+  d.tab1 = at<double>(ws, L.tab1); d.w1 = at<double>(ws, L.w1);
+  d.tab2 = at<double>(ws, L.tab2); d.w2 = at<double>(ws, L.w2);
+  d.e1first = at<int>(ws, L.e1first); d.e2first = at<int>(ws, L.e2first);
+  d.pe1 = at<int2>(ws, L.pe1); d.pe2 = at<int2>(ws, L.pe2);
+  d.srow = at<int>(ws, L.srow); d.krow = at<int>(ws, L.krow); d.kcol = at<int>(ws, L.kcol);
+  d.kp1 = at<int>(ws, L.kp1); d.kp2 = at<int>(ws, L.kp2);
+  d.zfirst = at<int>(ws, L.zfirst); d.zply = at<int>(ws, L.zply);
+  d.ztab = at<double>(ws, L.ztab); d.zw = at<double>(ws, L.zw);
+  d.zrow = at<int>(ws, L.zrow); d.zcol = at<int>(ws, L.zcol); d.zkrow = at<int>(ws, L.zkrow);
+  d.zcptr = at<int>(ws, L.zcptr); d.zcell = at<int>(ws, L.zcell);
+  d.zaptr = at<int>(ws, L.zaptr); d.zaset = at<int>(ws, L.zaset);
+  d.set_mat = at<int>(ws, L.set_mat); d.set_aux = at<int>(ws, L.set_aux);
+  d.ply_mat = at<int>(ws, L.ply_mat); d.ply_set = at<int>(ws, L.ply_set);
+  d.tiles = at<int>(ws, L.tiles);
+  d.D = at<double>(ws, L.D); d.Ec = at<double>(ws, L.Ec); d.P = at<double>(ws, L.P);
+  d.Qc = at<double>(ws, L.Qc); d.M = at<double>(ws, L.M);
+  return d;
+}
+
+// ---------------------------------------------------------------------------
+// Material rotation (eq. D).  With R[i][k] = e_i . a_k (material axes
+// a_1 = (c,s,0), a_2 = (-s,c,0), a_3 = e_3), the Voigt stress transformation
+// is T[I][J] = R[i][k] R[j][l] + [k != l] R[i][l] R[j][k] for I = (ij),
+// J = (kl); engineering strains transform with T^T, so D = T C T^T.
+__constant__ int kVi[6] = {0, 1, 2, 0, 0, 1};
+__constant__ int kVj[6] = {0, 1, 2, 1, 2, 2};
+
+__device__ void voigt_rotation(double c, double s, double T[6][6]) {
+  const double R[3][3] = {{c, -s, 0.0}, {s, c, 0.0}, {0.0, 0.0, 1.0}};
+  for (int I = 0; I < 6; ++I)
+    for (int J = 0; J < 6; ++J) {
+      int i = kVi[I], j = kVj[I], k = kVi[J], l = kVj[J];
+      double t = R[i][k] * R[j][l];
+      if (k != l) t += R[i][l] * R[j][k];
+      T[I][J] = t;
+    }
+}
+
+__device__ void rotate_c(const double *C, double c, double s, double D[6][6]) {
+  double T[6][6], TC[6][6];
+  voigt_rotation(c, s, T);
+  for (int I = 0; I < 6; ++I)
+    for (int J = 0; J < 6; ++J) {
+      double a = 0.0;
+      for (int K = 0; K < 6; ++K) a += T[I][K] * C[K * 6 + J];
+      TC[I][J] = a;
+    }
+  for (int I = 0; I < 6; ++I)
+    for (int J = 0; J < 6; ++J) {
+      double a = 0.0;
+      for (int K = 0; K < 6; ++K) a += TC[I][K] * T[J][K];
+      D[I][J] = a;
+    }
+}
+
+// Harmonic h of a set: order and kind (0 constant, 1 cosine, 2 sine).
+__device__ inline void harmonic(int n_harm, int h, int &order, int &kind) {
+  if (h == 0) { order = 0; kind = 0; return; }
+  if (n_harm == 5) { order = 2 * ((h + 1) / 2); kind = (h & 1) ? 1 : 2; return; }
+  order = (h + 1) / 2;
+  kind = (h & 1) ? 1 : 2;
+}
+
+__device__ inline double harmonic_weight(int n_harm, int h, double theta) {
+  int order, kind;
+  harmonic(n_harm, h, order, kind);
+  if (kind == 0) return 1.0;
+  return kind == 1 ? cos(order * theta) : sin(order * theta);
+}
+
+// Voigt strain of the displacement e_r * phi for a unit gradient e_k:
+// column r of B(e_k) (eq. B_1 with the gamma_23 entry of the u_3 column
+// taking the 2-derivative).
+__device__ inline double bunit(int k, int I, int r) {
+  // B(g)[I][r]: rows 11,22,33,12,13,23
+  switch (I) {
+    case 0: return (r == 0 && k == 0) ? 1.0 : 0.0;
+    case 1: return (r == 1 && k == 1) ? 1.0 : 0.0;
+    case 2: return (r == 2 && k == 2) ? 1.0 : 0.0;
+    case 3: return ((r == 0 && k == 1) || (r == 1 && k == 0)) ? 1.0 : 0.0;
+    case 4: return ((r == 0 && k == 2) || (r == 2 && k == 0)) ? 1.0 : 0.0;
+    default: return ((r == 1 && k == 2) || (r == 2 && k == 1)) ? 1.0 : 0.0;
+  }
+}
+
+// One thread per set.  Harmonic sets: the Fourier coefficient of D(phi)
+// sampled at NH equispaced angles (exact for trigonometric polynomials of
+// degree <= 4 once NH >= 9).
+constexpr int NH = 12;
+
+__global__ void k_rotate(Dev d, const double *__restrict__ C, const double *__restrict__ theta) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= d.n_sets) return;
+  const double *Cm = C + 36 * d.set_mat[s];
+  double D[6][6];
+  if (d.set_mode == LAM_SETS_BUCKET) {
+    double th = theta[d.set_aux[s]];
+    rotate_c(Cm, cos(th), sin(th), D);
+  } else {
+    int order, kind;
+    harmonic(d.n_harm, d.set_aux[s], order, kind);
+    for (int I = 0; I < 6; ++I)
+      for (int J = 0; J < 6; ++J) D[I][J] = 0.0;
+    for (int j = 0; j < NH; ++j) {
+      double phi = 2.0 * M_PI * j / NH;
+      double wgt = kind == 0 ? 1.0 / NH : (kind == 1 ? 2.0 * cos(order * phi) : 2.0 * sin(order * phi)) / NH;
+      double Dj[6][6];
+      rotate_c(Cm, cos(phi), sin(phi), Dj);
+      for (int I = 0; I < 6; ++I)
+        for (int J = 0; J < 6; ++J) D[I][J] += wgt * Dj[I][J];
+    }
+  }
+  for (int I = 0; I < 6; ++I)
+    for (int J = 0; J < 6; ++J) d.D[36 * s + 6 * I + J] = D[I][J];
+  // E[k][l][r][t] = sum_IJ B(e_k)[I][r] D[I][J] B(e_l)[J][t]
+  for (int k = 0; k < 3; ++k)
+    for (int l = 0; l < 3; ++l)
+      for (int r = 0; r < 3; ++r)
+        for (int t = 0; t < 3; ++t) {
+          double a = 0.0;
+          for (int I = 0; I < 6; ++I) {
+            double bi = bunit(k, I, r);
+            if (bi == 0.0) continue;
+            for (int J = 0; J < 6; ++J) a += bi * D[I][J] * bunit(l, J, t);
+          }
+          d.Ec[81 * s + ((k * 3 + l) * 3 + r) * 3 + t] = a;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// 2D operators (eq. P).  For in-plane pair k = (is, js), the 2D Gauss sum
+// over the elements shared by both supports of the parametric moments
+//   m11[a][b] = sum w dS^i/dxi_a dS^j/dxi_b,  m12[a] = sum w dS^i/dxi_a S^j,
+//   m21[b]    = sum w S^i dS^j/dxi_b,         m22    = sum w S^i S^j,
+// pushed through DF^{-T} (grad V = DF^{-T}(dS1,dS2,0), W = DF^{-T}(0,0,S))
+// into M_ab[k][l] = int (G_a^i)_k (G_b^j)_l |DF|.  Because each set's
+// material is constant over the plane, P_{s,ab}[r][t] = sum_kl M_ab[k][l] E_s[k][l][r][t].
+__global__ void __launch_bounds__(256) k_p2d(Dev d) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= d.nnz2) return;
+  const int is = d.krow[k], js = d.kcol[k];
+  const int i1 = is % d.n1, i2 = is / d.n1, j1 = js % d.n1, j2 = js / d.n1;
+  const int2 ra = d.pe1[d.kp1[k]], rb = d.pe2[d.kp2[k]];
+  const int P1 = d.p1 + 1, P2 = d.p2 + 1;
+  double m11[2][2] = {{0, 0}, {0, 0}}, m12[2] = {0, 0}, m21[2] = {0, 0}, m22 = 0.0;
+  for (int e2 = rb.x; e2 < rb.x + rb.y; ++e2) {
+    const int f2 = d.e2first[e2];
+    const int ai2 = i2 - f2, aj2 = j2 - f2;
+    for (int e1 = ra.x; e1 < ra.x + ra.y; ++e1) {
+      const int f1 = d.e1first[e1];
+      const int ai1 = i1 - f1, aj1 = j1 - f1;
+      for (int g2 = 0; g2 < d.ng2; ++g2) {
+        const double *t2 = d.tab2 + ((int64_t)e2 * d.ng2 + g2) * P2 * 2;
+        const double Ni2 = t2[2 * ai2], dNi2 = t2[2 * ai2 + 1];
+        const double Nj2 = t2[2 * aj2], dNj2 = t2[2 * aj2 + 1];
+        const double wg2 = d.w2[(int64_t)e2 * d.ng2 + g2];
+        for (int g1 = 0; g1 < d.ng1; ++g1) {
+          const double *t1 = d.tab1 + ((int64_t)e1 * d.ng1 + g1) * P1 * 2;
+          const double Ni1 = t1[2 * ai1], dNi1 = t1[2 * ai1 + 1];
+          const double Nj1 = t1[2 * aj1], dNj1 = t1[2 * aj1 + 1];
+          const double w = wg2 * d.w1[(int64_t)e1 * d.ng1 + g1];
+          const double gi[2] = {dNi1 * Ni2, Ni1 * dNi2}, gj[2] = {dNj1 * Nj2, Nj1 * dNj2};
+          const double Si = Ni1 * Ni2, Sj = Nj1 * Nj2;
+          const double wSi = w * Si, wSj = w * Sj;
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            const double wgi = w * gi[a];
+            m11[a][0] += wgi * gj[0];
+            m11[a][1] += wgi * gj[1];
+            m12[a] += wgi * Sj;
+            m21[a] += wSi * gj[a];
+          }
+          m22 += wSi * Sj;
+        }
+      }
+    }
+  }
+  // M_ab[k][l], ab = 11, 12, 21, 22
+  double M[4][3][3];
+  const double *J = d.jit;
+#pragma unroll
+  for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+    for (int ll = 0; ll < 3; ++ll) {
+      double v11 = 0.0, v12 = 0.0, v21 = 0.0;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        v12 += J[kk * 3 + a] * m12[a];
+        v21 += J[ll * 3 + a] * m21[a];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) v11 += J[kk * 3 + a] * J[ll * 3 + b] * m11[a][b];
+      }
+      M[0][kk][ll] = d.detj * v11;
+      M[1][kk][ll] = d.detj * v12 * J[ll * 3 + 2];
+      M[2][kk][ll] = d.detj * J[kk * 3 + 2] * v21;
+      M[3][kk][ll] = d.detj * J[kk * 3 + 2] * J[ll * 3 + 2] * m22;
+    }
+  double *Mo = d.M + 36 * k;
+#pragma unroll
+  for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+    for (int e = 0; e < 9; ++e) Mo[ab * 9 + e] = M[ab][e / 3][e % 3];
+  for (int s = 0; s < d.n_sets; ++s) {
+    const double *E = d.Ec + 81 * s;
+    double *Po = d.P + 36 * ((int64_t)s * d.nnz2 + k);
+#pragma unroll
+    for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+      for (int rt = 0; rt < 9; ++rt) {
+        double a = 0.0;
+#pragma unroll
+        for (int kl = 0; kl < 9; ++kl) a += M[ab][kl / 3][kl % 3] * E[kl * 9 + rt];
+        Po[ab * 9 + rt] = a;
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 1D operators (eq. Q) folded into the sets: for thickness pair zk = (it, jt)
+// and the j-th set active on row it,
+//   Qc[zk][j][ab] = sum_{cells c shared by it, jt} w_{s,ply(c)} sum_g w_g tau_a^{it} tau_b^{jt}
+// with tau_1 = T, tau_2 = dT/dxi3, a on the test function it, and
+// w_{s,l} = [set of l == s] (bucket) or [mat(l) == mat(s)] * harmonic_s(theta_l).
+__global__ void k_q1d(Dev d, const double *__restrict__ theta) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.nnzz * d.maxact) return;
+  const int zk = (int)(idx / d.maxact), j = (int)(idx % d.maxact);
+  const int it = d.zkrow[zk], jt = d.zcol[zk];
+  const int a0 = d.zaptr[it], na = d.zaptr[it + 1] - a0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (j < na) {
+    const int s = d.zaset[a0 + j];
+    const int Q1 = d.q + 1;
+    for (int ci = d.zcptr[zk]; ci < d.zcptr[zk + 1]; ++ci) {
+      const int c = d.zcell[ci], l = d.zply[c];
+      double wgt;
+      if (d.set_mode == LAM_SETS_BUCKET) {
+        wgt = d.ply_set[l] == s ? 1.0 : 0.0;
+      } else {
+        wgt = d.ply_mat[l] == d.set_mat[s] ? harmonic_weight(d.n_harm, d.set_aux[s], theta[l]) : 0.0;
+      }
+      if (wgt == 0.0) continue;
+      const int ai = it - d.zfirst[c], aj = jt - d.zfirst[c];
+      double q11 = 0.0, q12 = 0.0, q21 = 0.0, q22 = 0.0;
+      for (int g = 0; g < d.ngz; ++g) {
+        const double *t = d.ztab + ((int64_t)c * d.ngz + g) * Q1 * 2;
+        const double Ti = t[2 * ai], dTi = t[2 * ai + 1], Tj = t[2 * aj], dTj = t[2 * aj + 1];
+        const double w = d.zw[(int64_t)c * d.ngz + g];
+        q11 += w * Ti * Tj;
+        q12 += w * Ti * dTj;
+        q21 += w * dTi * Tj;
+        q22 += w * dTi * dTj;
+      }
+      acc[0] += wgt * q11;
+      acc[1] += wgt * q12;
+      acc[2] += wgt * q21;
+      acc[3] += wgt * q22;
+    }
+  }
+  double *o = d.Qc + 4 * idx;
+  o[0] = acc[0];
+  o[1] = acc[1];
+  o[2] = acc[2];
+  o[3] = acc[3];
+}
+
+// ---------------------------------------------------------------------------
+// CSR addressing.  Row (it, is, r) starts at
+//   9*nnz2*zrow[it] + 3*Lz(it)*(3*srow[is] + r*Ls(is))
+// and its entry for thickness column a (0..Lz-1), in-plane column b
+// (0..Ls-1) and component t sits at + a*3*Ls + 3*b + t: columns ascend in
+// (jt, js, t) because both 1D overlap lists are contiguous and ascending.
+
+// Kronecker scatter.  Block = (tile of in-plane nonzeros, chunk of thickness
+// rows); thread = (in-plane nonzero k, column component t).  For each
+// thickness row it of the chunk the thread loads P of the row's active sets
+// for its (k, t) and writes the 3 (r) x Lz (a) values
+//   vals = sum_j sum_ab Qc[zk][j][ab] * P[set_j][k][ab][r][t].
+constexpr int KRON_THREADS = 256;
+constexpr int KRON_AB = 4;  // thickness columns per register block
+
+__global__ void __launch_bounds__(KRON_THREADS) k_kron(Dev d, double *__restrict__ vals, int zchunk) {
+  const int tile = blockIdx.x % d.n_tiles;
+  const int zc = blockIdx.x / d.n_tiles;
+  const int k0 = d.tiles[tile], k1 = d.tiles[tile + 1];
+  const int kk = threadIdx.x / 3, t = threadIdx.x % 3;
+  const int k = k0 + kk;
+  if (k >= k1) return;
+  const int is = d.krow[k];
+  const int sr = d.srow[is], Ls = d.srow[is + 1] - sr, b = k - sr;
+  const int it0 = zc * zchunk, it1 = min(d.nt, it0 + zchunk);
+  for (int it = it0; it < it1; ++it) {
+    const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
+    const int a0 = d.zaptr[it], na = d.zaptr[it + 1] - a0;
+    const int64_t base = 9 * d.nnz2 * (int64_t)zb + 3 * (int64_t)Lz * 3 * sr + 3 * b + t;
+    for (int ab0 = 0; ab0 < Lz; ab0 += KRON_AB) {
+      double acc[KRON_AB][3];
+#pragma unroll
+      for (int x = 0; x < KRON_AB; ++x) acc[x][0] = acc[x][1] = acc[x][2] = 0.0;
+      for (int j = 0; j < na; ++j) {
+        const int s = d.zaset[a0 + j];
+        const double *Pp = d.P + 36 * ((int64_t)s * d.nnz2 + k) + t;
+        double pr[4][3];
+#pragma unroll
+        for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+          for (int r = 0; r < 3; ++r) pr[ab][r] = Pp[ab * 9 + 3 * r];
+#pragma unroll
+        for (int x = 0; x < KRON_AB; ++x) {
+          if (ab0 + x < Lz) {
+            const double *qq = d.Qc + 4 * ((int64_t)(zb + ab0 + x) * d.maxact + j);
+            const double q0 = qq[0], q1 = qq[1], q2 = qq[2], q3 = qq[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) acc[x][r] += q0 * pr[0][r] + q1 * pr[1][r] + q2 * pr[2][r] + q3 * pr[3][r];
+          }
+        }
+      }
+#pragma unroll
+      for (int x = 0; x < KRON_AB; ++x) {
+        if (ab0 + x < Lz) {
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+            vals[base + 3 * (int64_t)Lz * r * Ls + (int64_t)(ab0 + x) * 3 * Ls] = acc[x][r];
+        }
+      }
+    }
+  }
+}
+
+__global__ void k_rowptr(Dev d, int64_t *__restrict__ rowptr) {
+  int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row > d.nrows) return;
+  if (row == d.nrows) {
+    rowptr[row] = d.nnz;
+    return;
+  }
+  const int64_t i = row / 3;
+  const int r = (int)(row % 3);
+  const int it = (int)(i / d.ns), is = (int)(i % d.ns);
+  const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
+  const int sr = d.srow[is], Ls = d.srow[is + 1] - sr;
+  rowptr[row] = 9 * d.nnz2 * (int64_t)zb + 3 * (int64_t)Lz * (3 * (int64_t)sr + (int64_t)r * Ls);
+}
+
+__global__ void __launch_bounds__(KRON_THREADS) k_colind(Dev d, int32_t *__restrict__ colind, int zchunk) {
+  const int tile = blockIdx.x % d.n_tiles;
+  const int zc = blockIdx.x / d.n_tiles;
+  const int k0 = d.tiles[tile], k1 = d.tiles[tile + 1];
+  const int kk = threadIdx.x / 3, t = threadIdx.x % 3;
+  const int k = k0 + kk;
+  if (k >= k1) return;
+  const int is = d.krow[k], js = d.kcol[k];
+  const int sr = d.srow[is], Ls = d.srow[is + 1] - sr, b = k - sr;
+  const int it0 = zc * zchunk, it1 = min(d.nt, it0 + zchunk);
+  for (int it = it0; it < it1; ++it) {
+    const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
+    const int64_t base = 9 * d.nnz2 * (int64_t)zb + 3 * (int64_t)Lz * 3 * sr + 3 * b + t;
+    for (int a = 0; a < Lz; ++a) {
+      const int jt = d.zcol[zb + a];
+      const int32_t col = 3 * (jt * d.ns + js) + t;
+      for (int r = 0; r < 3; ++r) colind[base + 3 * (int64_t)Lz * r * Ls + (int64_t)a * 3 * Ls] = col;
+    }
+  }
+}
+
+lam_status hip_status() {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? LAM_OK : LAM_EHIP;
+}
+
+int kron_zchunk(const lam_plan *p, int *nblocks) {
+  // enough blocks to fill 256 CUs several times over; each block keeps its
+  // tile of P warm in cache across its chunk of thickness rows
+  int64_t want = 4096;
+  int nz = (int)std::max<int64_t>(1, std::min<int64_t>(p->nt, (want + p->n_tiles - 1) / p->n_tiles));
+  int zchunk = (p->nt + nz - 1) / nz;
+  nz = (p->nt + zchunk - 1) / zchunk;
+  *nblocks = p->n_tiles * nz;
+  return zchunk;
+}
+
+lam_status check_ws(const lam_plan *p, const void *ws, int64_t ws_bytes) {
+  if (!p || !ws) return LAM_EINVAL;
+  if (ws_bytes < p->L.total) return LAM_ESIZE;
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return LAM_EINVAL;
+  return LAM_OK;
+}
+
+}  // namespace
+
+extern "C" LAM_API lam_status lam_plan_upload(const lam_plan *p, void *ws, int64_t ws_bytes, void *stream) {
+  lam_status st = check_ws(p, ws, ws_bytes);
+  if (st != LAM_OK) return st;
+  hipError_t e = hipMemcpyAsync(ws, p->image.data(), p->L.const_bytes, hipMemcpyHostToDevice,
+                                static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? LAM_OK : LAM_EHIP;
+}
+
+extern "C" LAM_API lam_status lam_pattern(const lam_plan *p, const void *ws, int64_t ws_bytes, int64_t *rowptr,
+                                          int32_t *colind, void *stream) {
+  lam_status st = check_ws(p, ws, ws_bytes);
+  if (st != LAM_OK) return st;
+  if (!rowptr || !colind) return LAM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Dev d = make_dev(p, const_cast<void *>(ws));
+  int64_t nb = (p->nrows + 1 + 255) / 256;
+  hipLaunchKernelGGL(k_rowptr, dim3((unsigned)nb), dim3(256), 0, s, d, rowptr);
+  int nblocks;
+  int zchunk = kron_zchunk(p, &nblocks);
+  hipLaunchKernelGGL(k_colind, dim3(nblocks), dim3(KRON_THREADS), 0, s, d, colind, zchunk);
+  return hip_status();
+}
+
+extern "C" LAM_API lam_status lam_assemble(const lam_plan *p, void *ws, int64_t ws_bytes, const double *C,
+                                           const double *theta, double *vals, int64_t nnz, void *stream) {
+  lam_status st = check_ws(p, ws, ws_bytes);
+  if (st != LAM_OK) return st;
+  if (!C || !theta || !vals) return LAM_EINVAL;
+  if (nnz != p->nnz) return LAM_ESIZE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Dev d = make_dev(p, ws);
+  hipLaunchKernelGGL(k_rotate, dim3((p->n_sets + 63) / 64), dim3(64), 0, s, d, C, theta);
+  hipLaunchKernelGGL(k_p2d, dim3((unsigned)((p->nnz2 + 255) / 256)), dim3(256), 0, s, d);
+  int64_t nq = p->nnzz * p->maxact;
+  hipLaunchKernelGGL(k_q1d, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, d, theta);
+  int nblocks;
+  int zchunk = kron_zchunk(p, &nblocks);
+  hipLaunchKernelGGL(k_kron, dim3(nblocks), dim3(KRON_THREADS), 0, s, d, vals, zchunk);
+  return hip_status();
+}
+
+extern "C" LAM_API lam_status lam_assemble_standard(const lam_plan *p, void *ws, int64_t ws_bytes, const double *C,
+                                                    const double *theta, double *vals, int64_t nnz, void *stream) {
+  (void)p; (void)ws; (void)ws_bytes; (void)C; (void)theta; (void)vals; (void)nnz; (void)stream;
+  return LAM_EUNSUP;
+}
+
+extern "C" LAM_API lam_status lam_adjoint(const lam_plan *p, void *ws, int64_t ws_bytes, const double *C,
+                                          const double *theta, const double *grad_vals, int64_t nnz, double *grad_C,
+                                          double *grad_theta, void *stream) {
+  (void)p; (void)ws; (void)ws_bytes; (void)C; (void)theta; (void)grad_vals; (void)nnz; (void)grad_C;
+  (void)grad_theta; (void)stream;
+  return LAM_EUNSUP;
+}

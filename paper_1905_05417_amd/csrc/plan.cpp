@@ -1,0 +1,533 @@
+// plan.cpp -- host side of the C ABI: descriptor validation, knot spans,
+// basis tables at Gauss points, the in-plane / thickness / Kronecker CSR
+// structure, the grouping of plies into sets, and the workspace layout.
+//
+// Everything here depends only on the discretisation (knots, plies, Gauss
+// rules), never on the material values or angles, which arrive on the device
+// at assembly time.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+using lam::MAXG;
+using lam::MAXP;
+
+// Gauss-Legendre nodes/weights on [-1,1]: Newton's method on P_n from the
+// asymptotic first guess, derivative from P'_n = n (x P_n - P_{n-1}) / (x^2 - 1).
+void gauss_rule(int n, double *x, double *w) {
+  const double pi = 3.141592653589793238462643;
+  for (int k = 1; k <= n; ++k) {
+    double t = std::cos(pi * (4.0 * k - 1.0) / (4.0 * n + 2.0));
+    double pn = 0, pm = 0;
+    for (int it = 0; it < 64; ++it) {
+      pm = 1.0;
+      pn = t;
+      for (int j = 2; j <= n; ++j) {
+        double pj = ((2 * j - 1) * t * pn - (j - 1) * pm) / j;
+        pm = pn;
+        pn = pj;
+      }
+      if (n == 1) { pm = 1.0; pn = t; }
+      double dp = n * (t * pn - pm) / (t * t - 1.0);
+      double step = pn / dp;
+      t -= step;
+      if (std::fabs(step) <= 1e-17) break;
+    }
+    pm = 1.0;
+    pn = t;
+    for (int j = 2; j <= n; ++j) {
+      double pj = ((2 * j - 1) * t * pn - (j - 1) * pm) / j;
+      pm = pn;
+      pn = pj;
+    }
+    double dp = (n == 1) ? 1.0 : n * (t * pn - pm) / (t * t - 1.0);
+    // t runs from the largest root down; store ascending
+    x[n - k] = t;
+    w[n - k] = 2.0 / ((1.0 - t * t) * dp * dp);
+  }
+  if (n & 1) x[n / 2] = 0.0;
+}
+
+// Values and first derivatives of the p+1 B-splines nonzero on knot span s
+// (t[s] <= u < t[s+1]), by de Boor's left/right differences.
+void basis_and_derivative(int p, const double *t, int s, double u, double *val, double *der) {
+  double left[MAXP + 2], right[MAXP + 2];
+  double ndu[MAXP + 1][MAXP + 1];  // ndu[j][r]: basis of degree j (upper) and knot differences (lower)
+  ndu[0][0] = 1.0;
+  for (int j = 1; j <= p; ++j) {
+    left[j] = u - t[s + 1 - j];
+    right[j] = t[s + j] - u;
+    double saved = 0.0;
+    for (int r = 0; r < j; ++r) {
+      ndu[j][r] = right[r + 1] + left[j - r];
+      double tmp = ndu[j][r] != 0.0 ? ndu[r][j - 1] / ndu[j][r] : 0.0;
+      ndu[r][j] = saved + right[r + 1] * tmp;
+      saved = left[j - r] * tmp;
+    }
+    ndu[j][j] = saved;
+  }
+  for (int r = 0; r <= p; ++r) val[r] = ndu[r][p];
+  if (p == 0) {
+    der[0] = 0.0;
+    return;
+  }
+  // first derivative: p * (N_{r,p-1}/(t_{r+p}-t_r) - N_{r+1,p-1}/(t_{r+p+1}-t_{r+1}))
+  for (int r = 0; r <= p; ++r) {
+    double d = 0.0;
+    if (r >= 1) {
+      double den = ndu[p][r - 1];
+      if (den != 0.0) d += ndu[r - 1][p - 1] / den;
+    }
+    if (r <= p - 1) {
+      double den = ndu[p][r];
+      if (den != 0.0) d -= ndu[r][p - 1] / den;
+    }
+    der[r] = p * d;
+  }
+}
+
+struct Dir {
+  int p = 0, n = 0, ne = 0, ng = 0;
+  std::vector<double> knots;
+  std::vector<int> span;       // knot index of each nonzero span (element)
+  std::vector<double> tab;     // [e][g][a][2]
+  std::vector<double> w;       // [e][g]
+  std::vector<int> adj_first;  // first overlapping function of i (overlaps are contiguous)
+  std::vector<int> adj_cnt;
+  std::vector<int> adj_ptr;    // prefix over i
+  std::vector<int> pair_elo, pair_ecnt;  // per 1D pair (indexed by adj_ptr[i] + b)
+};
+
+lam_status check_open_knots(int p, int nk, const double *k) {
+  if (p < 1 || p > MAXP) return LAM_EUNSUP;
+  if (!k || nk < 2 * p + 2) return LAM_EKNOT;
+  for (int i = 0; i < nk; ++i)
+    if (!std::isfinite(k[i])) return LAM_EKNOT;
+  for (int i = 0; i + 1 < nk; ++i)
+    if (!(k[i + 1] >= k[i])) return LAM_EKNOT;
+  for (int i = 0; i <= p; ++i)
+    if (k[i] != 0.0 || k[nk - 1 - i] != 1.0) return LAM_EKNOT;
+  // a knot repeated more than p times would split the space (not open inside)
+  for (int i = p + 1; i + p + 1 < nk; ++i) {
+    int m = 1;
+    while (i + m < nk - p - 1 && k[i + m] == k[i]) ++m;
+    if (m > p) return LAM_EKNOT;
+  }
+  return LAM_OK;
+}
+
+void build_dir(Dir &d, int p, int nk, const double *k, int ng) {
+  d.p = p;
+  d.ng = ng;
+  d.knots.assign(k, k + nk);
+  d.n = nk - p - 1;
+  for (int s = p; s < d.n; ++s)
+    if (k[s + 1] > k[s]) d.span.push_back(s);
+  d.ne = (int)d.span.size();
+  double gx[MAXG], gw[MAXG];
+  gauss_rule(ng, gx, gw);
+  d.tab.assign((size_t)d.ne * ng * (p + 1) * 2, 0.0);
+  d.w.assign((size_t)d.ne * ng, 0.0);
+  for (int e = 0; e < d.ne; ++e) {
+    int s = d.span[e];
+    double a = k[s], b = k[s + 1], h = 0.5 * (b - a), c = 0.5 * (a + b);
+    for (int g = 0; g < ng; ++g) {
+      double val[MAXP + 1], der[MAXP + 1];
+      basis_and_derivative(p, k, s, c + h * gx[g], val, der);
+      for (int r = 0; r <= p; ++r) {
+        d.tab[(((size_t)e * ng + g) * (p + 1) + r) * 2 + 0] = val[r];
+        d.tab[(((size_t)e * ng + g) * (p + 1) + r) * 2 + 1] = der[r];
+      }
+      d.w[(size_t)e * ng + g] = gw[g] * h;
+    }
+  }
+  // overlaps: i and j overlap iff some element carries both (its functions are span-p..span)
+  d.adj_first.assign(d.n, 0);
+  d.adj_cnt.assign(d.n, 0);
+  for (int i = 0; i < d.n; ++i) {
+    int lo = 1 << 30, hi = -1;
+    for (int e = 0; e < d.ne; ++e) {
+      int f = d.span[e] - p;
+      if (i >= f && i <= f + p) {
+        lo = std::min(lo, f);
+        hi = std::max(hi, f + p);
+      }
+    }
+    d.adj_first[i] = lo;
+    d.adj_cnt[i] = hi - lo + 1;
+  }
+  d.adj_ptr.assign(d.n + 1, 0);
+  for (int i = 0; i < d.n; ++i) d.adj_ptr[i + 1] = d.adj_ptr[i] + d.adj_cnt[i];
+  d.pair_elo.assign(d.adj_ptr[d.n], 0);
+  d.pair_ecnt.assign(d.adj_ptr[d.n], 0);
+  for (int i = 0; i < d.n; ++i)
+    for (int b = 0; b < d.adj_cnt[i]; ++b) {
+      int j = d.adj_first[i] + b;
+      int lo = -1, cnt = 0;
+      for (int e = 0; e < d.ne; ++e) {
+        int f = d.span[e] - p;
+        if (i >= f && i <= f + p && j >= f && j <= f + p) {
+          if (lo < 0) lo = e;
+          ++cnt;
+        }
+      }
+      d.pair_elo[d.adj_ptr[i] + b] = lo;
+      d.pair_ecnt[d.adj_ptr[i] + b] = cnt;
+    }
+}
+
+int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+struct Builder {
+  lam::Layout &L;
+  int64_t cur = 0;
+  explicit Builder(lam::Layout &l) : L(l) {}
+  lam::Region take(int64_t bytes) {
+    lam::Region r;
+    r.off = cur;
+    r.bytes = bytes;
+    cur = align256(cur + std::max<int64_t>(bytes, 1));
+    return r;
+  }
+};
+
+template <class T>
+void put(std::vector<uint8_t> &img, const lam::Region &r, const std::vector<T> &v) {
+  if (!v.empty()) std::memcpy(img.data() + r.off, v.data(), v.size() * sizeof(T));
+}
+
+}  // namespace
+
+extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_plan **out) {
+  if (!d || !out) return LAM_EINVAL;
+  *out = nullptr;
+  lam_status st;
+  if ((st = check_open_knots(d->p1, d->nk1, d->k1)) != LAM_OK) return st;
+  if ((st = check_open_knots(d->p2, d->nk2, d->k2)) != LAM_OK) return st;
+  if ((st = check_open_knots(d->q, d->nk3, d->k3)) != LAM_OK) return st;
+  if (d->set_mode < LAM_SETS_BUCKET || d->set_mode > LAM_SETS_HARMONIC9) return LAM_EINVAL;
+  if (d->n_ply < 1 || d->n_ply > 4096 || !d->iface || !d->ply_mat) return LAM_EPLY;
+  if (d->n_mat < 1 || d->n_mat > 64) return LAM_EINVAL;
+  if (d->set_mode == LAM_SETS_BUCKET && !d->ply_theta) return LAM_EINVAL;
+  if (d->iface[0] != 0.0 || d->iface[d->n_ply] != 1.0) return LAM_EPLY;
+  for (int l = 0; l < d->n_ply; ++l) {
+    if (!std::isfinite(d->iface[l + 1]) || !(d->iface[l + 1] > d->iface[l])) return LAM_EPLY;
+    if (d->ply_mat[l] < 0 || d->ply_mat[l] >= d->n_mat) return LAM_EPLY;
+    if (d->set_mode == LAM_SETS_BUCKET && !std::isfinite(d->ply_theta[l])) return LAM_EMAT;
+  }
+  int ng1 = d->ng1 ? d->ng1 : d->p1 + 1, ng2 = d->ng2 ? d->ng2 : d->p2 + 1, ngz = d->ngz ? d->ngz : d->q + 1;
+  if (ng1 < 1 || ng1 > MAXG || ng2 < 1 || ng2 > MAXG || ngz < 1 || ngz > MAXG) return LAM_EUNSUP;
+  const double *J = d->jac;
+  for (int a = 0; a < 9; ++a)
+    if (!std::isfinite(J[a])) return LAM_EMAT;
+  double cof[9] = {J[4] * J[8] - J[5] * J[7], -(J[3] * J[8] - J[5] * J[6]), J[3] * J[7] - J[4] * J[6],
+                   -(J[1] * J[8] - J[2] * J[7]), J[0] * J[8] - J[2] * J[6], -(J[0] * J[7] - J[1] * J[6]),
+                   J[1] * J[5] - J[2] * J[4], -(J[0] * J[5] - J[2] * J[3]), J[0] * J[4] - J[1] * J[3]};
+  double det = J[0] * cof[0] + J[1] * cof[1] + J[2] * cof[2];
+  if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return LAM_EMAT;
+
+  lam_plan *P = new (std::nothrow) lam_plan();
+  if (!P) return LAM_EINVAL;
+  // DF^{-1} = cof^T / det, so DF^{-T} = cof / det
+  for (int a = 0; a < 9; ++a) P->jit[a] = cof[a] / det;
+  P->detj = std::fabs(det);
+  P->p1 = d->p1;
+  P->p2 = d->p2;
+  P->q = d->q;
+  P->ng1 = ng1;
+  P->ng2 = ng2;
+  P->ngz = ngz;
+  P->n_ply = d->n_ply;
+  P->n_mat = d->n_mat;
+  P->set_mode = d->set_mode;
+
+  Dir d1, d2, dz;
+  build_dir(d1, d->p1, d->nk1, d->k1, ng1);
+  build_dir(d2, d->p2, d->nk2, d->k2, ng2);
+  P->n1 = d1.n;
+  P->n2 = d2.n;
+  P->ne1 = d1.ne;
+  P->ne2 = d2.ne;
+  P->ns = d1.n * d2.n;
+
+  // ---- thickness: cells = (ply, nonzero knot span) intersections, bottom to top
+  Dir zs;
+  zs.p = d->q;
+  zs.knots.assign(d->k3, d->k3 + d->nk3);
+  zs.n = d->nk3 - d->q - 1;
+  for (int s = d->q; s < zs.n; ++s)
+    if (d->k3[s + 1] > d->k3[s]) zs.span.push_back(s);
+  P->nt = zs.n;
+  std::vector<int> zfirst, zply;
+  std::vector<double> ztab, zw;
+  double gx[MAXG], gw[MAXG];
+  gauss_rule(ngz, gx, gw);
+  for (int l = 0; l < d->n_ply; ++l)
+    for (int s : zs.span) {
+      double a = std::max(d->iface[l], d->k3[s]), b = std::min(d->iface[l + 1], d->k3[s + 1]);
+      if (!(b > a)) continue;
+      zfirst.push_back(s - d->q);
+      zply.push_back(l);
+      double h = 0.5 * (b - a), c = 0.5 * (a + b);
+      for (int g = 0; g < ngz; ++g) {
+        double val[MAXP + 1], der[MAXP + 1];
+        basis_and_derivative(d->q, d->k3, s, c + h * gx[g], val, der);
+        for (int r = 0; r <= d->q; ++r) {
+          ztab.push_back(val[r]);
+          ztab.push_back(der[r]);
+        }
+        zw.push_back(gw[g] * h);
+      }
+    }
+  P->nzc = (int)zfirst.size();
+  // thickness overlap (contiguous ranges) and the cells shared by each pair
+  std::vector<int> zrow(P->nt + 1, 0), zcol, zkrow, zcptr(1, 0), zcell;
+  for (int it = 0; it < P->nt; ++it) {
+    int lo = 1 << 30, hi = -1;
+    for (int s : zs.span) {
+      int f = s - d->q;
+      if (it >= f && it <= f + d->q) {
+        lo = std::min(lo, f);
+        hi = std::max(hi, f + d->q);
+      }
+    }
+    for (int jt = lo; jt <= hi; ++jt) {
+      zcol.push_back(jt);
+      zkrow.push_back(it);
+      for (int c = 0; c < P->nzc; ++c) {
+        int f = zfirst[c];
+        if (it >= f && it <= f + d->q && jt >= f && jt <= f + d->q) zcell.push_back(c);
+      }
+      zcptr.push_back((int)zcell.size());
+    }
+    zrow[it + 1] = (int)zcol.size();
+  }
+  P->nnzz = (int64_t)zcol.size();
+
+  // ---- in-plane pattern: row is = i1 + n1*i2, columns (j2, j1) ascending
+  std::vector<int> srow(P->ns + 1, 0);
+  for (int i2 = 0; i2 < d2.n; ++i2)
+    for (int i1 = 0; i1 < d1.n; ++i1) {
+      int is = i1 + d1.n * i2;
+      srow[is + 1] = d1.adj_cnt[i1] * d2.adj_cnt[i2];
+    }
+  for (int is = 0; is < P->ns; ++is) srow[is + 1] += srow[is];
+  P->nnz2 = srow[P->ns];
+  P->nnz1 = d1.adj_ptr[d1.n];
+  std::vector<int> krow(P->nnz2), kcol(P->nnz2), kp1(P->nnz2), kp2(P->nnz2);
+  for (int i2 = 0; i2 < d2.n; ++i2)
+    for (int i1 = 0; i1 < d1.n; ++i1) {
+      int is = i1 + d1.n * i2, k = srow[is];
+      for (int b2 = 0; b2 < d2.adj_cnt[i2]; ++b2)
+        for (int b1 = 0; b1 < d1.adj_cnt[i1]; ++b1, ++k) {
+          krow[k] = is;
+          kcol[k] = (d1.adj_first[i1] + b1) + d1.n * (d2.adj_first[i2] + b2);
+          kp1[k] = d1.adj_ptr[i1] + b1;
+          kp2[k] = d2.adj_ptr[i2] + b2;
+        }
+    }
+  P->nnz = 9 * P->nnz2 * P->nnzz;
+  P->nrows = 3 * (int64_t)P->ns * P->nt;
+  if ((int64_t)3 * P->ns * P->nt >= (int64_t(1) << 31) || P->nnz2 >= (int64_t(1) << 31) ||
+      P->nnz >= (int64_t(1) << 62)) {
+    delete P;
+    return LAM_EUNSUP;
+  }
+
+  // ---- sets
+  std::vector<int> set_mat, set_aux, ply_set(d->n_ply, -1);
+  if (d->set_mode == LAM_SETS_BUCKET) {
+    std::map<std::pair<int, uint64_t>, int> key;
+    for (int l = 0; l < d->n_ply; ++l) {
+      uint64_t bits;
+      double th = d->ply_theta[l] == 0.0 ? 0.0 : d->ply_theta[l];  // -0 == +0
+      std::memcpy(&bits, &th, 8);
+      auto k = std::make_pair((int)d->ply_mat[l], bits);
+      auto itk = key.find(k);
+      if (itk == key.end()) {
+        int s = (int)set_mat.size();
+        key[k] = s;
+        set_mat.push_back(d->ply_mat[l]);
+        set_aux.push_back(l);  // representative ply: its runtime angle defines the set
+        ply_set[l] = s;
+      } else {
+        ply_set[l] = itk->second;
+      }
+    }
+    P->n_harm = 0;
+  } else {
+    P->n_harm = d->set_mode == LAM_SETS_HARMONIC5 ? 5 : 9;
+    std::vector<int> used(d->n_mat, 0);
+    for (int l = 0; l < d->n_ply; ++l) used[d->ply_mat[l]] = 1;
+    std::vector<int> first_set(d->n_mat, -1);
+    for (int m = 0; m < d->n_mat; ++m) {
+      if (!used[m]) continue;
+      first_set[m] = (int)set_mat.size();
+      for (int h = 0; h < P->n_harm; ++h) {
+        set_mat.push_back(m);
+        set_aux.push_back(h);
+      }
+    }
+    for (int l = 0; l < d->n_ply; ++l) ply_set[l] = first_set[d->ply_mat[l]];  // first harmonic of its material
+  }
+  P->n_sets = (int)set_mat.size();
+  // sets active on each thickness row: those of plies with a cell in the row's support
+  std::vector<int> zaptr(P->nt + 1, 0), zaset;
+  int maxact = 0;
+  for (int it = 0; it < P->nt; ++it) {
+    std::vector<int> act;
+    for (int c = 0; c < P->nzc; ++c) {
+      if (it < zfirst[c] || it > zfirst[c] + d->q) continue;
+      int l = zply[c];
+      if (d->set_mode == LAM_SETS_BUCKET) {
+        act.push_back(ply_set[l]);
+      } else {
+        for (int h = 0; h < P->n_harm; ++h) act.push_back(ply_set[l] + h);
+      }
+    }
+    std::sort(act.begin(), act.end());
+    act.erase(std::unique(act.begin(), act.end()), act.end());
+    maxact = std::max(maxact, (int)act.size());
+    zaset.insert(zaset.end(), act.begin(), act.end());
+    zaptr[it + 1] = (int)zaset.size();
+  }
+  P->maxact = std::max(maxact, 1);
+
+  // ---- Kronecker scatter tiles: runs of in-plane nonzeros, one thread per (k, s)
+  P->tile_k = 85;
+  P->n_tiles = (int)((P->nnz2 + P->tile_k - 1) / P->tile_k);
+  std::vector<int> tiles(P->n_tiles + 1);
+  for (int t = 0; t <= P->n_tiles; ++t) tiles[t] = (int)std::min<int64_t>((int64_t)t * P->tile_k, P->nnz2);
+
+  std::vector<int> plymat(d->ply_mat, d->ply_mat + d->n_ply);
+
+  // ---- layout
+  lam::Layout &L = P->L;
+  Builder B(L);
+  L.tab1 = B.take(sizeof(double) * d1.tab.size());
+  L.w1 = B.take(sizeof(double) * d1.w.size());
+  L.tab2 = B.take(sizeof(double) * d2.tab.size());
+  L.w2 = B.take(sizeof(double) * d2.w.size());
+  L.e1first = B.take(sizeof(int) * d1.ne);
+  L.e2first = B.take(sizeof(int) * d2.ne);
+  L.pe1 = B.take(sizeof(int) * 2 * d1.pair_elo.size());
+  L.pe2 = B.take(sizeof(int) * 2 * d2.pair_elo.size());
+  L.srow = B.take(sizeof(int) * srow.size());
+  L.krow = B.take(sizeof(int) * krow.size());
+  L.kcol = B.take(sizeof(int) * kcol.size());
+  L.kp1 = B.take(sizeof(int) * kp1.size());
+  L.kp2 = B.take(sizeof(int) * kp2.size());
+  L.zfirst = B.take(sizeof(int) * zfirst.size());
+  L.zply = B.take(sizeof(int) * zply.size());
+  L.ztab = B.take(sizeof(double) * ztab.size());
+  L.zw = B.take(sizeof(double) * zw.size());
+  L.zrow = B.take(sizeof(int) * zrow.size());
+  L.zcol = B.take(sizeof(int) * zcol.size());
+  L.zkrow = B.take(sizeof(int) * zkrow.size());
+  L.zcptr = B.take(sizeof(int) * zcptr.size());
+  L.zcell = B.take(sizeof(int) * zcell.size());
+  L.zaptr = B.take(sizeof(int) * zaptr.size());
+  L.zaset = B.take(sizeof(int) * zaset.size());
+  L.set_mat = B.take(sizeof(int) * set_mat.size());
+  L.set_aux = B.take(sizeof(int) * set_aux.size());
+  L.ply_mat = B.take(sizeof(int) * plymat.size());
+  L.ply_set = B.take(sizeof(int) * ply_set.size());
+  L.tiles = B.take(sizeof(int) * tiles.size());
+  L.const_bytes = B.cur;
+  L.D = B.take(sizeof(double) * 36 * P->n_sets);
+  L.Ec = B.take(sizeof(double) * 81 * P->n_sets);
+  L.P = B.take(sizeof(double) * 36 * (int64_t)P->n_sets * P->nnz2);
+  L.Qc = B.take(sizeof(double) * 4 * (int64_t)P->maxact * P->nnzz);
+  L.M = B.take(sizeof(double) * 36 * P->nnz2);
+  L.total = B.cur;
+
+  P->image.assign(L.const_bytes, 0);
+  auto &img = P->image;
+  put(img, L.tab1, d1.tab);
+  put(img, L.w1, d1.w);
+  put(img, L.tab2, d2.tab);
+  put(img, L.w2, d2.w);
+  {
+    std::vector<int> f(d1.ne);
+    for (int e = 0; e < d1.ne; ++e) f[e] = d1.span[e] - d1.p;
+    put(img, L.e1first, f);
+    f.assign(d2.ne, 0);
+    for (int e = 0; e < d2.ne; ++e) f[e] = d2.span[e] - d2.p;
+    put(img, L.e2first, f);
+  }
+  {
+    std::vector<int> pe(2 * d1.pair_elo.size());
+    for (size_t i = 0; i < d1.pair_elo.size(); ++i) {
+      pe[2 * i] = d1.pair_elo[i];
+      pe[2 * i + 1] = d1.pair_ecnt[i];
+    }
+    put(img, L.pe1, pe);
+    pe.assign(2 * d2.pair_elo.size(), 0);
+    for (size_t i = 0; i < d2.pair_elo.size(); ++i) {
+      pe[2 * i] = d2.pair_elo[i];
+      pe[2 * i + 1] = d2.pair_ecnt[i];
+    }
+    put(img, L.pe2, pe);
+  }
+  put(img, L.srow, srow);
+  put(img, L.krow, krow);
+  put(img, L.kcol, kcol);
+  put(img, L.kp1, kp1);
+  put(img, L.kp2, kp2);
+  put(img, L.zfirst, zfirst);
+  put(img, L.zply, zply);
+  put(img, L.ztab, ztab);
+  put(img, L.zw, zw);
+  put(img, L.zrow, zrow);
+  put(img, L.zcol, zcol);
+  put(img, L.zkrow, zkrow);
+  put(img, L.zcptr, zcptr);
+  put(img, L.zcell, zcell);
+  put(img, L.zaptr, zaptr);
+  put(img, L.zaset, zaset);
+  put(img, L.set_mat, set_mat);
+  put(img, L.set_aux, set_aux);
+  put(img, L.ply_mat, plymat);
+  put(img, L.ply_set, ply_set);
+  put(img, L.tiles, tiles);
+  *out = P;
+  return LAM_OK;
+}
+
+extern "C" LAM_API void lam_plan_destroy(lam_plan *p) { delete p; }
+
+extern "C" LAM_API lam_status lam_plan_info(const lam_plan *p, int64_t *n_rows, int64_t *nnz, int64_t *ws_bytes,
+                                            int32_t *n_sets, int32_t *n_ply, int32_t *n_mat) {
+  if (!p) return LAM_EINVAL;
+  if (n_rows) *n_rows = p->nrows;
+  if (nnz) *nnz = p->nnz;
+  if (ws_bytes) *ws_bytes = p->L.total;
+  if (n_sets) *n_sets = p->n_sets;
+  if (n_ply) *n_ply = p->n_ply;
+  if (n_mat) *n_mat = p->n_mat;
+  return LAM_OK;
+}
+
+extern "C" LAM_API const char *lam_status_string(lam_status s) {
+  switch (s) {
+    case LAM_OK: return "ok";
+    case LAM_EINVAL: return "invalid argument";
+    case LAM_EKNOT: return "invalid knot vector or degree";
+    case LAM_EPLY: return "invalid ply stack";
+    case LAM_EMAT: return "invalid material, angle or map gradient";
+    case LAM_ESIZE: return "workspace or output size does not match the plan";
+    case LAM_EHIP: return "HIP runtime error";
+    case LAM_EUNSUP: return "outside the limits of this build";
+    default: return "unknown status";
+  }
+}
+
+extern "C" LAM_API const char *lam_version(void) { return "lamasm 0.1 (gfx950, FP64)"; }

@@ -1,0 +1,215 @@
+"""Python binding of liblamasm.so (argument marshalling only).
+
+Every step of the assembly runs in the library's HIP kernels; torch supplies
+device memory and the current stream.  If the library is missing this module
+raises: there is no CPU fallback.
+
+    plan = Plan(laminate)                   # host plan + device workspace
+    rowptr, colind = plan.pattern()         # CSR structure (int64, int32)
+    vals = plan.assemble(C, theta)          # fast 2D x 1D assembly
+    vals = plan.assemble_standard(C, theta) # standard 3D assembly, same CSR
+    vals = assemble(plan, C, theta)         # differentiable in C and theta
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # loads the HIP runtime the library shares
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblamasm.so")
+
+LAM_SETS = {"bucket": 0, "harmonic5": 1, "harmonic9": 2}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [
+        ("p1", ctypes.c_int32), ("nk1", ctypes.c_int32), ("k1", _dp),
+        ("p2", ctypes.c_int32), ("nk2", ctypes.c_int32), ("k2", _dp),
+        ("q", ctypes.c_int32), ("nk3", ctypes.c_int32), ("k3", _dp),
+        ("jac", ctypes.c_double * 9),
+        ("n_ply", ctypes.c_int32),
+        ("iface", _dp),
+        ("ply_mat", _i32p),
+        ("n_mat", ctypes.c_int32),
+        ("ply_theta", _dp),
+        ("ng1", ctypes.c_int32), ("ng2", ctypes.c_int32), ("ngz", ctypes.c_int32),
+        ("set_mode", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+EXPORTED = ("lam_plan_create", "lam_plan_destroy", "lam_plan_info", "lam_plan_upload", "lam_pattern",
+            "lam_assemble", "lam_assemble_standard", "lam_adjoint", "lam_status_string", "lam_version")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("liblamasm.so is not built (run paper_1905_05417_amd/build.py); "
+                               "there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i64p = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)
+        L.lam_plan_create.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(vp)]
+        L.lam_plan_destroy.argtypes = [vp]
+        L.lam_plan_destroy.restype = None
+        L.lam_plan_info.argtypes = [vp, i64p, i64p, i64p, _i32p, _i32p, _i32p]
+        L.lam_plan_upload.argtypes = [vp, vp, i64, vp]
+        L.lam_pattern.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.lam_assemble.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
+        L.lam_assemble_standard.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
+        L.lam_adjoint.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
+        L.lam_status_string.argtypes = [ctypes.c_int32]
+        L.lam_status_string.restype = ctypes.c_char_p
+        L.lam_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+class LamError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (where, lib().lam_status_string(code).decode(), code))
+
+
+def _check(code, where):
+    if code != 0:
+        raise LamError(code, where)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def default_set_mode(lam) -> str:
+    """Bucket sets when plies share few (material, angle) pairs, harmonics otherwise."""
+    keys = {(int(m), float(t)) for m, t in zip(lam.ply_mat, lam.theta)}
+    n_mat = len(set(int(m) for m in lam.ply_mat))
+    return "bucket" if len(keys) <= 5 * n_mat else "harmonic9"
+
+
+class Plan:
+    """Host plan and device workspace for one laminate discretisation."""
+
+    def __init__(self, lam, set_mode: str | None = None, device="cuda"):
+        set_mode = set_mode or default_set_mode(lam)
+        self.lam = lam
+        self.set_mode = set_mode
+        self._keep = [np.ascontiguousarray(lam.k1, dtype=np.float64),
+                      np.ascontiguousarray(lam.k2, dtype=np.float64),
+                      np.ascontiguousarray(lam.k3, dtype=np.float64),
+                      np.ascontiguousarray(lam.iface, dtype=np.float64),
+                      np.ascontiguousarray(lam.ply_mat, dtype=np.int32),
+                      np.ascontiguousarray(lam.theta, dtype=np.float64)]
+        k1, k2, k3, iface, pm, th = self._keep
+        d = _Desc()
+        d.p1, d.nk1, d.k1 = int(lam.p1), len(k1), k1.ctypes.data_as(_dp)
+        d.p2, d.nk2, d.k2 = int(lam.p2), len(k2), k2.ctypes.data_as(_dp)
+        d.q, d.nk3, d.k3 = int(lam.q), len(k3), k3.ctypes.data_as(_dp)
+        J = np.asarray(lam.jac, dtype=np.float64).reshape(9)
+        for a in range(9):
+            d.jac[a] = float(J[a])
+        d.n_ply = len(th)
+        d.iface = iface.ctypes.data_as(_dp)
+        d.ply_mat = pm.ctypes.data_as(_i32p)
+        d.n_mat = int(np.asarray(lam.C).shape[0])
+        d.ply_theta = th.ctypes.data_as(_dp)
+        d.ng1, d.ng2, d.ngz = (int(g) for g in getattr(lam, "ng", (0, 0, 0)))
+        d.set_mode = LAM_SETS[set_mode]
+        self._desc = d
+        h = ctypes.c_void_p()
+        _check(lib().lam_plan_create(ctypes.byref(d), ctypes.byref(h)), "lam_plan_create")
+        self._h = h
+        nr, nz, wb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        ns, npl, nm = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().lam_plan_info(h, ctypes.byref(nr), ctypes.byref(nz), ctypes.byref(wb), ctypes.byref(ns),
+                                   ctypes.byref(npl), ctypes.byref(nm)), "lam_plan_info")
+        self.n_rows, self.nnz, self.ws_bytes = nr.value, nz.value, wb.value
+        self.n_sets, self.n_ply, self.n_mat = ns.value, npl.value, nm.value
+        self.device = torch.device(device)
+        self.ws = None
+        if self.device.type == "cuda":
+            self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+            _check(lib().lam_plan_upload(h, self.ws.data_ptr(), self.ws_bytes, _stream()), "lam_plan_upload")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.lam_plan_destroy(h)
+            self._h = None
+
+    def _ws(self):
+        if self.ws is None:
+            raise RuntimeError("plan has no device workspace")
+        return self.ws
+
+    def _inputs(self, C, theta):
+        C = torch.as_tensor(C, dtype=torch.float64, device=self.device).contiguous()
+        theta = torch.as_tensor(theta, dtype=torch.float64, device=self.device).contiguous()
+        if C.numel() != 36 * self.n_mat or theta.numel() != self.n_ply:
+            raise ValueError("C must hold n_mat*36 values and theta n_ply values")
+        return C, theta
+
+    def pattern(self):
+        ws = self._ws()
+        rowptr = torch.empty(self.n_rows + 1, dtype=torch.int64, device=self.device)
+        colind = torch.empty(self.nnz, dtype=torch.int32, device=self.device)
+        _check(lib().lam_pattern(self._h, ws.data_ptr(), self.ws_bytes, rowptr.data_ptr(), colind.data_ptr(),
+                                 _stream()), "lam_pattern")
+        return rowptr, colind
+
+    def assemble(self, C, theta, out=None):
+        ws = self._ws()
+        C, theta = self._inputs(C, theta)
+        vals = torch.empty(self.nnz, dtype=torch.float64, device=self.device) if out is None else out
+        _check(lib().lam_assemble(self._h, ws.data_ptr(), self.ws_bytes, C.data_ptr(), theta.data_ptr(),
+                                  vals.data_ptr(), vals.numel(), _stream()), "lam_assemble")
+        return vals
+
+    def assemble_standard(self, C, theta, out=None):
+        ws = self._ws()
+        C, theta = self._inputs(C, theta)
+        vals = torch.empty(self.nnz, dtype=torch.float64, device=self.device) if out is None else out
+        _check(lib().lam_assemble_standard(self._h, ws.data_ptr(), self.ws_bytes, C.data_ptr(), theta.data_ptr(),
+                                           vals.data_ptr(), vals.numel(), _stream()), "lam_assemble_standard")
+        return vals
+
+    def adjoint(self, C, theta, grad_vals):
+        ws = self._ws()
+        C, theta = self._inputs(C, theta)
+        G = grad_vals.to(dtype=torch.float64).contiguous()
+        gC = torch.empty(self.n_mat * 36, dtype=torch.float64, device=self.device)
+        gT = torch.empty(self.n_ply, dtype=torch.float64, device=self.device)
+        _check(lib().lam_adjoint(self._h, ws.data_ptr(), self.ws_bytes, C.data_ptr(), theta.data_ptr(),
+                                 G.data_ptr(), G.numel(), gC.data_ptr(), gT.data_ptr(), _stream()), "lam_adjoint")
+        return gC.view(self.n_mat, 6, 6), gT
+
+    def csr(self, vals, pattern=None):
+        rowptr, colind = self.pattern() if pattern is None else pattern
+        return torch.sparse_csr_tensor(rowptr, colind.to(torch.int64), vals, size=(self.n_rows, self.n_rows))
+
+
+class _Assemble(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, C, theta, plan):
+        ctx.plan = plan
+        ctx.save_for_backward(C, theta)
+        return plan.assemble(C.detach(), theta.detach())
+
+    @staticmethod
+    def backward(ctx, grad_vals):
+        C, theta = ctx.saved_tensors
+        gC, gT = ctx.plan.adjoint(C.detach(), theta.detach(), grad_vals)
+        return gC.view_as(C), gT.view_as(theta), None
+
+
+def assemble(plan: Plan, C: torch.Tensor, theta: torch.Tensor) -> torch.Tensor:
+    """CSR values of K(C, theta); differentiable in C (n_mat,6,6) and theta (n_ply,)."""
+    return _Assemble.apply(C, theta, plan)
