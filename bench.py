@@ -1,0 +1,217 @@
+#!/usr/bin/env python
+"""Benchmark of the fast 2D x 1D laminate stiffness assembly on one MI355X.
+
+One step = one lam_assemble call (material rotation, 2D operators P, 1D
+operators Q, Kronecker scatter into the CSR values) on the degree-2 IGA plate:
+64x64 in-plane elements, 32 plies [0/90]_16, degree 2 per ply (C0 at
+interfaces), thickness 0.02, 3x3x3 Gauss: 849,420 DOF, 242,809,488 nonzeros.
+Inputs (plan tables, C, theta) are resident in HBM before timing starts.
+
+Prints ONE JSON line.  `value` is assembled CSR nonzeros per second (FP64).
+`roofline` is for the dominant kernel (the Kronecker scatter), timed with HIP
+events recorded around its own launch on the assembly stream; its algorithmic
+traffic is the 8-byte write of every nonzero.  `cpu_baseline` times the CPU
+oracle (standard 3D Gauss assembly, layer by layer) on a slab of the same plate.
+`extra` carries the standard 3D GPU assembly on the same CSR and the other
+plate workloads when their entry points are built.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, spec
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector / matrix, spec
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-extra", action="store_true", help="only the headline workload")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (counter calibration)")
+    return ap.parse_args()
+
+
+def _kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_1905_05417_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(workload, kernel):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
+    were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != _kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def _time_steps(torch, fn, steps, warmup, L, which):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    L.profile_enable(True)
+    L.profile_read()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / steps
+    prof = L.profile_read()
+    L.profile_enable(False)
+    ms_k, n_k = prof[which]
+    return ms_step, (ms_k / n_k if n_k else None)
+
+
+def _sample_parity(oracle, lam, plan, vals, rowptr, n_rows=200, seed=3):
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(seed)
+    rows = np.unique(rng.choice(plan.n_rows, size=n_rows, replace=False))
+    ptr, col, ref = oracle.assemble_rows(lam, rows)
+    rp = rowptr.cpu().numpy()
+    idx = torch.tensor(np.concatenate([np.arange(rp[r], rp[r + 1]) for r in rows]), device="cuda")
+    g = vals[idx].cpu().numpy()
+    return float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+
+
+def _fast_workload(torch, np, L, O, lam, mode, steps, warmup):
+    """Fast assembly of another plate: nnz/s, scatter roofline, sampled parity."""
+    plan = L.Plan(lam, set_mode=mode)
+    rowptr, colind = plan.pattern()
+    C = torch.tensor(np.asarray(lam.C), device="cuda")
+    th = torch.tensor(np.asarray(lam.theta), device="cuda")
+    vals = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
+    ms_step, ms_k = _time_steps(torch, lambda: plan.assemble(C, th, out=vals), steps, warmup, L, "assemble")
+    res = {"nnz": plan.nnz, "sets": plan.n_sets, "set_mode": mode, "ms_per_step": ms_step,
+           "nnz_per_s": plan.nnz / (ms_step * 1e-3), "k_kron_ms": ms_k,
+           "k_kron_hbm_frac": 8.0 * plan.nnz / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "parity_sample_relF": _sample_parity(O, lam, plan, vals, rowptr, n_rows=100)}
+    del vals, rowptr, colind
+    torch.cuda.empty_cache()
+    return res
+
+
+def _cpu_baseline(oracle, W):
+    """Oracle on a slab of the headline plate: 16 x 64 in-plane elements, all
+    32 plies, same degrees and Gauss rules."""
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    lam = W.plate(2, 16, 2, [0, 90] * 16, [W.material(W.CARBON)], [0] * 32, ne2=64, name="slab")
+    lam.ng = (3, 3, 3)
+    pat = oracle.pattern(lam)
+    t0 = time.perf_counter()
+    oracle.assemble(lam, nthreads=threads, pattern_=pat)
+    dt = time.perf_counter() - t0
+    nnz = len(pat[1])
+    return {"value": nnz / dt, "unit": "nnz/s", "cores": threads, "kind": "oracle",
+            "sample": "standard 3D assembly of a 16x64-element slab of the same plate (all 32 plies, "
+                      "%d nnz) in %.2f s; full plate projected at %.0f s" % (nnz, dt, dt * 4.0)}
+
+
+def main():
+    args = _parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only (requested %d); multi-GPU sharding of the "
+              "assembly is described in DESIGN.md but not built" % max(args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1905_05417_amd import lamasm as L
+    from paper_1905_05417_amd import workloads as W
+
+    torch.cuda.init()
+    L.lib()
+
+    lam = W.config_p2_64x64_32ply()
+    t0 = time.perf_counter()
+    plan = L.Plan(lam, set_mode="bucket")
+    rowptr, colind = plan.pattern()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    C = torch.tensor(np.asarray(lam.C), device="cuda")
+    th = torch.tensor(np.asarray(lam.theta), device="cuda")
+    vals = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
+    ms_step, ms_kron = _time_steps(torch, lambda: plan.assemble(C, th, out=vals), args.steps, args.warmup, L,
+                                   "assemble")
+    value = plan.nnz / (ms_step * 1e-3)
+    alg_bytes = 8.0 * plan.nnz
+    achieved = alg_bytes / (ms_kron * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(lam.name, "k_kron"),
+                "kernel": "k_kron", "kernel_ms": round(ms_kron, 5), "bytes_per_launch": alg_bytes}
+
+    out = {
+        "metric": "assembled CSR nnz/s (FP64, rel err <=1e-12) fast 2Dx1D vs standard 3D; adjoint ms",
+        "value": value, "unit": "nnz/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": lam.name, "nnz": plan.nnz, "dof": plan.n_rows, "plies": lam.n_ply,
+                   "degree_inplane": lam.p1, "degree_thickness": lam.q, "elements_inplane": "64x64",
+                   "sets": plan.n_sets, "set_mode": plan.set_mode, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "setup_s": round(setup_s, 3),
+    }
+
+    from oracle import oracle as O
+    out["parity_sample_relF"] = _sample_parity(O, lam, plan, vals, rowptr)
+    if out["parity_sample_relF"] > 1e-12:
+        out["value_invalid"] = "sampled parity above 1e-12"
+
+    extra = {}
+    if not args.no_extra:
+        try:
+            ms_std, ms_std_k = _time_steps(torch, lambda: plan.assemble_standard(C, th, out=vals),
+                                           max(3, args.steps // 4), 1, L, "standard")
+            extra["standard_same_plate"] = {"nnz_per_s": plan.nnz / (ms_std * 1e-3), "ms_per_step": ms_std,
+                                            "speedup_fast_vs_standard": ms_std / ms_step}
+        except L.LamError as e:
+            extra["standard_same_plate"] = {"skipped": str(e)}
+    del vals, rowptr, colind
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        extra["p3_128x128_128ply"] = _fast_workload(torch, np, L, O, W.config_p3_128x128_128ply(), "bucket",
+                                                     max(5, args.steps // 2), args.warmup)
+    out["extra"] = extra
+
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = 8 * n
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = _cpu_baseline(O, W)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

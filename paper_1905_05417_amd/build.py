@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblamasm.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("plan.cpp", "kernels.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("plan.cpp", "profile.cpp", "kernels.hip")]
 HEADERS = [os.path.join(ROOT, "include", "lamasm.h"), os.path.join(HERE, "csrc", "internal.h")]
 
 HIPCC_FLAGS = [
@@ -33,8 +33,12 @@ def build(verbose: bool = False) -> str:
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
+    noise = "'-packed-fp32-ops' is not a recognized feature for this target (ignoring feature)"
+    msg = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if noise not in l)
+    if msg.strip() and verbose:
+        sys.stderr.write(msg + "\n")
     if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
+        sys.stderr.write(msg + "\n")
         raise RuntimeError("hipcc failed building liblamasm.so")
     os.replace(tmp, LIB)
     return LIB

@@ -37,13 +37,21 @@ struct Layout {
   Region zaptr, zaset;
   // sets: material and (bucket) representative ply or (harmonic) harmonic index
   Region set_mat, set_aux, ply_mat, ply_set;
-  // Kronecker scatter tiles: first in-plane nonzero of each tile
-  Region tiles;
+  // Kronecker scatter: tiles of whole in-plane rows (first in-plane nonzero
+  // of each tile), chunks of thickness rows (first row of each chunk), the
+  // sets each chunk keeps in LDS (chunk_sptr, chunk_set), and for every
+  // active set of a row its LDS slot in the row's chunk (zaslot, parallel to zaset)
+  Region tiles, chunk_ptr, chunk_sptr, chunk_set, zaslot;
   int64_t const_bytes = 0;  // end of the constant part
   // scratch
   Region D, Ec, P, Qc, M;
   int64_t total = 0;
 };
+
+// Kernel timing hooks (profile.cpp): a slot recorded around the dominant
+// kernel of entry point `which` (0 assemble, 1 standard, 2 adjoint).
+void *profile_begin(int which, void *stream);
+void profile_end(void *slot, void *stream);
 
 }  // namespace lam
 
@@ -55,7 +63,11 @@ struct lam_plan {
   int ng1 = 0, ng2 = 0, ngz = 0;
   int n_ply = 0, n_mat = 0, n_sets = 0, set_mode = 0, n_harm = 0, maxact = 0;
   int64_t nnz1 = 0, nnz2 = 0, nnzz = 0, nnz = 0, nrows = 0;
-  int n_tiles = 0, tile_k = 0;
+  int n_tiles = 0, tile_k = 0;      // tiles of whole rows, at most tile_k in-plane nonzeros each
+  int n_chunks = 0, chunk_sets = 0; // thickness-row chunks, at most chunk_sets sets in LDS each
+  int64_t kron_lds = 0;             // LDS bytes of the scatter kernel
+  int kron_lzmax = 0;               // longest thickness row (columns) of the pattern
+  int64_t kron_lds_q = 0, kron_lds_p = 0;  // LDS bytes of the Q and P parts (output buffer follows)
   double jit[9] = {0};  // DF^{-T}, row-major
   double detj = 0.0;    // |det DF|
 

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 
 #include "internal.h"
 
@@ -38,7 +39,10 @@ struct Dev {
   const int *zfirst, *zply;
   const double *ztab, *zw;
   const int *zrow, *zcol, *zkrow, *zcptr, *zcell, *zaptr, *zaset;
-  const int *set_mat, *set_aux, *ply_mat, *ply_set, *tiles;
+  const int *set_mat, *set_aux, *ply_mat, *ply_set;
+  const int *tiles, *chunk_ptr, *chunk_sptr, *chunk_set, *zaslot;
+  int n_chunks, chunk_sets;
+  int64_t kron_lds_q, kron_lds_p;
   // scratch
   double *D, *Ec, *P, *Qc, *M;
 };
@@ -73,6 +77,14 @@ Dev make_dev(const lam_plan *p, void *ws) {
   d.set_mat = at<int>(ws, L.set_mat); d.set_aux = at<int>(ws, L.set_aux);
   d.ply_mat = at<int>(ws, L.ply_mat); d.ply_set = at<int>(ws, L.ply_set);
   d.tiles = at<int>(ws, L.tiles);
+  d.chunk_ptr = at<int>(ws, L.chunk_ptr);
+  d.chunk_sptr = at<int>(ws, L.chunk_sptr);
+  d.chunk_set = at<int>(ws, L.chunk_set);
+  d.zaslot = at<int>(ws, L.zaslot);
+  d.n_chunks = p->n_chunks;
+  d.chunk_sets = p->chunk_sets;
+  d.kron_lds_q = p->kron_lds_q;
+  d.kron_lds_p = p->kron_lds_p;
   d.D = at<double>(ws, L.D); d.Ec = at<double>(ws, L.Ec); d.P = at<double>(ws, L.P);
   d.Qc = at<double>(ws, L.Qc); d.M = at<double>(ws, L.M);
   return d;
@@ -332,35 +344,69 @@ __global__ void k_q1d(Dev d, const double *__restrict__ theta) {
 // (0..Ls-1) and component t sits at + a*3*Ls + 3*b + t: columns ascend in
 // (jt, js, t) because both 1D overlap lists are contiguous and ascending.
 
-// Kronecker scatter.  Block = (tile of in-plane nonzeros, chunk of thickness
-// rows); thread = (in-plane nonzero k, column component t).  For each
-// thickness row it of the chunk the thread loads P of the row's active sets
-// for its (k, t) and writes the 3 (r) x Lz (a) values
-//   vals = sum_j sum_ab Qc[zk][j][ab] * P[set_j][k][ab][r][t].
-constexpr int KRON_THREADS = 256;
-constexpr int KRON_AB = 4;  // thickness columns per register block
+// Kronecker scatter.  Block = (tile of whole in-plane rows, chunk of
+// thickness rows); the blocks of each XCD (block ids congruent mod 8) take a
+// contiguous range of tiles.  For every thickness row it the tile's output is
+// one contiguous range of the CSR values: rows is of the tile, then r, then
+// thickness column a, then in-plane column b, then t.  Thread = one
+// (in-plane nonzero k, component t) slot, consecutive slots on consecutive
+// lanes; it computes
+//   out = sum_j sum_ab Qc[zk][j][ab] * P[set_j][k][ab][r][t]
+// for all (r, a) with P of the chunk's sets and the chunk's coefficients Qc
+// staged in LDS (so that no global load is waited on while stores are in
+// flight), then stores r-major, a-minor: consecutive store instructions of a
+// wave write adjacent runs, so each CSR row is written front to back as one
+// sequential stream.
+constexpr int KRON_THREADS = 256;  // 3 * tile_k <= KRON_THREADS
+constexpr int KRON_AB = 5;         // thickness columns per register block
 
-__global__ void __launch_bounds__(KRON_THREADS) k_kron(Dev d, double *__restrict__ vals, int zchunk) {
-  const int tile = blockIdx.x % d.n_tiles;
-  const int zc = blockIdx.x / d.n_tiles;
-  const int k0 = d.tiles[tile], k1 = d.tiles[tile + 1];
-  const int kk = threadIdx.x / 3, t = threadIdx.x % 3;
-  const int k = k0 + kk;
-  if (k >= k1) return;
-  const int is = d.krow[k];
-  const int sr = d.srow[is], Ls = d.srow[is + 1] - sr, b = k - sr;
-  const int it0 = zc * zchunk, it1 = min(d.nt, it0 + zchunk);
+__device__ inline int kron_block(const Dev &d, int &tile, int &ch) {
+  const int nblk = d.n_tiles * d.n_chunks;
+  const int per = (nblk + 7) / 8;
+  const int L = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  tile = L / d.n_chunks;
+  ch = L - tile * d.n_chunks;
+  return L < nblk;
+}
+
+template <bool USE_LDS>
+__global__ void __launch_bounds__(KRON_THREADS) k_kron(Dev d, double *__restrict__ vals) {
+  extern __shared__ double lds[];
+  int tile, ch;
+  if (!kron_block(d, tile, ch)) return;
+  const int k0 = d.tiles[tile], tk = d.tiles[tile + 1] - k0;
+  const int it0 = d.chunk_ptr[ch], it1 = d.chunk_ptr[ch + 1];
+  const int zk0 = d.zrow[it0], nzk = d.zrow[it1] - zk0;
+  const int c0 = d.chunk_sptr[ch], nsc = d.chunk_sptr[ch + 1] - c0;
+  const int per_set = 36 * tk;
+  double *lq = lds;                     // [nzk][maxact][4]
+  double *lp = lds + d.kron_lds_q / 8;  // [nsc][tk][36]
+  for (int e = threadIdx.x; e < 4 * d.maxact * nzk; e += KRON_THREADS) lq[e] = d.Qc[4 * (int64_t)d.maxact * zk0 + e];
+  if (USE_LDS) {
+    for (int e = threadIdx.x; e < nsc * per_set; e += KRON_THREADS) {
+      const int sc = e / per_set, rem = e - sc * per_set;
+      lp[e] = d.P[((int64_t)d.chunk_set[c0 + sc] * d.nnz2 + k0) * 36 + rem];
+    }
+  }
+  __syncthreads();
+  const int sig = threadIdx.x;
+  if (sig >= 3 * tk) return;
+  const int kk = sig / 3, t = sig - 3 * kk, k = k0 + kk;
+  const int is = d.krow[k], sr = d.srow[is];
+  const int Ls = d.srow[is + 1] - sr, off = 3 * (k - sr) + t;
+  const int64_t astride = 3 * (int64_t)Ls;
   for (int it = it0; it < it1; ++it) {
     const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
     const int a0 = d.zaptr[it], na = d.zaptr[it + 1] - a0;
-    const int64_t base = 9 * d.nnz2 * (int64_t)zb + 3 * (int64_t)Lz * 3 * sr + 3 * b + t;
+    double *out = vals + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
+    const int64_t rstride = 3 * (int64_t)Lz * Ls;
     for (int ab0 = 0; ab0 < Lz; ab0 += KRON_AB) {
       double acc[KRON_AB][3];
 #pragma unroll
       for (int x = 0; x < KRON_AB; ++x) acc[x][0] = acc[x][1] = acc[x][2] = 0.0;
       for (int j = 0; j < na; ++j) {
-        const int s = d.zaset[a0 + j];
-        const double *Pp = d.P + 36 * ((int64_t)s * d.nnz2 + k) + t;
+        const double *Pp = USE_LDS ? lp + (d.zaslot[a0 + j] * tk + kk) * 36 + t
+                                   : d.P + ((int64_t)d.zaset[a0 + j] * d.nnz2 + k) * 36 + t;
         double pr[4][3];
 #pragma unroll
         for (int ab = 0; ab < 4; ++ab)
@@ -369,7 +415,7 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron(Dev d, double *__restrict
 #pragma unroll
         for (int x = 0; x < KRON_AB; ++x) {
           if (ab0 + x < Lz) {
-            const double *qq = d.Qc + 4 * ((int64_t)(zb + ab0 + x) * d.maxact + j);
+            const double *qq = lq + 4 * ((zb + ab0 + x - zk0) * d.maxact + j);
             const double q0 = qq[0], q1 = qq[1], q2 = qq[2], q3 = qq[3];
 #pragma unroll
             for (int r = 0; r < 3; ++r) acc[x][r] += q0 * pr[0][r] + q1 * pr[1][r] + q2 * pr[2][r] + q3 * pr[3][r];
@@ -377,13 +423,10 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron(Dev d, double *__restrict
         }
       }
 #pragma unroll
-      for (int x = 0; x < KRON_AB; ++x) {
-        if (ab0 + x < Lz) {
+      for (int r = 0; r < 3; ++r)
 #pragma unroll
-          for (int r = 0; r < 3; ++r)
-            vals[base + 3 * (int64_t)Lz * r * Ls + (int64_t)(ab0 + x) * 3 * Ls] = acc[x][r];
-        }
-      }
+        for (int x = 0; x < KRON_AB; ++x)
+          if (ab0 + x < Lz) out[r * rstride + (int64_t)(ab0 + x) * astride] = acc[x][r];
     }
   }
 }
@@ -403,23 +446,22 @@ __global__ void k_rowptr(Dev d, int64_t *__restrict__ rowptr) {
   rowptr[row] = 9 * d.nnz2 * (int64_t)zb + 3 * (int64_t)Lz * (3 * (int64_t)sr + (int64_t)r * Ls);
 }
 
-__global__ void __launch_bounds__(KRON_THREADS) k_colind(Dev d, int32_t *__restrict__ colind, int zchunk) {
-  const int tile = blockIdx.x % d.n_tiles;
-  const int zc = blockIdx.x / d.n_tiles;
-  const int k0 = d.tiles[tile], k1 = d.tiles[tile + 1];
-  const int kk = threadIdx.x / 3, t = threadIdx.x % 3;
-  const int k = k0 + kk;
-  if (k >= k1) return;
-  const int is = d.krow[k], js = d.kcol[k];
-  const int sr = d.srow[is], Ls = d.srow[is + 1] - sr, b = k - sr;
-  const int it0 = zc * zchunk, it1 = min(d.nt, it0 + zchunk);
-  for (int it = it0; it < it1; ++it) {
-    const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
-    const int64_t base = 9 * d.nnz2 * (int64_t)zb + 3 * (int64_t)Lz * 3 * sr + 3 * b + t;
-    for (int a = 0; a < Lz; ++a) {
-      const int jt = d.zcol[zb + a];
-      const int32_t col = 3 * (jt * d.ns + js) + t;
-      for (int r = 0; r < 3; ++r) colind[base + 3 * (int64_t)Lz * r * Ls + (int64_t)a * 3 * Ls] = col;
+__global__ void __launch_bounds__(KRON_THREADS) k_colind(Dev d, int32_t *__restrict__ colind) {
+  int tile, ch;
+  if (!kron_block(d, tile, ch)) return;
+  const int k0 = d.tiles[tile], tk = d.tiles[tile + 1] - k0;
+  const int it0 = d.chunk_ptr[ch], it1 = d.chunk_ptr[ch + 1];
+  for (int sig = threadIdx.x; sig < 3 * tk; sig += KRON_THREADS) {
+    const int kk = sig / 3, t = sig - 3 * kk, k = k0 + kk;
+    const int is = d.krow[k], js = d.kcol[k];
+    const int sr = d.srow[is], Ls = d.srow[is + 1] - sr;
+    for (int it = it0; it < it1; ++it) {
+      const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
+      int32_t *out = colind + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + 3 * (k - sr) + t;
+      for (int a = 0; a < Lz; ++a) {
+        const int32_t col = 3 * (d.zcol[zb + a] * d.ns + js) + t;
+        for (int r = 0; r < 3; ++r) out[r * 3 * (int64_t)Lz * Ls + (int64_t)a * 3 * Ls] = col;
+      }
     }
   }
 }
@@ -429,15 +471,18 @@ lam_status hip_status() {
   return e == hipSuccess ? LAM_OK : LAM_EHIP;
 }
 
-int kron_zchunk(const lam_plan *p, int *nblocks) {
-  // enough blocks to fill 256 CUs several times over; each block keeps its
-  // tile of P warm in cache across its chunk of thickness rows
-  int64_t want = 4096;
-  int nz = (int)std::max<int64_t>(1, std::min<int64_t>(p->nt, (want + p->n_tiles - 1) / p->n_tiles));
-  int zchunk = (p->nt + nz - 1) / nz;
-  nz = (p->nt + zchunk - 1) / zchunk;
-  *nblocks = p->n_tiles * nz;
-  return zchunk;
+int kron_grid(const lam_plan *p) {
+  int nblk = p->n_tiles * p->n_chunks;
+  return 8 * ((nblk + 7) / 8);
+}
+
+void launch_kron(const lam_plan *p, const Dev &d, double *vals, hipStream_t s) {
+  const int grid = kron_grid(p);
+  const size_t lds = (size_t)p->kron_lds;
+  if (p->chunk_sets > 0)
+    hipLaunchKernelGGL((k_kron<true>), dim3(grid), dim3(KRON_THREADS), lds, s, d, vals);
+  else
+    hipLaunchKernelGGL((k_kron<false>), dim3(grid), dim3(KRON_THREADS), lds, s, d, vals);
 }
 
 lam_status check_ws(const lam_plan *p, const void *ws, int64_t ws_bytes) {
@@ -466,9 +511,7 @@ extern "C" LAM_API lam_status lam_pattern(const lam_plan *p, const void *ws, int
   Dev d = make_dev(p, const_cast<void *>(ws));
   int64_t nb = (p->nrows + 1 + 255) / 256;
   hipLaunchKernelGGL(k_rowptr, dim3((unsigned)nb), dim3(256), 0, s, d, rowptr);
-  int nblocks;
-  int zchunk = kron_zchunk(p, &nblocks);
-  hipLaunchKernelGGL(k_colind, dim3(nblocks), dim3(KRON_THREADS), 0, s, d, colind, zchunk);
+  hipLaunchKernelGGL(k_colind, dim3(kron_grid(p)), dim3(KRON_THREADS), 0, s, d, colind);
   return hip_status();
 }
 
@@ -484,9 +527,9 @@ extern "C" LAM_API lam_status lam_assemble(const lam_plan *p, void *ws, int64_t 
   hipLaunchKernelGGL(k_p2d, dim3((unsigned)((p->nnz2 + 255) / 256)), dim3(256), 0, s, d);
   int64_t nq = p->nnzz * p->maxact;
   hipLaunchKernelGGL(k_q1d, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, d, theta);
-  int nblocks;
-  int zchunk = kron_zchunk(p, &nblocks);
-  hipLaunchKernelGGL(k_kron, dim3(nblocks), dim3(KRON_THREADS), 0, s, d, vals, zchunk);
+  void *prof = lam::profile_begin(0, stream);
+  launch_kron(p, d, vals, s);
+  lam::profile_end(prof, stream);
   return hip_status();
 }
 

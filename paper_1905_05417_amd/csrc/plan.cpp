@@ -7,6 +7,7 @@
 // at assembly time.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -401,11 +402,106 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
   }
   P->maxact = std::max(maxact, 1);
 
-  // ---- Kronecker scatter tiles: runs of in-plane nonzeros, one thread per (k, s)
-  P->tile_k = 85;
-  P->n_tiles = (int)((P->nnz2 + P->tile_k - 1) / P->tile_k);
-  std::vector<int> tiles(P->n_tiles + 1);
-  for (int t = 0; t <= P->n_tiles; ++t) tiles[t] = (int)std::min<int64_t>((int64_t)t * P->tile_k, P->nnz2);
+  // ---- Kronecker scatter tiles and chunks.
+  // A tile is a run of whole in-plane rows, so that for every thickness row
+  // one block writes one contiguous range of the CSR values (no cache line is
+  // shared between blocks except at the two ends).  The block keeps the
+  // tile's P of the sets active in its chunk of thickness rows in LDS.
+  const int64_t per_k = 36 * (int64_t)sizeof(double);  // P bytes per in-plane nonzero and set
+  int max_ls = 0, lzmax = 0;
+  for (int is = 0; is < P->ns; ++is) max_ls = std::max(max_ls, srow[is + 1] - srow[is]);
+  for (int it = 0; it < P->nt; ++it) lzmax = std::max(lzmax, zrow[it + 1] - zrow[it]);
+  const int64_t per_out = 0;  // the scatter keeps no output buffer in LDS
+  int64_t lds_budget = 80 * 1024;
+  if (const char *e = std::getenv("LAMASM_KRON_LDS")) lds_budget = std::max<int64_t>(16 * 1024, std::atoll(e) * 1024);
+  int64_t qbudget = 8 * 1024;
+  int tk_target = 85;  // 255 (k, component) slots per block
+  if (const char *e = std::getenv("LAMASM_KRON_TK")) tk_target = std::min(85, std::max(1, std::atoi(e)));
+  tk_target = std::max(tk_target, max_ls);
+  if (tk_target > 85) {
+    delete P;
+    return LAM_EUNSUP;
+  }
+  // largest tile (whole rows, <= tk_target nonzeros) whose P of every set, output
+  // buffer and coefficients fit the budget; else the largest number of sets
+  // that fits next to a one-row tile
+  int tkmax = tk_target, sc = 0;
+  for (int tk = tk_target; tk >= max_ls; --tk) {
+    if (per_k * tk * P->n_sets + per_out * tk + qbudget <= lds_budget) {
+      tkmax = tk;
+      sc = P->n_sets;
+      break;
+    }
+  }
+  if (sc == 0) {
+    tkmax = max_ls;
+    sc = (int)std::min<int64_t>(P->n_sets, (lds_budget - per_out * tkmax - qbudget) / (per_k * tkmax));
+  }
+  // else a single thickness row needs more sets than fit: P is read from memory
+  const bool lds_mode = sc >= P->maxact;
+  if (!lds_mode) {
+    tkmax = tk_target;
+    sc = 0;
+  }
+  std::vector<int> tiles(1, 0);
+  for (int is = 0; is < P->ns; ++is) {
+    int cur = srow[is + 1] - tiles.back();
+    if (cur > tkmax) tiles.push_back(srow[is]);
+  }
+  tiles.push_back((int)P->nnz2);
+  P->n_tiles = (int)tiles.size() - 1;
+  P->tile_k = tkmax;
+  // chunks: consecutive thickness rows whose active sets fit in sc LDS slots
+  // and whose folded 1D coefficients (4 doubles per row pair and active slot)
+  // fit in qbudget bytes of LDS
+  const int64_t q_per_zk = 4 * (int64_t)sizeof(double) * P->maxact;
+  std::vector<int> chunk_ptr(1, 0), chunk_sptr(1, 0), chunk_set, zaslot(zaset.size(), 0);
+  {
+    std::vector<int> cur;
+    int start = 0;
+    int64_t qbytes = 0;
+    auto flush = [&](int end) {
+      std::sort(cur.begin(), cur.end());
+      for (int it = start; it < end; ++it)
+        for (int j = zaptr[it]; j < zaptr[it + 1]; ++j)
+          zaslot[j] = lds_mode ? (int)(std::lower_bound(cur.begin(), cur.end(), zaset[j]) - cur.begin()) : 0;
+      chunk_set.insert(chunk_set.end(), cur.begin(), cur.end());
+      chunk_sptr.push_back((int)chunk_set.size());
+      chunk_ptr.push_back(end);
+      cur.clear();
+      start = end;
+      qbytes = 0;
+    };
+    for (int it = 0; it < P->nt; ++it) {
+      int64_t qrow = q_per_zk * (zrow[it + 1] - zrow[it]);
+      std::vector<int> uni = cur;
+      if (lds_mode)
+        for (int j = zaptr[it]; j < zaptr[it + 1]; ++j)
+          if (std::find(uni.begin(), uni.end(), zaset[j]) == uni.end()) uni.push_back(zaset[j]);
+      if (it > start && ((int)uni.size() > sc || qbytes + qrow > qbudget)) {
+        flush(it);
+        uni.clear();
+        if (lds_mode) uni.assign(zaset.begin() + zaptr[it], zaset.begin() + zaptr[it + 1]);
+      }
+      cur = uni;
+      qbytes += qrow;
+    }
+    flush(P->nt);
+  }
+  P->n_chunks = (int)chunk_ptr.size() - 1;
+  P->chunk_sets = sc;
+  // LDS: the chunk's folded 1D coefficients and its P slots
+  int max_chunk_zk = 0;
+  for (int c = 0; c < P->n_chunks; ++c)
+    max_chunk_zk = std::max(max_chunk_zk, zrow[chunk_ptr[c + 1]] - zrow[chunk_ptr[c]]);
+  P->kron_lzmax = lzmax;
+  P->kron_lds_q = 4 * (int64_t)sizeof(double) * P->maxact * max_chunk_zk;
+  P->kron_lds_p = per_k * tkmax * sc;
+  P->kron_lds = P->kron_lds_q + P->kron_lds_p + per_out * tkmax;
+  if (P->kron_lds > 160 * 1024) {
+    delete P;
+    return LAM_EUNSUP;  // one thickness row's coefficients exceed the LDS of a compute unit
+  }
 
   std::vector<int> plymat(d->ply_mat, d->ply_mat + d->n_ply);
 
@@ -441,6 +537,10 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
   L.ply_mat = B.take(sizeof(int) * plymat.size());
   L.ply_set = B.take(sizeof(int) * ply_set.size());
   L.tiles = B.take(sizeof(int) * tiles.size());
+  L.chunk_ptr = B.take(sizeof(int) * chunk_ptr.size());
+  L.chunk_sptr = B.take(sizeof(int) * chunk_sptr.size());
+  L.chunk_set = B.take(sizeof(int) * chunk_set.size());
+  L.zaslot = B.take(sizeof(int) * zaslot.size());
   L.const_bytes = B.cur;
   L.D = B.take(sizeof(double) * 36 * P->n_sets);
   L.Ec = B.take(sizeof(double) * 81 * P->n_sets);
@@ -498,6 +598,10 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
   put(img, L.ply_mat, plymat);
   put(img, L.ply_set, ply_set);
   put(img, L.tiles, tiles);
+  put(img, L.chunk_ptr, chunk_ptr);
+  put(img, L.chunk_sptr, chunk_sptr);
+  put(img, L.chunk_set, chunk_set);
+  put(img, L.zaslot, zaslot);
   *out = P;
   return LAM_OK;
 }

@@ -46,7 +46,8 @@ class _Desc(ctypes.Structure):
 _lib = None
 
 EXPORTED = ("lam_plan_create", "lam_plan_destroy", "lam_plan_info", "lam_plan_upload", "lam_pattern",
-            "lam_assemble", "lam_assemble_standard", "lam_adjoint", "lam_status_string", "lam_version")
+            "lam_assemble", "lam_assemble_standard", "lam_adjoint", "lam_profile_enable", "lam_profile_read",
+            "lam_status_string", "lam_version")
 
 
 def lib():
@@ -66,6 +67,8 @@ def lib():
         L.lam_assemble.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
         L.lam_assemble_standard.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
         L.lam_adjoint.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
+        L.lam_profile_enable.argtypes = [ctypes.c_int32]
+        L.lam_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.lam_status_string.argtypes = [ctypes.c_int32]
         L.lam_status_string.restype = ctypes.c_char_p
         L.lam_version.restype = ctypes.c_char_p
@@ -194,6 +197,19 @@ class Plan:
     def csr(self, vals, pattern=None):
         rowptr, colind = self.pattern() if pattern is None else pattern
         return torch.sparse_csr_tensor(rowptr, colind.to(torch.int64), vals, size=(self.n_rows, self.n_rows))
+
+
+def profile_enable(on: bool = True):
+    """Record HIP events around each entry point's dominant kernel."""
+    _check(lib().lam_profile_enable(1 if on else 0), "lam_profile_enable")
+
+
+def profile_read():
+    """{'assemble'|'standard'|'adjoint': (ms_total, launches)} since the last read."""
+    ms = (ctypes.c_double * 3)()
+    n = (ctypes.c_int64 * 3)()
+    _check(lib().lam_profile_read(ms, n), "lam_profile_read")
+    return {k: (ms[i], n[i]) for i, k in enumerate(("assemble", "standard", "adjoint"))}
 
 
 class _Assemble(torch.autograd.Function):
