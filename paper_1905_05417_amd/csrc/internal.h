@@ -41,7 +41,7 @@ struct Layout {
   // of each tile), chunks of thickness rows (first row of each chunk), the
   // sets each chunk keeps in LDS (chunk_sptr, chunk_set), and for every
   // active set of a row its LDS slot in the row's chunk (zaslot, parallel to zaset)
-  Region tiles, chunk_ptr, chunk_sptr, chunk_set, zaslot;
+  Region tiles, chunk_ptr, chunk_sptr, chunk_set, zaslot, zchunk;
   int64_t const_bytes = 0;  // end of the constant part
   // scratch
   Region D, Ec, P, Qc, M;
@@ -66,7 +66,8 @@ struct lam_plan {
   int n_tiles = 0, tile_k = 0;      // tiles of whole rows, at most tile_k in-plane nonzeros each
   int n_chunks = 0, chunk_sets = 0; // thickness-row chunks, at most chunk_sets sets in LDS each
   int64_t kron_lds = 0;             // LDS bytes of the scatter kernel
-  int kron_lzmax = 0;               // longest thickness row (columns) of the pattern
+  int kron_nsc = 0;                 // register mode: set slots per thread (0: LDS mode)
+  int kron_threads = 256;           // scatter block size
   int64_t kron_lds_q = 0, kron_lds_p = 0;  // LDS bytes of the Q and P parts (output buffer follows)
   double jit[9] = {0};  // DF^{-T}, row-major
   double detj = 0.0;    // |det DF|

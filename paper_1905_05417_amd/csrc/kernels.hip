@@ -43,6 +43,8 @@ struct Dev {
   const int *tiles, *chunk_ptr, *chunk_sptr, *chunk_set, *zaslot;
   int n_chunks, chunk_sets;
   int64_t kron_lds_q, kron_lds_p;
+  const int *zchunk;
+  int kron_nsc;
   // scratch
   double *D, *Ec, *P, *Qc, *M;
 };
@@ -84,6 +86,8 @@ Dev make_dev(const lam_plan *p, void *ws) {
   d.n_chunks = p->n_chunks;
   d.chunk_sets = p->chunk_sets;
   d.kron_lds_q = p->kron_lds_q;
+  d.zchunk = at<int>(ws, L.zchunk);
+  d.kron_nsc = p->kron_nsc;
   d.kron_lds_p = p->kron_lds_p;
   d.D = at<double>(ws, L.D); d.Ec = at<double>(ws, L.Ec); d.P = at<double>(ws, L.P);
   d.Qc = at<double>(ws, L.Qc); d.M = at<double>(ws, L.M);
@@ -208,7 +212,8 @@ __global__ void k_rotate(Dev d, const double *__restrict__ C, const double *__re
 // pushed through DF^{-T} (grad V = DF^{-T}(dS1,dS2,0), W = DF^{-T}(0,0,S))
 // into M_ab[k][l] = int (G_a^i)_k (G_b^j)_l |DF|.  Because each set's
 // material is constant over the plane, P_{s,ab}[r][t] = sum_kl M_ab[k][l] E_s[k][l][r][t].
-__global__ void __launch_bounds__(256) k_p2d(Dev d) {
+__global__ void __launch_bounds__(256) k_p2d(Dev d, const double *__restrict__ Ec, double *__restrict__ Pt,
+                                             double *__restrict__ Mt) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= d.nnz2) return;
   const int is = d.krow[k], js = d.kcol[k];
@@ -268,14 +273,14 @@ __global__ void __launch_bounds__(256) k_p2d(Dev d) {
       M[2][kk][ll] = d.detj * J[kk * 3 + 2] * v21;
       M[3][kk][ll] = d.detj * J[kk * 3 + 2] * J[ll * 3 + 2] * m22;
     }
-  double *Mo = d.M + 36 * k;
+  // component-major tables: consecutive threads (k) store consecutive addresses
 #pragma unroll
   for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
-    for (int e = 0; e < 9; ++e) Mo[ab * 9 + e] = M[ab][e / 3][e % 3];
+    for (int e = 0; e < 9; ++e) Mt[(int64_t)(ab * 9 + e) * d.nnz2 + k] = M[ab][e / 3][e % 3];
   for (int s = 0; s < d.n_sets; ++s) {
-    const double *E = d.Ec + 81 * s;
-    double *Po = d.P + 36 * ((int64_t)s * d.nnz2 + k);
+    const double *E = Ec + 81 * s;
+    double *Po = Pt + (int64_t)s * 36 * d.nnz2 + k;
 #pragma unroll
     for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
@@ -283,7 +288,7 @@ __global__ void __launch_bounds__(256) k_p2d(Dev d) {
         double a = 0.0;
 #pragma unroll
         for (int kl = 0; kl < 9; ++kl) a += M[ab][kl / 3][kl % 3] * E[kl * 9 + rt];
-        Po[ab * 9 + rt] = a;
+        Po[(int64_t)(ab * 9 + rt) * d.nnz2] = a;
       }
   }
 }
@@ -295,14 +300,23 @@ __global__ void __launch_bounds__(256) k_p2d(Dev d) {
 // with tau_1 = T, tau_2 = dT/dxi3, a on the test function it, and
 // w_{s,l} = [set of l == s] (bucket) or [mat(l) == mat(s)] * harmonic_s(theta_l).
 __global__ void k_q1d(Dev d, const double *__restrict__ theta) {
+  // register mode: one entry per chunk set slot (zeros where the slot's set
+  // does not act on the pair); LDS mode: one per set active on the row
+  const int width = d.kron_nsc > 0 ? d.kron_nsc : d.maxact;
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= d.nnzz * d.maxact) return;
-  const int zk = (int)(idx / d.maxact), j = (int)(idx % d.maxact);
+  if (idx >= d.nnzz * width) return;
+  const int zk = (int)(idx / width), j = (int)(idx % width);
   const int it = d.zkrow[zk], jt = d.zcol[zk];
-  const int a0 = d.zaptr[it], na = d.zaptr[it + 1] - a0;
+  int s = -1;
+  if (d.kron_nsc > 0) {
+    const int ch = d.zchunk[it], c0 = d.chunk_sptr[ch];
+    if (j < d.chunk_sptr[ch + 1] - c0) s = d.chunk_set[c0 + j];
+  } else {
+    const int a0 = d.zaptr[it];
+    if (j < d.zaptr[it + 1] - a0) s = d.zaset[a0 + j];
+  }
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  if (j < na) {
-    const int s = d.zaset[a0 + j];
+  if (s >= 0) {
     const int Q1 = d.q + 1;
     for (int ci = d.zcptr[zk]; ci < d.zcptr[zk + 1]; ++ci) {
       const int c = d.zcell[ci], l = d.zply[c];
@@ -370,7 +384,7 @@ __device__ inline int kron_block(const Dev &d, int &tile, int &ch) {
 }
 
 template <bool USE_LDS>
-__global__ void __launch_bounds__(KRON_THREADS) k_kron(Dev d, double *__restrict__ vals) {
+__global__ void __launch_bounds__(KRON_THREADS) k_kron_lds(Dev d, double *__restrict__ vals) {
   extern __shared__ double lds[];
   int tile, ch;
   if (!kron_block(d, tile, ch)) return;
@@ -384,8 +398,9 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron(Dev d, double *__restrict
   for (int e = threadIdx.x; e < 4 * d.maxact * nzk; e += KRON_THREADS) lq[e] = d.Qc[4 * (int64_t)d.maxact * zk0 + e];
   if (USE_LDS) {
     for (int e = threadIdx.x; e < nsc * per_set; e += KRON_THREADS) {
-      const int sc = e / per_set, rem = e - sc * per_set;
-      lp[e] = d.P[((int64_t)d.chunk_set[c0 + sc] * d.nnz2 + k0) * 36 + rem];
+      // read k-fastest from the component-major table, store [slot][k][36]
+      const int sc = e / per_set, rem = e - sc * per_set, comp = rem / tk, kk = rem - comp * tk;
+      lp[(sc * tk + kk) * 36 + comp] = d.P[((int64_t)d.chunk_set[c0 + sc] * 36 + comp) * d.nnz2 + k0 + kk];
     }
   }
   __syncthreads();
@@ -405,13 +420,20 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron(Dev d, double *__restrict
 #pragma unroll
       for (int x = 0; x < KRON_AB; ++x) acc[x][0] = acc[x][1] = acc[x][2] = 0.0;
       for (int j = 0; j < na; ++j) {
-        const double *Pp = USE_LDS ? lp + (d.zaslot[a0 + j] * tk + kk) * 36 + t
-                                   : d.P + ((int64_t)d.zaset[a0 + j] * d.nnz2 + k) * 36 + t;
         double pr[4][3];
+        if (USE_LDS) {
+          const double *Pp = lp + (d.zaslot[a0 + j] * tk + kk) * 36 + t;
 #pragma unroll
-        for (int ab = 0; ab < 4; ++ab)
+          for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
-          for (int r = 0; r < 3; ++r) pr[ab][r] = Pp[ab * 9 + 3 * r];
+            for (int r = 0; r < 3; ++r) pr[ab][r] = Pp[ab * 9 + 3 * r];
+        } else {
+          const double *Pp = d.P + (int64_t)d.zaset[a0 + j] * 36 * d.nnz2 + k;
+#pragma unroll
+          for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) pr[ab][r] = Pp[(int64_t)(ab * 9 + 3 * r + t) * d.nnz2];
+        }
 #pragma unroll
         for (int x = 0; x < KRON_AB; ++x) {
           if (ab0 + x < Lz) {
@@ -419,6 +441,67 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron(Dev d, double *__restrict
             const double q0 = qq[0], q1 = qq[1], q2 = qq[2], q3 = qq[3];
 #pragma unroll
             for (int r = 0; r < 3; ++r) acc[x][r] += q0 * pr[0][r] + q1 * pr[1][r] + q2 * pr[2][r] + q3 * pr[3][r];
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int x = 0; x < KRON_AB; ++x)
+          if (ab0 + x < Lz) out[r * rstride + (int64_t)(ab0 + x) * astride] = acc[x][r];
+    }
+  }
+}
+
+// Register mode of the scatter: each thread loads P of the chunk's NSC set
+// slots for its (k, t) once into registers and reads the slot-dense
+// coefficients Qd[zk][slot][ab] with scalar loads (uniform addresses), so the
+// row loop issues no vector loads at all and the stores stream.
+template <int NSC>
+__global__ void __launch_bounds__(KRON_THREADS) k_kron_reg(Dev d, const double *__restrict__ qd,
+                                                           double *__restrict__ vals) {
+  extern __shared__ double lq[];  // the chunk's slot-dense coefficients [zk - zk0][NSC][4]
+  int tile, ch;
+  if (!kron_block(d, tile, ch)) return;
+  const int k0 = d.tiles[tile], tk = d.tiles[tile + 1] - k0;
+  const int it0 = d.chunk_ptr[ch], it1 = d.chunk_ptr[ch + 1];
+  const int zk0 = d.zrow[it0], nq = 4 * NSC * (d.zrow[it1] - zk0);
+  const int sig = threadIdx.x;
+  const bool act = sig < 3 * tk;
+  const int kk = act ? sig / 3 : 0, t = act ? sig - 3 * kk : 0, k = k0 + kk;
+  const int c0 = d.chunk_sptr[ch], nsc = d.chunk_sptr[ch + 1] - c0;
+  double pr[NSC][4][3];
+#pragma unroll
+  for (int u = 0; u < NSC; ++u) {
+    const double *Pp = d.P + (int64_t)(u < nsc ? d.chunk_set[c0 + u] : 0) * 36 * d.nnz2 + k;
+#pragma unroll
+    for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) pr[u][ab][r] = u < nsc ? Pp[(int64_t)(ab * 9 + 3 * r + t) * d.nnz2] : 0.0;
+  }
+  for (int e = sig; e < nq; e += blockDim.x) lq[e] = qd[4 * (int64_t)NSC * zk0 + e];
+  __syncthreads();
+  if (!act) return;
+  const int is = d.krow[k], sr = d.srow[is];
+  const int Ls = d.srow[is + 1] - sr, off = 3 * (k - sr) + t;
+  const int64_t astride = 3 * (int64_t)Ls;
+  for (int it = it0; it < it1; ++it) {
+    const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
+    double *out = vals + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
+    const int64_t rstride = 3 * (int64_t)Lz * Ls;
+    for (int ab0 = 0; ab0 < Lz; ab0 += KRON_AB) {
+      double acc[KRON_AB][3];
+#pragma unroll
+      for (int x = 0; x < KRON_AB; ++x) {
+        acc[x][0] = acc[x][1] = acc[x][2] = 0.0;
+        if (ab0 + x < Lz) {
+          const double *qq = lq + 4 * NSC * (zb + ab0 + x - zk0);
+#pragma unroll
+          for (int u = 0; u < NSC; ++u) {
+            const double q0 = qq[4 * u], q1 = qq[4 * u + 1], q2 = qq[4 * u + 2], q3 = qq[4 * u + 3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+              acc[x][r] += q0 * pr[u][0][r] + q1 * pr[u][1][r] + q2 * pr[u][2][r] + q3 * pr[u][3][r];
           }
         }
       }
@@ -479,10 +562,18 @@ int kron_grid(const lam_plan *p) {
 void launch_kron(const lam_plan *p, const Dev &d, double *vals, hipStream_t s) {
   const int grid = kron_grid(p);
   const size_t lds = (size_t)p->kron_lds;
+  const dim3 blk(p->kron_threads);
+  switch (p->kron_nsc) {
+    case 1: hipLaunchKernelGGL((k_kron_reg<1>), dim3(grid), blk, lds, s, d, d.Qc, vals); return;
+    case 2: hipLaunchKernelGGL((k_kron_reg<2>), dim3(grid), blk, lds, s, d, d.Qc, vals); return;
+    case 4: hipLaunchKernelGGL((k_kron_reg<4>), dim3(grid), blk, lds, s, d, d.Qc, vals); return;
+    case 8: hipLaunchKernelGGL((k_kron_reg<8>), dim3(grid), blk, lds, s, d, d.Qc, vals); return;
+    default: break;
+  }
   if (p->chunk_sets > 0)
-    hipLaunchKernelGGL((k_kron<true>), dim3(grid), dim3(KRON_THREADS), lds, s, d, vals);
+    hipLaunchKernelGGL((k_kron_lds<true>), dim3(grid), dim3(KRON_THREADS), lds, s, d, vals);
   else
-    hipLaunchKernelGGL((k_kron<false>), dim3(grid), dim3(KRON_THREADS), lds, s, d, vals);
+    hipLaunchKernelGGL((k_kron_lds<false>), dim3(grid), dim3(KRON_THREADS), lds, s, d, vals);
 }
 
 lam_status check_ws(const lam_plan *p, const void *ws, int64_t ws_bytes) {
@@ -524,8 +615,8 @@ extern "C" LAM_API lam_status lam_assemble(const lam_plan *p, void *ws, int64_t 
   hipStream_t s = static_cast<hipStream_t>(stream);
   Dev d = make_dev(p, ws);
   hipLaunchKernelGGL(k_rotate, dim3((p->n_sets + 63) / 64), dim3(64), 0, s, d, C, theta);
-  hipLaunchKernelGGL(k_p2d, dim3((unsigned)((p->nnz2 + 255) / 256)), dim3(256), 0, s, d);
-  int64_t nq = p->nnzz * p->maxact;
+  hipLaunchKernelGGL(k_p2d, dim3((unsigned)((p->nnz2 + 255) / 256)), dim3(256), 0, s, d, d.Ec, d.P, d.M);
+  int64_t nq = p->nnzz * (p->kron_nsc > 0 ? p->kron_nsc : p->maxact);
   hipLaunchKernelGGL(k_q1d, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, d, theta);
   void *prof = lam::profile_begin(0, stream);
   launch_kron(p, d, vals, s);

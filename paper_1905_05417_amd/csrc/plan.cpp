@@ -403,68 +403,89 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
   P->maxact = std::max(maxact, 1);
 
   // ---- Kronecker scatter tiles and chunks.
-  // A tile is a run of whole in-plane rows, so that for every thickness row
-  // one block writes one contiguous range of the CSR values (no cache line is
-  // shared between blocks except at the two ends).  The block keeps the
-  // tile's P of the sets active in its chunk of thickness rows in LDS.
+  // A tile is a run of whole in-plane rows (at most 85 in-plane nonzeros, one
+  // thread per (nonzero, component) slot), so that for every thickness row one
+  // block writes one contiguous range of the CSR values and no cache line is
+  // shared between blocks except at the two ends of the range.  A chunk is a
+  // run of thickness rows whose active sets fit the block's set slots.
+  //  - register mode (every row needs at most 8 sets): each thread keeps P of
+  //    the chunk's sets for its slot in registers (kron_nsc slots: 1, 2, 4 or 8)
+  //    and reads the slot-dense coefficients Qd with scalar loads;
+  //  - LDS mode (more sets per row): the tile's P of the chunk's sets and the
+  //    chunk's coefficients Qc are staged in LDS.
   const int64_t per_k = 36 * (int64_t)sizeof(double);  // P bytes per in-plane nonzero and set
-  int max_ls = 0, lzmax = 0;
+  int max_ls = 0;
   for (int is = 0; is < P->ns; ++is) max_ls = std::max(max_ls, srow[is + 1] - srow[is]);
-  for (int it = 0; it < P->nt; ++it) lzmax = std::max(lzmax, zrow[it + 1] - zrow[it]);
-  const int64_t per_out = 0;  // the scatter keeps no output buffer in LDS
-  int64_t lds_budget = 80 * 1024;
-  if (const char *e = std::getenv("LAMASM_KRON_LDS")) lds_budget = std::max<int64_t>(16 * 1024, std::atoll(e) * 1024);
-  int64_t qbudget = 8 * 1024;
-  int tk_target = 85;  // 255 (k, component) slots per block
+  // whole rows of the typical (interior) length fill a 256-thread block best
+  int tk_target = max_ls > 0 ? max_ls * std::max(1, 85 / max_ls) : 85;
   if (const char *e = std::getenv("LAMASM_KRON_TK")) tk_target = std::min(85, std::max(1, std::atoi(e)));
   tk_target = std::max(tk_target, max_ls);
   if (tk_target > 85) {
     delete P;
     return LAM_EUNSUP;
   }
-  // largest tile (whole rows, <= tk_target nonzeros) whose P of every set, output
-  // buffer and coefficients fit the budget; else the largest number of sets
-  // that fits next to a one-row tile
-  int tkmax = tk_target, sc = 0;
-  for (int tk = tk_target; tk >= max_ls; --tk) {
-    if (per_k * tk * P->n_sets + per_out * tk + qbudget <= lds_budget) {
-      tkmax = tk;
-      sc = P->n_sets;
-      break;
-    }
-  }
-  if (sc == 0) {
-    tkmax = max_ls;
-    sc = (int)std::min<int64_t>(P->n_sets, (lds_budget - per_out * tkmax - qbudget) / (per_k * tkmax));
-  }
-  // else a single thickness row needs more sets than fit: P is read from memory
-  const bool lds_mode = sc >= P->maxact;
-  if (!lds_mode) {
-    tkmax = tk_target;
+  int nsc_cap = 4;
+  if (const char *e = std::getenv("LAMASM_KRON_NSC")) nsc_cap = std::max(1, std::atoi(e));
+  const bool reg_mode = P->maxact <= 8;
+  int sc, tkmax = tk_target;
+  int64_t qbudget = 8 * 1024, lds_budget = 80 * 1024;
+  if (const char *e = std::getenv("LAMASM_KRON_LDS")) lds_budget = std::max<int64_t>(16 * 1024, std::atoll(e) * 1024);
+  if (reg_mode) {
+    int want = std::max(P->maxact, std::min(P->n_sets, nsc_cap));
+    sc = want <= 1 ? 1 : want <= 2 ? 2 : want <= 4 ? 4 : 8;
+    P->kron_nsc = sc;
+  } else {
+    // largest tile whose P of every set and coefficients fit; else as many
+    // sets as fit next to a one-row tile; else P is read from memory
     sc = 0;
+    for (int tk = tk_target; tk >= max_ls; --tk)
+      if (per_k * tk * P->n_sets + qbudget <= lds_budget) {
+        tkmax = tk;
+        sc = P->n_sets;
+        break;
+      }
+    if (sc == 0) {
+      tkmax = max_ls;
+      sc = (int)std::min<int64_t>(P->n_sets, (lds_budget - qbudget) / (per_k * tkmax));
+    }
+    if (sc < P->maxact) {
+      tkmax = tk_target;
+      sc = 0;
+    }
+    P->kron_nsc = 0;
   }
+  const bool lds_sets = !reg_mode && sc > 0;
   std::vector<int> tiles(1, 0);
+  int tk_real = 0;
   for (int is = 0; is < P->ns; ++is) {
     int cur = srow[is + 1] - tiles.back();
-    if (cur > tkmax) tiles.push_back(srow[is]);
+    if (cur > tkmax) {
+      tk_real = std::max(tk_real, srow[is] - tiles.back());
+      tiles.push_back(srow[is]);
+    }
   }
+  tk_real = std::max<int>(tk_real, (int)P->nnz2 - tiles.back());
   tiles.push_back((int)P->nnz2);
   P->n_tiles = (int)tiles.size() - 1;
-  P->tile_k = tkmax;
-  // chunks: consecutive thickness rows whose active sets fit in sc LDS slots
-  // and whose folded 1D coefficients (4 doubles per row pair and active slot)
-  // fit in qbudget bytes of LDS
+  P->tile_k = tk_real;
+  P->kron_threads = std::min(256, 64 * ((3 * tk_real + 63) / 64));
+  // chunks of consecutive thickness rows: the union of their active sets fits
+  // sc slots (register mode, LDS-set mode) and, in LDS mode, their
+  // coefficients fit qbudget bytes
   const int64_t q_per_zk = 4 * (int64_t)sizeof(double) * P->maxact;
-  std::vector<int> chunk_ptr(1, 0), chunk_sptr(1, 0), chunk_set, zaslot(zaset.size(), 0);
+  std::vector<int> chunk_ptr(1, 0), chunk_sptr(1, 0), chunk_set, zaslot(zaset.size(), 0), zchunk(P->nt, 0);
   {
     std::vector<int> cur;
     int start = 0;
     int64_t qbytes = 0;
+    const bool by_sets = reg_mode || lds_sets;
     auto flush = [&](int end) {
       std::sort(cur.begin(), cur.end());
-      for (int it = start; it < end; ++it)
+      for (int it = start; it < end; ++it) {
+        zchunk[it] = (int)chunk_ptr.size() - 1;
         for (int j = zaptr[it]; j < zaptr[it + 1]; ++j)
-          zaslot[j] = lds_mode ? (int)(std::lower_bound(cur.begin(), cur.end(), zaset[j]) - cur.begin()) : 0;
+          zaslot[j] = by_sets ? (int)(std::lower_bound(cur.begin(), cur.end(), zaset[j]) - cur.begin()) : 0;
+      }
       chunk_set.insert(chunk_set.end(), cur.begin(), cur.end());
       chunk_sptr.push_back((int)chunk_set.size());
       chunk_ptr.push_back(end);
@@ -475,32 +496,66 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
     for (int it = 0; it < P->nt; ++it) {
       int64_t qrow = q_per_zk * (zrow[it + 1] - zrow[it]);
       std::vector<int> uni = cur;
-      if (lds_mode)
+      if (by_sets)
         for (int j = zaptr[it]; j < zaptr[it + 1]; ++j)
           if (std::find(uni.begin(), uni.end(), zaset[j]) == uni.end()) uni.push_back(zaset[j]);
-      if (it > start && ((int)uni.size() > sc || qbytes + qrow > qbudget)) {
+      bool over = by_sets && (int)uni.size() > sc;
+      if (!reg_mode) over = over || qbytes + qrow > qbudget;
+      if (it > start && over) {
         flush(it);
         uni.clear();
-        if (lds_mode) uni.assign(zaset.begin() + zaptr[it], zaset.begin() + zaptr[it + 1]);
+        if (by_sets) uni.assign(zaset.begin() + zaptr[it], zaset.begin() + zaptr[it + 1]);
       }
       cur = uni;
       qbytes += qrow;
     }
     flush(P->nt);
   }
+  // enough blocks to keep every compute unit busy through the tail: split
+  // chunks into pieces of at most max_rows rows; a piece keeps its chunk's
+  // set list (and so the slots of zaslot)
+  {
+    int64_t target_blocks = 6144;
+    if (const char *e = std::getenv("LAMASM_KRON_BLOCKS")) target_blocks = std::max(1, std::atoi(e));
+    const int64_t per_tile = (target_blocks + P->n_tiles - 1) / P->n_tiles;
+    const int max_rows = (int)std::max<int64_t>(1, (P->nt + per_tile - 1) / per_tile);
+    std::vector<int> cp(1, 0), csp(1, 0), cs;
+    for (size_t c = 0; c + 1 < chunk_ptr.size(); ++c) {
+      const int a = chunk_ptr[c], b = chunk_ptr[c + 1];
+      const int pieces = (b - a + max_rows - 1) / max_rows;
+      for (int q = 0; q < pieces; ++q) {
+        const int e = a + (int)((int64_t)(b - a) * (q + 1) / pieces);
+        for (int it = cp.back(); it < e; ++it) zchunk[it] = (int)cp.size() - 1;
+        cp.push_back(e);
+        cs.insert(cs.end(), chunk_set.begin() + chunk_sptr[c], chunk_set.begin() + chunk_sptr[c + 1]);
+        csp.push_back((int)cs.size());
+      }
+    }
+    chunk_ptr.swap(cp);
+    chunk_sptr.swap(csp);
+    chunk_set.swap(cs);
+  }
   P->n_chunks = (int)chunk_ptr.size() - 1;
-  P->chunk_sets = sc;
-  // LDS: the chunk's folded 1D coefficients and its P slots
+  P->chunk_sets = lds_sets ? sc : 0;
   int max_chunk_zk = 0;
   for (int c = 0; c < P->n_chunks; ++c)
     max_chunk_zk = std::max(max_chunk_zk, zrow[chunk_ptr[c + 1]] - zrow[chunk_ptr[c]]);
-  P->kron_lzmax = lzmax;
-  P->kron_lds_q = 4 * (int64_t)sizeof(double) * P->maxact * max_chunk_zk;
-  P->kron_lds_p = per_k * tkmax * sc;
-  P->kron_lds = P->kron_lds_q + P->kron_lds_p + per_out * tkmax;
-  if (P->kron_lds > 160 * 1024) {
-    delete P;
-    return LAM_EUNSUP;  // one thickness row's coefficients exceed the LDS of a compute unit
+  if (reg_mode) {
+    P->kron_lds_q = 4 * (int64_t)sizeof(double) * P->kron_nsc * max_chunk_zk;
+    P->kron_lds_p = 0;
+    P->kron_lds = P->kron_lds_q;
+    if (P->kron_lds > 64 * 1024) {
+      delete P;
+      return LAM_EUNSUP;
+    }
+  } else {
+    P->kron_lds_q = 4 * (int64_t)sizeof(double) * P->maxact * max_chunk_zk;
+    P->kron_lds_p = per_k * tkmax * P->chunk_sets;
+    P->kron_lds = P->kron_lds_q + P->kron_lds_p;
+    if (P->kron_lds > 160 * 1024) {
+      delete P;
+      return LAM_EUNSUP;  // one thickness row's coefficients exceed the LDS of a compute unit
+    }
   }
 
   std::vector<int> plymat(d->ply_mat, d->ply_mat + d->n_ply);
@@ -537,6 +592,7 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
   L.ply_mat = B.take(sizeof(int) * plymat.size());
   L.ply_set = B.take(sizeof(int) * ply_set.size());
   L.tiles = B.take(sizeof(int) * tiles.size());
+  L.zchunk = B.take(sizeof(int) * zchunk.size());
   L.chunk_ptr = B.take(sizeof(int) * chunk_ptr.size());
   L.chunk_sptr = B.take(sizeof(int) * chunk_sptr.size());
   L.chunk_set = B.take(sizeof(int) * chunk_set.size());
@@ -545,7 +601,7 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
   L.D = B.take(sizeof(double) * 36 * P->n_sets);
   L.Ec = B.take(sizeof(double) * 81 * P->n_sets);
   L.P = B.take(sizeof(double) * 36 * (int64_t)P->n_sets * P->nnz2);
-  L.Qc = B.take(sizeof(double) * 4 * (int64_t)P->maxact * P->nnzz);
+  L.Qc = B.take(sizeof(double) * 4 * (int64_t)std::max(P->maxact, P->kron_nsc) * P->nnzz);
   L.M = B.take(sizeof(double) * 36 * P->nnz2);
   L.total = B.cur;
 
@@ -598,6 +654,7 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
   put(img, L.ply_mat, plymat);
   put(img, L.ply_set, ply_set);
   put(img, L.tiles, tiles);
+  put(img, L.zchunk, zchunk);
   put(img, L.chunk_ptr, chunk_ptr);
   put(img, L.chunk_sptr, chunk_sptr);
   put(img, L.chunk_set, chunk_set);
