@@ -145,6 +145,17 @@ LAM_API lam_status lam_adjoint(const lam_plan *plan, void *ws, int64_t ws_bytes,
                                const double *theta, const double *grad_vals, int64_t nnz, double *grad_C,
                                double *grad_theta, void *stream);
 
+/* Kernel timing for measurement.  While enabled, every device entry point
+ * records a pair of HIP events on its stream around its dominant kernel
+ * (the Kronecker scatter of lam_assemble, the element kernel of
+ * lam_assemble_standard, the streaming contraction of lam_adjoint); no work
+ * is added or skipped.  lam_profile_read waits for the recorded events and
+ * returns the summed milliseconds and the number of timed launches per entry
+ * point (index 0 assemble, 1 standard, 2 adjoint), then clears them.
+ * Up to 4096 launches are kept; later ones are not timed. */
+LAM_API lam_status lam_profile_enable(int32_t on);
+LAM_API lam_status lam_profile_read(double ms[3], int64_t launches[3]);
+
 LAM_API const char *lam_status_string(lam_status s);
 
 /* Library version, for diagnostics. */
