@@ -45,6 +45,9 @@ struct Dev {
   int64_t kron_lds_q, kron_lds_p;
   const int *zchunk;
   int kron_nsc;
+  const int *a1f, *a1c, *a2f, *a2c, *zs_first, *zs_cptr, *zs_cell;
+  int ne1, ne2, nzs;
+  double *Eply;
   // scratch
   double *D, *Ec, *P, *Qc, *M;
 };
@@ -87,6 +90,11 @@ Dev make_dev(const lam_plan *p, void *ws) {
   d.chunk_sets = p->chunk_sets;
   d.kron_lds_q = p->kron_lds_q;
   d.zchunk = at<int>(ws, L.zchunk);
+  d.a1f = at<int>(ws, L.a1f); d.a1c = at<int>(ws, L.a1c);
+  d.a2f = at<int>(ws, L.a2f); d.a2c = at<int>(ws, L.a2c);
+  d.zs_first = at<int>(ws, L.zs_first); d.zs_cptr = at<int>(ws, L.zs_cptr); d.zs_cell = at<int>(ws, L.zs_cell);
+  d.ne1 = p->ne1; d.ne2 = p->ne2; d.nzs = p->nzs;
+  d.Eply = at<double>(ws, L.Eply);
   d.kron_nsc = p->kron_nsc;
   d.kron_lds_p = p->kron_lds_p;
   d.D = at<double>(ws, L.D); d.Ec = at<double>(ws, L.Ec); d.P = at<double>(ws, L.P);
@@ -160,6 +168,23 @@ __device__ inline double bunit(int k, int I, int r) {
   }
 }
 
+// E[k][l][r][t] = sum_IJ B(e_k)[I][r] D[I][J] B(e_l)[J][t]: the 3x3 block
+// B(a)^T D B(b) of two gradients is sum_kl a_k b_l E[k][l].
+__device__ void bracket_coefficients(const double D[6][6], double *E) {
+  for (int k = 0; k < 3; ++k)
+    for (int l = 0; l < 3; ++l)
+      for (int r = 0; r < 3; ++r)
+        for (int t = 0; t < 3; ++t) {
+          double a = 0.0;
+          for (int I = 0; I < 6; ++I) {
+            double bi = bunit(k, I, r);
+            if (bi == 0.0) continue;
+            for (int J = 0; J < 6; ++J) a += bi * D[I][J] * bunit(l, J, t);
+          }
+          E[((k * 3 + l) * 3 + r) * 3 + t] = a;
+        }
+}
+
 // One thread per set.  Harmonic sets: the Fourier coefficient of D(phi)
 // sampled at NH equispaced angles (exact for trigonometric polynomials of
 // degree <= 4 once NH >= 9).
@@ -189,19 +214,16 @@ __global__ void k_rotate(Dev d, const double *__restrict__ C, const double *__re
   }
   for (int I = 0; I < 6; ++I)
     for (int J = 0; J < 6; ++J) d.D[36 * s + 6 * I + J] = D[I][J];
-  // E[k][l][r][t] = sum_IJ B(e_k)[I][r] D[I][J] B(e_l)[J][t]
-  for (int k = 0; k < 3; ++k)
-    for (int l = 0; l < 3; ++l)
-      for (int r = 0; r < 3; ++r)
-        for (int t = 0; t < 3; ++t) {
-          double a = 0.0;
-          for (int I = 0; I < 6; ++I) {
-            double bi = bunit(k, I, r);
-            if (bi == 0.0) continue;
-            for (int J = 0; J < 6; ++J) a += bi * D[I][J] * bunit(l, J, t);
-          }
-          d.Ec[81 * s + ((k * 3 + l) * 3 + r) * 3 + t] = a;
-        }
+  bracket_coefficients(D, d.Ec + 81 * s);
+}
+
+// Standard assembly: every ply's rotated tensor as bracket coefficients.
+__global__ void k_rotate_plies(Dev d, const double *__restrict__ C, const double *__restrict__ theta) {
+  int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= d.n_ply) return;
+  double D[6][6];
+  rotate_c(C + 36 * d.ply_mat[l], cos(theta[l]), sin(theta[l]), D);
+  bracket_coefficients(D, d.Eply + 81 * l);
 }
 
 // ---------------------------------------------------------------------------
@@ -514,6 +536,99 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron_reg(Dev d, const double *
   }
 }
 
+// ---------------------------------------------------------------------------
+// Standard 3D assembly (the comparator of the method, Sec. 2.4).  One block
+// per 3D element = (in-plane element e1, e2) x (thickness knot span), with all
+// the ply cells inside the span; elements of one colour
+// (e1 mod p1+1, e2 mod p2+1, span mod q+1) share no basis function, so a
+// launch per colour adds its element matrices into the CSR without atomics.
+// Per cell, the physical gradients of the (p1+1)(p2+1)(q+1) local functions
+// at the (ng1 ng2 ngz) Gauss points go to LDS; a thread per local pair (a, b)
+// accumulates the moments m_kl = sum_g w_g G_a(g)_k G_b(g)_l and, the ply's
+// tensor being constant in the cell, the block K_ab[r][t] += sum_kl m_kl E_l[kl][rt].
+constexpr int STD_THREADS = 256;
+
+__global__ void k_fill_zero(double *__restrict__ v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = 0.0;
+}
+
+__global__ void __launch_bounds__(STD_THREADS) k_std3d(Dev d, double *__restrict__ vals, int c1, int c2, int c3,
+                                                       int n1c, int n2c) {
+  extern __shared__ double sm[];
+  const int P1 = d.p1 + 1, P2 = d.p2 + 1, Q1 = d.q + 1;
+  const int nloc = P1 * P2 * Q1, ng = d.ng1 * d.ng2 * d.ngz;
+  double *G = sm;              // [ng][nloc][3]
+  double *W = sm + ng * nloc * 3;  // [ng]
+  const int b = blockIdx.x;
+  const int e1 = c1 + P1 * (b % n1c), e2 = c2 + P2 * ((b / n1c) % n2c), zsp = c3 + Q1 * (b / (n1c * n2c));
+  const int f1 = d.e1first[e1], f2 = d.e2first[e2], fz = d.zs_first[zsp];
+  const int npairs = nloc * nloc;
+  for (int p0 = 0; p0 < npairs; p0 += STD_THREADS) {
+    const int pair = p0 + (int)threadIdx.x;
+    const bool valid = pair < npairs;
+    const int la = valid ? pair / nloc : 0, lb = valid ? pair - la * nloc : 0;
+    double ke[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) ke[e] = 0.0;
+    for (int ci = d.zs_cptr[zsp]; ci < d.zs_cptr[zsp + 1]; ++ci) {
+      const int c = d.zs_cell[ci], ply = d.zply[c];
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < ng * nloc; idx += STD_THREADS) {
+        const int g = idx / nloc, a = idx - g * nloc;
+        const int g1 = g % d.ng1, g2 = (g / d.ng1) % d.ng2, gz = g / (d.ng1 * d.ng2);
+        const int a1 = a % P1, a2 = (a / P1) % P2, at = a / (P1 * P2);
+        const double *t1 = d.tab1 + (((int64_t)e1 * d.ng1 + g1) * P1 + a1) * 2;
+        const double *t2 = d.tab2 + (((int64_t)e2 * d.ng2 + g2) * P2 + a2) * 2;
+        const double *t3 = d.ztab + (((int64_t)c * d.ngz + gz) * Q1 + at) * 2;
+        const double gh[3] = {t1[1] * t2[0] * t3[0], t1[0] * t2[1] * t3[0], t1[0] * t2[0] * t3[1]};
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          G[(g * nloc + a) * 3 + k] = d.jit[k * 3 + 0] * gh[0] + d.jit[k * 3 + 1] * gh[1] + d.jit[k * 3 + 2] * gh[2];
+        if (a == 0)
+          W[g] = d.w1[(int64_t)e1 * d.ng1 + g1] * d.w2[(int64_t)e2 * d.ng2 + g2] * d.zw[(int64_t)c * d.ngz + gz] * d.detj;
+      }
+      __syncthreads();
+      if (valid) {
+        double m[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) m[e] = 0.0;
+        for (int g = 0; g < ng; ++g) {
+          const double w = W[g];
+          const double *ga = G + (g * nloc + la) * 3, *gb = G + (g * nloc + lb) * 3;
+          const double wa0 = w * ga[0], wa1 = w * ga[1], wa2 = w * ga[2];
+          const double b0 = gb[0], b1 = gb[1], b2 = gb[2];
+          m[0] += wa0 * b0; m[1] += wa0 * b1; m[2] += wa0 * b2;
+          m[3] += wa1 * b0; m[4] += wa1 * b1; m[5] += wa1 * b2;
+          m[6] += wa2 * b0; m[7] += wa2 * b1; m[8] += wa2 * b2;
+        }
+        const double *E = d.Eply + 81 * ply;
+#pragma unroll
+        for (int rt = 0; rt < 9; ++rt) {
+          double acc = 0.0;
+#pragma unroll
+          for (int kl = 0; kl < 9; ++kl) acc += m[kl] * E[kl * 9 + rt];
+          ke[rt] += acc;
+        }
+      }
+    }
+    if (valid) {
+      const int i1 = f1 + la % P1, i2 = f2 + (la / P1) % P2, it = fz + la / (P1 * P2);
+      const int j1 = f1 + lb % P1, j2 = f2 + (lb / P1) % P2, jt = fz + lb / (P1 * P2);
+      const int is = i1 + d.n1 * i2;
+      const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
+      const int sr = d.srow[is], Ls = d.srow[is + 1] - sr;
+      const int az = jt - d.zcol[zb];
+      const int bs = (j2 - d.a2f[i2]) * d.a1c[i1] + (j1 - d.a1f[i1]);
+      double *row = vals + 9 * d.nnz2 * (int64_t)zb + 3 * (int64_t)Lz * 3 * sr + (int64_t)az * 3 * Ls + 3 * bs;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int t = 0; t < 3; ++t) row[(int64_t)r * 3 * Lz * Ls + t] += ke[r * 3 + t];
+    }
+  }
+}
+
 __global__ void k_rowptr(Dev d, int64_t *__restrict__ rowptr) {
   int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (row > d.nrows) return;
@@ -626,8 +741,30 @@ extern "C" LAM_API lam_status lam_assemble(const lam_plan *p, void *ws, int64_t 
 
 extern "C" LAM_API lam_status lam_assemble_standard(const lam_plan *p, void *ws, int64_t ws_bytes, const double *C,
                                                     const double *theta, double *vals, int64_t nnz, void *stream) {
-  (void)p; (void)ws; (void)ws_bytes; (void)C; (void)theta; (void)vals; (void)nnz; (void)stream;
-  return LAM_EUNSUP;
+  lam_status st = check_ws(p, ws, ws_bytes);
+  if (st != LAM_OK) return st;
+  if (!C || !theta || !vals) return LAM_EINVAL;
+  if (nnz != p->nnz) return LAM_ESIZE;
+  const int P1 = p->p1 + 1, P2 = p->p2 + 1, Q1 = p->q + 1;
+  const int nloc = P1 * P2 * Q1, ng = p->ng1 * p->ng2 * p->ngz;
+  const size_t lds = sizeof(double) * ((size_t)ng * nloc * 3 + ng);
+  if (lds > 160 * 1024) return LAM_EUNSUP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Dev d = make_dev(p, ws);
+  void *prof = lam::profile_begin(1, stream);
+  hipLaunchKernelGGL(k_rotate_plies, dim3((p->n_ply + 63) / 64), dim3(64), 0, s, d, C, theta);
+  hipLaunchKernelGGL(k_fill_zero, dim3(4096), dim3(256), 0, s, vals, p->nnz);
+  for (int c3 = 0; c3 < Q1; ++c3)
+    for (int c2 = 0; c2 < P2; ++c2)
+      for (int c1 = 0; c1 < P1; ++c1) {
+        const int n1c = (p->ne1 - c1 + P1 - 1) / P1, n2c = (p->ne2 - c2 + P2 - 1) / P2;
+        const int n3c = (p->nzs - c3 + Q1 - 1) / Q1;
+        const int64_t nb = (int64_t)n1c * n2c * n3c;
+        if (nb <= 0) continue;
+        hipLaunchKernelGGL(k_std3d, dim3((unsigned)nb), dim3(STD_THREADS), lds, s, d, vals, c1, c2, c3, n1c, n2c);
+      }
+  lam::profile_end(prof, stream);
+  return hip_status();
 }
 
 extern "C" LAM_API lam_status lam_adjoint(const lam_plan *p, void *ws, int64_t ws_bytes, const double *C,

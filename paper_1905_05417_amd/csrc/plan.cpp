@@ -424,7 +424,7 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
     delete P;
     return LAM_EUNSUP;
   }
-  int nsc_cap = 4;
+  int nsc_cap = 2;  // fewer slots keep more waves resident; chunks reload P from cache
   if (const char *e = std::getenv("LAMASM_KRON_NSC")) nsc_cap = std::max(1, std::atoi(e));
   const bool reg_mode = P->maxact <= 8;
   int sc, tkmax = tk_target;
@@ -558,6 +558,22 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
     }
   }
 
+  // ---- standard assembly: 1D overlap ranges, thickness spans and their cells
+  std::vector<int> a1f(d1.adj_first), a1c(d1.adj_cnt), a2f(d2.adj_first), a2c(d2.adj_cnt);
+  std::vector<int> zs_first, zs_cptr(1, 0), zs_cell;
+  for (int s3 : zs.span) {
+    zs_first.push_back(s3 - d->q);
+    for (int c = 0; c < P->nzc; ++c)
+      if (zfirst[c] == s3 - d->q) zs_cell.push_back(c);
+    zs_cptr.push_back((int)zs_cell.size());
+  }
+  P->nzs = (int)zs.span.size();
+  {
+    int mx = 0;
+    for (int z = 0; z < P->nzs; ++z) mx = std::max(mx, zs_cptr[z + 1] - zs_cptr[z]);
+    P->max_span_cells = mx;
+  }
+
   std::vector<int> plymat(d->ply_mat, d->ply_mat + d->n_ply);
 
   // ---- layout
@@ -587,6 +603,13 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
   L.zcell = B.take(sizeof(int) * zcell.size());
   L.zaptr = B.take(sizeof(int) * zaptr.size());
   L.zaset = B.take(sizeof(int) * zaset.size());
+  L.a1f = B.take(sizeof(int) * a1f.size());
+  L.a1c = B.take(sizeof(int) * a1c.size());
+  L.a2f = B.take(sizeof(int) * a2f.size());
+  L.a2c = B.take(sizeof(int) * a2c.size());
+  L.zs_first = B.take(sizeof(int) * zs_first.size());
+  L.zs_cptr = B.take(sizeof(int) * zs_cptr.size());
+  L.zs_cell = B.take(sizeof(int) * zs_cell.size());
   L.set_mat = B.take(sizeof(int) * set_mat.size());
   L.set_aux = B.take(sizeof(int) * set_aux.size());
   L.ply_mat = B.take(sizeof(int) * plymat.size());
@@ -603,6 +626,7 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
   L.P = B.take(sizeof(double) * 36 * (int64_t)P->n_sets * P->nnz2);
   L.Qc = B.take(sizeof(double) * 4 * (int64_t)std::max(P->maxact, P->kron_nsc) * P->nnzz);
   L.M = B.take(sizeof(double) * 36 * P->nnz2);
+  L.Eply = B.take(sizeof(double) * 81 * P->n_ply);
   L.total = B.cur;
 
   P->image.assign(L.const_bytes, 0);
@@ -649,6 +673,13 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
   put(img, L.zcell, zcell);
   put(img, L.zaptr, zaptr);
   put(img, L.zaset, zaset);
+  put(img, L.a1f, a1f);
+  put(img, L.a1c, a1c);
+  put(img, L.a2f, a2f);
+  put(img, L.a2c, a2c);
+  put(img, L.zs_first, zs_first);
+  put(img, L.zs_cptr, zs_cptr);
+  put(img, L.zs_cell, zs_cell);
   put(img, L.set_mat, set_mat);
   put(img, L.set_aux, set_aux);
   put(img, L.ply_mat, plymat);
