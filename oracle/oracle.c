@@ -878,3 +878,61 @@ int or_Q_pair(const or_problem *P, int ply, int it, int jt, double *Qout) {
   ctx_free(&c);
   return 0;
 }
+
+/* For L = u^T K u (G = u u^T), dL/dD_l = int_{ply l} eps(u) eps(u)^T |DF| dxi,
+ * eps(u) = sum_a B_a u_a the Voigt strain of the discrete field (eq. Km_0 is
+ * linear in D_l).  u holds 3 values per global function (DOF order). */
+int or_grad_uu(const or_problem *P, const double *u, double *dLdD, int nthreads) {
+  ctx c;
+  if (ctx_init(&c, P)) { ctx_free(&c); return -1; }
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+  const int nloc = (P->p1 + 1) * (P->p2 + 1) * (P->q + 1);
+  const int ncell_max = column_cells(&c, c.sp1[0], c.sp2[0], NULL, NULL);
+  const size_t per = 36 * (size_t)P->n_ply;
+  double *part = (double *)calloc((size_t)c.ns2 * per, sizeof(double));
+#pragma omp parallel
+  {
+    double (*grad)[3] = (double (*)[3])malloc(sizeof(double) * 3 * nloc);
+    cell_t *cells = (cell_t *)malloc(sizeof(cell_t) * (size_t)(ncell_max > 0 ? ncell_max : 1));
+    int *plies = (int *)malloc(sizeof(int) * (size_t)(ncell_max > 0 ? ncell_max : 1));
+#pragma omp for schedule(dynamic, 1)
+    for (int z2 = 0; z2 < c.ns2; ++z2) {
+      int s2 = c.sp2[z2];
+      double *acc = part + (size_t)z2 * per;
+      for (int z1 = 0; z1 < c.ns1; ++z1) {
+        int s1 = c.sp1[z1];
+        int ncell = column_cells(&c, s1, s2, cells, plies);
+        for (int ic = 0; ic < ncell; ++ic) {
+          const cell_t *cl = &cells[ic];
+          double *dD = acc + 36 * (size_t)plies[ic];
+          for (int g3 = 0; g3 < c.P.ngz; ++g3)
+            for (int g2 = 0; g2 < c.P.ng2; ++g2)
+              for (int g1 = 0; g1 < c.P.ng1; ++g1) {
+                double w = cell_point(&c, cl, g1, g2, g3, grad);
+                double eps[6] = {0, 0, 0, 0, 0, 0};
+                for (int a = 0; a < nloc; ++a) {
+                  double B[6][3];
+                  bmat(grad[a], B);
+                  int64_t gi = local_to_global(&c, cl, a);
+                  for (int I = 0; I < 6; ++I)
+                    for (int r = 0; r < 3; ++r) eps[I] += B[I][r] * u[3 * gi + r];
+                }
+                for (int I = 0; I < 6; ++I)
+                  for (int J = 0; J < 6; ++J) dD[I * 6 + J] += w * eps[I] * eps[J];
+              }
+        }
+      }
+    }
+    free(grad); free(cells); free(plies);
+  }
+  for (size_t e = 0; e < per; ++e) dLdD[e] = 0.0;
+  for (int z2 = 0; z2 < c.ns2; ++z2)
+    for (size_t e = 0; e < per; ++e) dLdD[e] += part[(size_t)z2 * per + e];
+  free(part);
+  ctx_free(&c);
+  return 0;
+}

@@ -73,6 +73,7 @@ def lib():
         L.or_assemble_rows.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int64, _i64p, _i64p, _i32p, _dp,
                                        ctypes.c_int]
         L.or_grad_D.argtypes = [ctypes.POINTER(_Problem), _i64p, _i32p, _dp, _dp, ctypes.c_int]
+        L.or_grad_uu.argtypes = [ctypes.POINTER(_Problem), _dp, _dp, ctypes.c_int]
         L.or_grad_material.argtypes = [ctypes.c_int32, _i32p, _dp, ctypes.c_int32, _dp, _dp, _dp, _dp]
         L.or_P_pair.argtypes = [ctypes.POINTER(_Problem), _dp, ctypes.c_int, ctypes.c_int, _dp]
         L.or_Q_pair.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
@@ -211,6 +212,15 @@ def grad_D(lam, rowptr, colind, G, nthreads=0):
     G = np.ascontiguousarray(G, dtype=np.float64)
     out = np.zeros(36 * len(b.theta))
     _check(lib().or_grad_D(b.ref(), _p(rowptr, _i64p), _p(colind, _i32p), _p(G), _p(out), int(nthreads)), "grad_D")
+    return out.reshape(-1, 6, 6)
+
+
+def grad_D_uu(lam, u, nthreads=0):
+    """dL/dD_l (n_ply, 6, 6) for L = u^T K u, without forming G or K."""
+    b = _Bound(lam)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(36 * len(b.theta))
+    _check(lib().or_grad_uu(b.ref(), _p(u), _p(out), int(nthreads)), "grad_uu")
     return out.reshape(-1, 6, 6)
 
 

@@ -38,6 +38,8 @@ struct Layout {
   // standard assembly: first overlapping function and overlap count per 1D
   // function, first function of every nonzero thickness span, the cells of each span
   Region a1f, a1c, a2f, a2c, zs_first, zs_cptr, zs_cell;
+  // adjoint: ply of each accumulator slot per thickness row, slots finished after each row
+  Region rowply, rowfin;
   // sets: material and (bucket) representative ply or (harmonic) harmonic index
   Region set_mat, set_aux, ply_mat, ply_set;
   // Kronecker scatter: tiles of whole in-plane rows (first in-plane nonzero
@@ -47,7 +49,7 @@ struct Layout {
   Region tiles, chunk_ptr, chunk_sptr, chunk_set, zaslot, zchunk;
   int64_t const_bytes = 0;  // end of the constant part
   // scratch
-  Region D, Ec, P, Qc, M, Eply;
+  Region D, Ec, P, Qc, M, Eply, Qp, adj_part, adj_y, adj_dD;
   int64_t total = 0;
 };
 
@@ -64,6 +66,7 @@ struct lam_plan {
   int n1 = 0, n2 = 0, nt = 0, ns = 0;
   int ne1 = 0, ne2 = 0, nzc = 0;  // in-plane elements per direction, thickness cells
   int nzs = 0, max_span_cells = 0; // nonzero thickness knot spans, most cells in one span
+  int adj_ok = 0;                   // every thickness pair touches at most two plies (adjoint supported)
   int ng1 = 0, ng2 = 0, ngz = 0;
   int n_ply = 0, n_mat = 0, n_sets = 0, set_mode = 0, n_harm = 0, maxact = 0;
   int64_t nnz1 = 0, nnz2 = 0, nnzz = 0, nnz = 0, nrows = 0;

@@ -48,6 +48,8 @@ struct Dev {
   const int *a1f, *a1c, *a2f, *a2c, *zs_first, *zs_cptr, *zs_cell;
   int ne1, ne2, nzs;
   double *Eply;
+  const int *rowply, *rowfin;
+  double *Qp, *adj_part, *adj_y, *adj_dD;
   // scratch
   double *D, *Ec, *P, *Qc, *M;
 };
@@ -95,6 +97,9 @@ Dev make_dev(const lam_plan *p, void *ws) {
   d.zs_first = at<int>(ws, L.zs_first); d.zs_cptr = at<int>(ws, L.zs_cptr); d.zs_cell = at<int>(ws, L.zs_cell);
   d.ne1 = p->ne1; d.ne2 = p->ne2; d.nzs = p->nzs;
   d.Eply = at<double>(ws, L.Eply);
+  d.rowply = at<int>(ws, L.rowply); d.rowfin = at<int>(ws, L.rowfin);
+  d.Qp = at<double>(ws, L.Qp); d.adj_part = at<double>(ws, L.adj_part);
+  d.adj_y = at<double>(ws, L.adj_y); d.adj_dD = at<double>(ws, L.adj_dD);
   d.kron_nsc = p->kron_nsc;
   d.kron_lds_p = p->kron_lds_p;
   d.D = at<double>(ws, L.D); d.Ec = at<double>(ws, L.Ec); d.P = at<double>(ws, L.P);
@@ -235,7 +240,7 @@ __global__ void k_rotate_plies(Dev d, const double *__restrict__ C, const double
 // into M_ab[k][l] = int (G_a^i)_k (G_b^j)_l |DF|.  Because each set's
 // material is constant over the plane, P_{s,ab}[r][t] = sum_kl M_ab[k][l] E_s[k][l][r][t].
 __global__ void __launch_bounds__(256) k_p2d(Dev d, const double *__restrict__ Ec, double *__restrict__ Pt,
-                                             double *__restrict__ Mt) {
+                                             double *__restrict__ Mt, int write_p) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= d.nnz2) return;
   const int is = d.krow[k], js = d.kcol[k];
@@ -300,7 +305,7 @@ __global__ void __launch_bounds__(256) k_p2d(Dev d, const double *__restrict__ E
   for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
     for (int e = 0; e < 9; ++e) Mt[(int64_t)(ab * 9 + e) * d.nnz2 + k] = M[ab][e / 3][e % 3];
-  for (int s = 0; s < d.n_sets; ++s) {
+  for (int s = 0; s < (write_p ? d.n_sets : 0); ++s) {
     const double *E = Ec + 81 * s;
     double *Po = Pt + (int64_t)s * 36 * d.nnz2 + k;
 #pragma unroll
@@ -629,6 +634,196 @@ __global__ void __launch_bounds__(STD_THREADS) k_std3d(Dev d, double *__restrict
   }
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint.  K is linear in every ply's rotated tensor D_l (eq. Km_0); with the
+// split of Sec. 3 written per ply, K = sum_l sum_ab Q_{l,ab} (x) P_ab[D_l] and
+// P_ab[D][k][rt] = sum_kl M_ab[k][kl] E[D][kl][rt] (moments M of k_p2d,
+// bracket coefficients E of D), so for L = <G, vals>
+//   dL/dE_l[kl][rt] = Y_l[kl][rt] = sum_k sum_ab M_ab[k][kl] Z_{l,ab}[k][rt],
+//   Z_{l,ab}[k][rt] = sum_zk Q_{l,ab}[zk] G[zk, k, r, t],
+// and dL/dD_l[I][J] sums Y_l over the (k,r) with Voigt index I and (l,t) with J.
+// dK is never formed: G is streamed once in the scatter's order.
+
+// Per-ply 1D operators by accumulator slot (ply & 1): Qp[zk][slot][ab].
+__global__ void k_q1d_ply(Dev d) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 2 * d.nnzz) return;
+  const int zk = (int)(idx >> 1), slot = (int)(idx & 1);
+  const int it = d.zkrow[zk], jt = d.zcol[zk], Q1 = d.q + 1;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int ci = d.zcptr[zk]; ci < d.zcptr[zk + 1]; ++ci) {
+    const int c = d.zcell[ci];
+    if ((d.zply[c] & 1) != slot) continue;
+    const int ai = it - d.zfirst[c], aj = jt - d.zfirst[c];
+    for (int g = 0; g < d.ngz; ++g) {
+      const double *t = d.ztab + ((int64_t)c * d.ngz + g) * Q1 * 2;
+      const double Ti = t[2 * ai], dTi = t[2 * ai + 1], Tj = t[2 * aj], dTj = t[2 * aj + 1];
+      const double w = d.zw[(int64_t)c * d.ngz + g];
+      acc[0] += w * Ti * Tj;
+      acc[1] += w * Ti * dTj;
+      acc[2] += w * dTi * Tj;
+      acc[3] += w * dTi * dTj;
+    }
+  }
+  double *o = d.Qp + 4 * idx;
+  o[0] = acc[0];
+  o[1] = acc[1];
+  o[2] = acc[2];
+  o[3] = acc[3];
+}
+
+// One block per scatter tile (whole in-plane rows), one thread per
+// (in-plane nonzero k, component t).  Thickness rows are streamed in order;
+// Z of the (at most two) plies a row touches accumulates in registers; when
+// a ply's last row is done the block contracts Z with its moments and sums
+// over its nonzeros in LDS: adj_part[tile][ply][kl][rt].
+constexpr int ADJ_THREADS = 256;
+
+__global__ void __launch_bounds__(ADJ_THREADS) k_adj_stream(Dev d, const double *__restrict__ G,
+                                                            const double *__restrict__ qp) {
+  __shared__ double red[ADJ_THREADS * 27];
+  const int tile = blockIdx.x;
+  const int k0 = d.tiles[tile], tk = d.tiles[tile + 1] - k0;
+  const int sig = threadIdx.x;
+  const bool act = sig < 3 * tk;
+  const int kk = act ? sig / 3 : 0, t = act ? sig - 3 * kk : 0, k = k0 + kk;
+  const int is = d.krow[k], sr = d.srow[is];
+  const int Ls = d.srow[is + 1] - sr, off = 3 * (k - sr) + t;
+  double m[4][9];
+#pragma unroll
+  for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+    for (int kl = 0; kl < 9; ++kl) m[ab][kl] = act ? d.M[(int64_t)(ab * 9 + kl) * d.nnz2 + k] : 0.0;
+  double z[2][4][3];
+#pragma unroll
+  for (int sl = 0; sl < 2; ++sl)
+#pragma unroll
+    for (int ab = 0; ab < 4; ++ab) z[sl][ab][0] = z[sl][ab][1] = z[sl][ab][2] = 0.0;
+  const int64_t astride = 3 * (int64_t)Ls;
+  for (int it = 0; it < d.nt; ++it) {
+    const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
+    if (act) {
+      const double *row = G + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
+      const int64_t rstride = 3 * (int64_t)Lz * Ls;
+      for (int a = 0; a < Lz; ++a) {
+        const double g0 = row[(int64_t)a * astride], g1 = row[rstride + (int64_t)a * astride],
+                     g2 = row[2 * rstride + (int64_t)a * astride];
+        const double *q = qp + 8 * (int64_t)(zb + a);
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl)
+#pragma unroll
+          for (int ab = 0; ab < 4; ++ab) {
+            const double qq = q[4 * sl + ab];
+            z[sl][ab][0] += qq * g0;
+            z[sl][ab][1] += qq * g1;
+            z[sl][ab][2] += qq * g2;
+          }
+      }
+    }
+    const int fin = d.rowfin[it];
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      if (!(fin & (1 << sl))) continue;
+      const int ply = d.rowply[2 * it + sl];
+      // Y[kl][r] for this thread's t, into LDS
+#pragma unroll
+      for (int kl = 0; kl < 9; ++kl)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+          red[sig * 27 + kl * 3 + r] =
+              m[0][kl] * z[sl][0][r] + m[1][kl] * z[sl][1][r] + m[2][kl] * z[sl][2][r] + m[3][kl] * z[sl][3][r];
+#pragma unroll
+      for (int ab = 0; ab < 4; ++ab) z[sl][ab][0] = z[sl][ab][1] = z[sl][ab][2] = 0.0;
+      __syncthreads();
+      if (sig < 81) {
+        const int kl = sig / 9, r = (sig / 3) % 3, tt = sig % 3;
+        double acc = 0.0;
+        for (int q2 = 0; q2 < tk; ++q2) acc += red[(3 * q2 + tt) * 27 + kl * 3 + r];
+        d.adj_part[((int64_t)tile * d.n_ply + ply) * 81 + sig] = acc;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Sum of the tile partials per ply, in tile order (deterministic).
+__global__ void k_adj_reduce(Dev d) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 81 * d.n_ply) return;
+  const int ply = idx / 81, e = idx % 81;
+  double acc = 0.0;
+  for (int tile = 0; tile < d.n_tiles; ++tile) acc += d.adj_part[((int64_t)tile * d.n_ply + ply) * 81 + e];
+  d.adj_y[idx] = acc;
+}
+
+__device__ inline int voigt_pair(int i, int j) {
+  if (i == j) return i;
+  const int a = i < j ? i : j, b = i < j ? j : i;
+  return a == 0 ? (b == 1 ? 3 : 4) : 5;
+}
+
+// dT/dtheta of the Voigt stress transformation (product rule on the two R factors).
+__device__ void voigt_rotation_dtheta(double c, double s, double T[6][6]) {
+  const double R[3][3] = {{c, -s, 0.0}, {s, c, 0.0}, {0.0, 0.0, 1.0}};
+  const double dR[3][3] = {{-s, -c, 0.0}, {c, -s, 0.0}, {0.0, 0.0, 0.0}};
+  for (int I = 0; I < 6; ++I)
+    for (int J = 0; J < 6; ++J) {
+      int i = kVi[I], j = kVj[I], k = kVi[J], l = kVj[J];
+      double t = dR[i][k] * R[j][l] + R[i][k] * dR[j][l];
+      if (k != l) t += dR[i][l] * R[j][k] + R[i][l] * dR[j][k];
+      T[I][J] = t;
+    }
+}
+
+// Per ply: dL/dD_l from Y_l, and dL/dtheta_l = <dL/dD_l, dT C T^T + T C dT^T>.
+__global__ void k_adj_ply(Dev d, const double *__restrict__ C, const double *__restrict__ theta,
+                          double *__restrict__ grad_theta) {
+  int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= d.n_ply) return;
+  const double *Y = d.adj_y + 81 * l;
+  double dD[6][6];
+  for (int I = 0; I < 6; ++I)
+    for (int J = 0; J < 6; ++J) dD[I][J] = 0.0;
+  for (int k = 0; k < 3; ++k)
+    for (int m = 0; m < 3; ++m)
+      for (int r = 0; r < 3; ++r)
+        for (int t = 0; t < 3; ++t) dD[voigt_pair(k, r)][voigt_pair(m, t)] += Y[(k * 3 + m) * 9 + r * 3 + t];
+  for (int I = 0; I < 6; ++I)
+    for (int J = 0; J < 6; ++J) d.adj_dD[36 * l + 6 * I + J] = dD[I][J];
+  const double c = cos(theta[l]), s = sin(theta[l]);
+  double T[6][6], dT[6][6];
+  voigt_rotation(c, s, T);
+  voigt_rotation_dtheta(c, s, dT);
+  const double *Cm = C + 36 * d.ply_mat[l];
+  // g = sum_IJ dD[I][J] (dT C T^T + T C dT^T)[I][J]
+  double g = 0.0;
+  for (int I = 0; I < 6; ++I)
+    for (int J = 0; J < 6; ++J) {
+      double a = 0.0;
+      for (int K = 0; K < 6; ++K)
+        for (int L = 0; L < 6; ++L) a += (dT[I][K] * T[J][L] + T[I][K] * dT[J][L]) * Cm[K * 6 + L];
+      g += dD[I][J] * a;
+    }
+  grad_theta[l] = g;
+}
+
+// dL/dC_m[A][B] = sum over the plies of material m (in order) of (T_l^T dL/dD_l T_l)[A][B].
+__global__ void k_adj_mat(Dev d, const double *__restrict__ theta, double *__restrict__ grad_C) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 36 * d.n_mat) return;
+  const int mt = idx / 36, A = (idx % 36) / 6, B = idx % 6;
+  double acc = 0.0;
+  for (int l = 0; l < d.n_ply; ++l) {
+    if (d.ply_mat[l] != mt) continue;
+    double T[6][6];
+    voigt_rotation(cos(theta[l]), sin(theta[l]), T);
+    const double *dD = d.adj_dD + 36 * l;
+    for (int I = 0; I < 6; ++I)
+      for (int J = 0; J < 6; ++J) acc += T[I][A] * dD[6 * I + J] * T[J][B];
+  }
+  grad_C[idx] = acc;
+}
+
 __global__ void k_rowptr(Dev d, int64_t *__restrict__ rowptr) {
   int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (row > d.nrows) return;
@@ -730,7 +925,7 @@ extern "C" LAM_API lam_status lam_assemble(const lam_plan *p, void *ws, int64_t 
   hipStream_t s = static_cast<hipStream_t>(stream);
   Dev d = make_dev(p, ws);
   hipLaunchKernelGGL(k_rotate, dim3((p->n_sets + 63) / 64), dim3(64), 0, s, d, C, theta);
-  hipLaunchKernelGGL(k_p2d, dim3((unsigned)((p->nnz2 + 255) / 256)), dim3(256), 0, s, d, d.Ec, d.P, d.M);
+  hipLaunchKernelGGL(k_p2d, dim3((unsigned)((p->nnz2 + 255) / 256)), dim3(256), 0, s, d, d.Ec, d.P, d.M, 1);
   int64_t nq = p->nnzz * (p->kron_nsc > 0 ? p->kron_nsc : p->maxact);
   hipLaunchKernelGGL(k_q1d, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, d, theta);
   void *prof = lam::profile_begin(0, stream);
@@ -770,7 +965,20 @@ extern "C" LAM_API lam_status lam_assemble_standard(const lam_plan *p, void *ws,
 extern "C" LAM_API lam_status lam_adjoint(const lam_plan *p, void *ws, int64_t ws_bytes, const double *C,
                                           const double *theta, const double *grad_vals, int64_t nnz, double *grad_C,
                                           double *grad_theta, void *stream) {
-  (void)p; (void)ws; (void)ws_bytes; (void)C; (void)theta; (void)grad_vals; (void)nnz; (void)grad_C;
-  (void)grad_theta; (void)stream;
-  return LAM_EUNSUP;
+  lam_status st = check_ws(p, ws, ws_bytes);
+  if (st != LAM_OK) return st;
+  if (!C || !theta || !grad_vals || !grad_C || !grad_theta) return LAM_EINVAL;
+  if (nnz != p->nnz) return LAM_ESIZE;
+  if (!p->adj_ok || 3 * p->tile_k > ADJ_THREADS) return LAM_EUNSUP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Dev d = make_dev(p, ws);
+  hipLaunchKernelGGL(k_p2d, dim3((unsigned)((p->nnz2 + 255) / 256)), dim3(256), 0, s, d, d.Ec, d.P, d.M, 0);
+  hipLaunchKernelGGL(k_q1d_ply, dim3((unsigned)((2 * p->nnzz + 255) / 256)), dim3(256), 0, s, d);
+  void *prof = lam::profile_begin(2, stream);
+  hipLaunchKernelGGL(k_adj_stream, dim3(p->n_tiles), dim3(ADJ_THREADS), 0, s, d, grad_vals, d.Qp);
+  lam::profile_end(prof, stream);
+  hipLaunchKernelGGL(k_adj_reduce, dim3((81 * p->n_ply + 255) / 256), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_adj_ply, dim3((p->n_ply + 63) / 64), dim3(64), 0, s, d, C, theta, grad_theta);
+  hipLaunchKernelGGL(k_adj_mat, dim3((36 * p->n_mat + 63) / 64), dim3(64), 0, s, d, theta, grad_C);
+  return hip_status();
 }

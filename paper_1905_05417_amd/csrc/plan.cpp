@@ -574,6 +574,33 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
     P->max_span_cells = mx;
   }
 
+  // ---- adjoint: every thickness pair touches at most two plies, kept in
+  // accumulator slot (ply & 1); a ply's accumulators are reduced after the last
+  // thickness row that touches it
+  std::vector<int> rowply(2 * (size_t)P->nt, -1), rowfin(P->nt, 0), last_row(d->n_ply, -1);
+  P->adj_ok = 1;
+  for (int it = 0; it < P->nt; ++it)
+    for (int zk = zrow[it]; zk < zrow[it + 1]; ++zk)
+      for (int ci = zcptr[zk]; ci < zcptr[zk + 1]; ++ci) {
+        const int l = zply[zcell[ci]], slot = l & 1;
+        if (rowply[2 * it + slot] >= 0 && rowply[2 * it + slot] != l) P->adj_ok = 0;
+        rowply[2 * it + slot] = l;
+        last_row[l] = std::max(last_row[l], it);
+      }
+  std::vector<int> first_row(d->n_ply, -1);
+  for (int it = P->nt - 1; it >= 0; --it)
+    for (int sl = 0; sl < 2; ++sl)
+      if (rowply[2 * it + sl] >= 0) first_row[rowply[2 * it + sl]] = it;
+  for (int l = 0; l < d->n_ply; ++l) {
+    if (last_row[l] < 0) continue;
+    rowfin[last_row[l]] |= 1 << (l & 1);
+    // while ply l accumulates, no other ply may use its slot
+    for (int it = first_row[l]; it <= last_row[l]; ++it) {
+      const int o = rowply[2 * it + (l & 1)];
+      if (o >= 0 && o != l) P->adj_ok = 0;
+    }
+  }
+
   std::vector<int> plymat(d->ply_mat, d->ply_mat + d->n_ply);
 
   // ---- layout
@@ -610,6 +637,8 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
   L.zs_first = B.take(sizeof(int) * zs_first.size());
   L.zs_cptr = B.take(sizeof(int) * zs_cptr.size());
   L.zs_cell = B.take(sizeof(int) * zs_cell.size());
+  L.rowply = B.take(sizeof(int) * rowply.size());
+  L.rowfin = B.take(sizeof(int) * rowfin.size());
   L.set_mat = B.take(sizeof(int) * set_mat.size());
   L.set_aux = B.take(sizeof(int) * set_aux.size());
   L.ply_mat = B.take(sizeof(int) * plymat.size());
@@ -627,6 +656,12 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
   L.Qc = B.take(sizeof(double) * 4 * (int64_t)std::max(P->maxact, P->kron_nsc) * P->nnzz);
   L.M = B.take(sizeof(double) * 36 * P->nnz2);
   L.Eply = B.take(sizeof(double) * 81 * P->n_ply);
+  // adjoint scratch: per-ply 1D operators by slot, per (tile, ply) partial sums,
+  // per-ply totals and dL/dD_l
+  L.Qp = B.take(sizeof(double) * 8 * P->nnzz);
+  L.adj_part = B.take(sizeof(double) * 81 * (int64_t)P->n_tiles * P->n_ply);
+  L.adj_y = B.take(sizeof(double) * 81 * P->n_ply);
+  L.adj_dD = B.take(sizeof(double) * 36 * P->n_ply);
   L.total = B.cur;
 
   P->image.assign(L.const_bytes, 0);
@@ -680,6 +715,8 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
   put(img, L.zs_first, zs_first);
   put(img, L.zs_cptr, zs_cptr);
   put(img, L.zs_cell, zs_cell);
+  put(img, L.rowply, rowply);
+  put(img, L.rowfin, rowfin);
   put(img, L.set_mat, set_mat);
   put(img, L.set_aux, set_aux);
   put(img, L.ply_mat, plymat);

@@ -1,0 +1,140 @@
+"""GPU adjoint (dL/dC per material, dL/dtheta per ply) against the CPU oracle's
+gradient, central finite differences of the GPU forward, and autograd.
+
+Bar: relative error <= 1e-7 (the adjoint is exact; expected ~1e-12), measured
+as max abs error over the gradient's max abs entry.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1905_05417_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-7
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1905_05417_amd import lamasm
+    lamasm.lib()
+    return lamasm
+
+
+def _mats(lam):
+    return (torch.tensor(np.asarray(lam.C, dtype=np.float64), device="cuda"),
+            torch.tensor(np.asarray(lam.theta, dtype=np.float64), device="cuda"))
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_adjoint_matches_oracle_gradient(oracle, L, case):
+    rng = np.random.default_rng(5000 + case)
+    if case == 0:
+        lam = W.config_q1_8x8()
+    else:
+        lam = W.random_small(rng, max_ply=5, n_mat=2)
+    mode = "bucket" if case % 2 == 0 else "harmonic9"
+    print("case", case, mode, lam.p1, lam.p2, lam.q, lam.n_ply, flush=True)
+    pat = oracle.pattern(lam)
+    G = rng.standard_normal(len(pat[1]))
+    gC_ref, gT_ref = oracle.grad(lam, G, pattern_=pat)
+    plan = L.Plan(lam, set_mode=mode)
+    C, th = _mats(lam)
+    gC, gT = plan.adjoint(C, th, torch.tensor(G, device="cuda"))
+    eC, eT = _rel(gC.cpu().numpy(), gC_ref), _rel(gT.cpu().numpy(), gT_ref)
+    print("  dC rel %.3e  dtheta rel %.3e" % (eC, eT), flush=True)
+    assert eC <= 1e-10 and eT <= 1e-10
+
+
+def test_autograd_function(oracle, L):
+    rng = np.random.default_rng(42)
+    lam = W.random_small(rng, max_ply=4, n_mat=2)
+    pat = oracle.pattern(lam)
+    G = rng.standard_normal(len(pat[1]))
+    gC_ref, gT_ref = oracle.grad(lam, G, pattern_=pat)
+    plan = L.Plan(lam, set_mode="harmonic9")
+    C, th = _mats(lam)
+    C.requires_grad_(True)
+    th.requires_grad_(True)
+    vals = L.assemble(plan, C, th)
+    loss = (vals * torch.tensor(G, device="cuda")).sum()
+    loss.backward()
+    assert _rel(C.grad.cpu().numpy(), gC_ref) <= 1e-10
+    assert _rel(th.grad.cpu().numpy(), gT_ref) <= 1e-10
+
+
+def _quad(plan, vals, rowptr, colind, u):
+    """u^T K u from CSR values on the GPU (float64)."""
+    rows = torch.repeat_interleave(torch.arange(plan.n_rows, device="cuda"), rowptr[1:] - rowptr[:-1])
+    return float((u[rows] * vals * u[colind.long()]).sum())
+
+
+def test_adjoint_vs_central_differences(L):
+    """Per-ply angle and a few moduli, h = 1e-6 (angles in radians; moduli
+    relative), L = u^T K u with the GPU forward in harmonic mode (exact for
+    any per-ply angle)."""
+    rng = np.random.default_rng(77)
+    lam = W.plate(2, 10, 2, list(rng.uniform(0, 180, 6)), [W.material(W.CARBON), W.material(W.GLASS)],
+                  [0, 1, 1, 0, 1, 0], ne2=8, name="fd")
+    plan = L.Plan(lam, set_mode="harmonic9")
+    rowptr, colind = plan.pattern()
+    C, th = _mats(lam)
+    u = torch.tensor(rng.standard_normal(plan.n_rows), device="cuda")
+    rows = torch.repeat_interleave(torch.arange(plan.n_rows, device="cuda"), rowptr[1:] - rowptr[:-1])
+    G = u[rows] * u[colind.long()]
+    gC, gT = plan.adjoint(C, th, G)
+    gC, gT = gC.cpu().numpy(), gT.cpu().numpy()
+    h = 1e-6
+    worst = 0.0
+    for l in range(lam.n_ply):
+        tp, tm = th.clone(), th.clone()
+        tp[l] += h
+        tm[l] -= h
+        fd = (_quad(plan, plan.assemble(C, tp), rowptr, colind, u) -
+              _quad(plan, plan.assemble(C, tm), rowptr, colind, u)) / (2 * h)
+        worst = max(worst, abs(fd - gT[l]) / np.abs(gT).max())
+    for (m, a, b) in [(0, 0, 0), (1, 1, 1), (0, 3, 3), (1, 4, 5), (0, 0, 2)]:
+        hc = 1e-6 * max(abs(float(C[m, a, b])), 1.0)
+        cp, cm = C.clone(), C.clone()
+        cp[m, a, b] += hc
+        cm[m, a, b] -= hc
+        fd = (_quad(plan, plan.assemble(cp, th), rowptr, colind, u) -
+              _quad(plan, plan.assemble(cm, th), rowptr, colind, u)) / (2 * hc)
+        worst = max(worst, abs(fd - gC[m, a, b]) / np.abs(gC).max())
+    print("worst FD rel error %.3e" % worst, flush=True)
+    assert worst <= TOL
+
+
+def test_full_size_adjoint_plate_uu(oracle, L):
+    """96x96 degree-2 plate, 64 plies with seeded angles and 4 materials,
+    L = u^T K u for seeded N(0,1) u: GPU adjoint vs the oracle's gradient
+    computed from u directly (no G on the CPU)."""
+    lam = W.config_adjoint_p2_96x96_64ply()
+    u_np = np.random.default_rng(W.SEED_U).standard_normal(lam.n_rows)
+    plan = L.Plan(lam, set_mode="bucket")
+    rowptr, colind = plan.pattern()
+    C, th = _mats(lam)
+    u = torch.tensor(u_np, device="cuda")
+    rows = torch.repeat_interleave(torch.arange(plan.n_rows, device="cuda"), rowptr[1:] - rowptr[:-1])
+    G = u[rows] * u[colind.long()]
+    del rows
+    gC, gT = plan.adjoint(C, th, G)
+    gC, gT = gC.cpu().numpy(), gT.cpu().numpy()
+    dD = oracle.grad_D_uu(lam, u_np)
+    gC_ref, gT_ref = oracle.grad_material(lam, dD)
+    eC, eT = _rel(gC, gC_ref), _rel(gT, gT_ref)
+    print("full size: dC rel %.3e  dtheta rel %.3e" % (eC, eT), flush=True)
+    assert eC <= TOL and eT <= TOL
+    # the same L from the forward: Euler identity sum <C, dL/dC> = L
+    Lq = _quad(plan, plan.assemble(C, th), rowptr, colind, u)
+    euler = float(np.sum(np.asarray(lam.C) * gC))
+    assert abs(euler - Lq) <= 1e-9 * abs(Lq)

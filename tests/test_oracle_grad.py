@@ -97,3 +97,20 @@ def test_isotropic_angle_gradient_is_zero(oracle):
     G = rng.standard_normal(len(pat[1]))
     gC, gT = oracle.grad(lam, G, pattern_=pat)
     assert np.abs(gT).max() < 1e-12 * np.abs(gC).max() * np.abs(lam.C).max()
+
+
+def test_uu_gradient_equals_general_gradient(oracle):
+    """The u u^T specialisation (used at full size) agrees with the general
+    gradient fed G = u u^T, and with u^T K u's Euler identity."""
+    rng = np.random.default_rng(7)
+    for k in range(3):
+        lam = W.random_small(rng, paper_regime=(k == 1), max_ply=3)
+        pat = oracle.pattern(lam)
+        u = rng.standard_normal(lam.n_rows)
+        dD = oracle.grad_D(lam, pat[0], pat[1], _G_uu(lam, pat, u))
+        dU = oracle.grad_D_uu(lam, u)
+        assert np.abs(dD - dU).max() < 1e-12 * np.abs(dD).max()
+        _, _, v = oracle.assemble(lam, pattern_=pat)
+        L = math.fsum(_G_uu(lam, pat, u) * v)
+        Ds = np.stack([oracle.rotate(lam.C[lam.ply_mat[l]], lam.theta[l]) for l in range(lam.n_ply)])
+        assert abs(math.fsum((Ds * dU).ravel()) - L) < 1e-12 * abs(L)
