@@ -145,16 +145,66 @@ LAM_API lam_status lam_adjoint(const lam_plan *plan, void *ws, int64_t ws_bytes,
                                const double *theta, const double *grad_vals, int64_t nnz, double *grad_C,
                                double *grad_theta, void *stream);
 
+/* Batched assembly: many laminates (different meshes, degrees, ply counts,
+ * materials) in one persistent kernel launch per memory wave (Sec. 3 applied
+ * per laminate; each laminate's values are exactly those of lam_assemble on
+ * its own plan).
+ *
+ * lam_batch_create plans every descriptor (host only) and splits the
+ * laminates, in the given order, into waves: runs of consecutive laminates
+ * whose CSR values plus scratch fit wave_bytes (<= 0: one wave).  A laminate
+ * larger than wave_bytes forms a wave of its own.  Fails with the first
+ * failing descriptor's status, or LAM_EUNSUP for a laminate whose scatter
+ * needs more than two set slots per thickness chunk (many distinct sets on
+ * one row: use lam_assemble for it).
+ *
+ * Device memory: one workspace of ws_bytes (lam_batch_info), 256-byte
+ * aligned, holding every plan's constant tables, one scratch arena reused by
+ * all waves, and the work queues.  C_all packs the laminates' n_mat*36
+ * tensors and theta_all their n_ply angles at the offsets lam_batch_laminate
+ * reports (device doubles).  Values of wave w go to vals_wave (device,
+ * vals_len >= that wave's length <= max_wave_vals doubles), laminate i at
+ * vals_offset (a multiple of 32 doubles) within its wave; gaps between
+ * laminates are not written. */
+typedef struct lam_batch lam_batch;
+
+LAM_API lam_status lam_batch_create(int32_t n, const lam_laminate_desc *descs, int64_t wave_bytes, lam_batch **out);
+LAM_API void lam_batch_destroy(lam_batch *batch);
+LAM_API lam_status lam_batch_info(const lam_batch *batch, int32_t *n_waves, int64_t *ws_bytes,
+                                  int64_t *max_wave_vals, int64_t *total_nnz);
+/* Per laminate i: its wave, the offset of its values in that wave's buffer,
+ * its nonzeros and rows, and its offsets into C_all and theta_all (doubles). */
+LAM_API lam_status lam_batch_laminate(const lam_batch *batch, int32_t i, int32_t *wave, int64_t *vals_offset,
+                                      int64_t *nnz, int64_t *n_rows, int64_t *C_offset, int64_t *theta_offset);
+/* Copies every plan's tables and the work queues to ws; synchronizes stream. */
+LAM_API lam_status lam_batch_upload(const lam_batch *batch, void *ws, int64_t ws_bytes, void *stream);
+/* CSR pattern of laminate i, as lam_pattern. */
+LAM_API lam_status lam_batch_pattern(const lam_batch *batch, const void *ws, int64_t ws_bytes, int32_t i,
+                                     int64_t *rowptr, int32_t *colind, void *stream);
+/* Assembles every laminate of wave `wave`: a small kernel clearing the queue
+ * counters, then the persistent kernel.  Asynchronous; may be captured in a
+ * HIP graph (no memset, no allocation, no host synchronization).  Waves
+ * share the scratch arena: waves on different streams must not overlap. */
+LAM_API lam_status lam_batch_assemble(const lam_batch *batch, void *ws, int64_t ws_bytes, int32_t wave,
+                                      const double *C_all, const double *theta_all, double *vals_wave,
+                                      int64_t vals_len, void *stream);
+/* Reads the batch error flag of the last wave (synchronizes stream): nonzero
+ * if any dependency wait of the persistent kernel gave up (its item was
+ * skipped and that wave's values are incomplete). */
+LAM_API lam_status lam_batch_check(const lam_batch *batch, const void *ws, int64_t ws_bytes, int32_t *error,
+                                   void *stream);
+
 /* Kernel timing for measurement.  While enabled, every device entry point
  * records a pair of HIP events on its stream around its dominant kernel
  * (the Kronecker scatter of lam_assemble, the element kernel of
- * lam_assemble_standard, the streaming contraction of lam_adjoint); no work
- * is added or skipped.  lam_profile_read waits for the recorded events and
- * returns the summed milliseconds and the number of timed launches per entry
- * point (index 0 assemble, 1 standard, 2 adjoint), then clears them.
+ * lam_assemble_standard, the streaming contraction of lam_adjoint, the
+ * persistent kernel of lam_batch_assemble); no work is added or skipped.
+ * lam_profile_read waits for the recorded events and returns the summed
+ * milliseconds and the number of timed launches per entry point (index 0
+ * assemble, 1 standard, 2 adjoint, 3 batch), then clears them.
  * Up to 4096 launches are kept; later ones are not timed. */
 LAM_API lam_status lam_profile_enable(int32_t on);
-LAM_API lam_status lam_profile_read(double ms[3], int64_t launches[3]);
+LAM_API lam_status lam_profile_read(double ms[4], int64_t launches[4]);
 
 LAM_API const char *lam_status_string(lam_status s);
 

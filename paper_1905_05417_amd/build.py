@@ -8,8 +8,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblamasm.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("plan.cpp", "profile.cpp", "kernels.hip")]
-HEADERS = [os.path.join(ROOT, "include", "lamasm.h"), os.path.join(HERE, "csrc", "internal.h")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("plan.cpp", "profile.cpp", "kernels.hip", "batch.hip")]
+HEADERS = [os.path.join(ROOT, "include", "lamasm.h"), os.path.join(HERE, "csrc", "internal.h"),
+           os.path.join(HERE, "csrc", "device.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-fvisibility=hidden",

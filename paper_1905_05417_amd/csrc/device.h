@@ -1,0 +1,430 @@
+// device.h -- device-side plan view and the work items of the batched
+// persistent kernel (batch.hip): the same per-laminate arithmetic as the
+// single-laminate kernels, written as block-level items.  Not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+
+#include "internal.h"
+
+namespace lamdev {
+
+using lam::Region;
+
+struct Dev {
+  // sizes
+  int p1, p2, q, n1, n2, nt, ns, ng1, ng2, ngz;
+  int n_ply, n_mat, n_sets, set_mode, n_harm, maxact, n_tiles, tile_k;
+  int64_t nnz2, nnzz, nnz, nrows;
+  double jit[9], detj;
+  // constant tables
+  const double *tab1, *w1, *tab2, *w2;
+  const int *e1first, *e2first;
+  const int2 *pe1, *pe2;
+  const int *srow, *krow, *kcol, *kp1, *kp2;
+  const int *zfirst, *zply;
+  const double *ztab, *zw;
+  const int *zrow, *zcol, *zkrow, *zcptr, *zcell, *zaptr, *zaset;
+  const int *set_mat, *set_aux, *ply_mat, *ply_set;
+  const int *tiles, *chunk_ptr, *chunk_sptr, *chunk_set, *zaslot;
+  int n_chunks, chunk_sets;
+  int64_t kron_lds_q, kron_lds_p;
+  const int *zchunk;
+  int kron_nsc;
+  const int *a1f, *a1c, *a2f, *a2c, *zs_first, *zs_cptr, *zs_cell;
+  int ne1, ne2, nzs;
+  double *Eply;
+  const int *rowply, *rowfin;
+  double *Qp, *adj_part, *adj_y, *adj_dD;
+  // scratch
+  double *D, *Ec, *P, *Qc, *M;
+};
+
+template <class T>
+inline T *at(void *ws, const Region &r) {
+  return reinterpret_cast<T *>(static_cast<char *>(ws) + r.off);
+}
+
+// Device view of a plan whose constant tables live at cbase and whose scratch
+// regions (offsets >= const_bytes) live at sbase (the single-laminate path
+// passes the same workspace for both).
+inline Dev make_dev_split(const lam_plan *p, void *cbase, void *sbase) {
+  char *sb = static_cast<char *>(sbase) - p->L.const_bytes;
+  Dev d;
+  d.p1 = p->p1; d.p2 = p->p2; d.q = p->q;
+  d.n1 = p->n1; d.n2 = p->n2; d.nt = p->nt; d.ns = p->ns;
+  d.ng1 = p->ng1; d.ng2 = p->ng2; d.ngz = p->ngz;
+  d.n_ply = p->n_ply; d.n_mat = p->n_mat; d.n_sets = p->n_sets; d.set_mode = p->set_mode;
+  d.n_harm = p->n_harm; d.maxact = p->maxact; d.n_tiles = p->n_tiles; d.tile_k = p->tile_k;
+  d.nnz2 = p->nnz2; d.nnzz = p->nnzz; d.nnz = p->nnz; d.nrows = p->nrows;
+  for (int a = 0; a < 9; ++a) d.jit[a] = p->jit[a];
+  d.detj = p->detj;
+  const lam::Layout &L = p->L;
+  d.tab1 = at<double>(cbase, L.tab1); d.w1 = at<double>(cbase, L.w1);
+  d.tab2 = at<double>(cbase, L.tab2); d.w2 = at<double>(cbase, L.w2);
+  d.e1first = at<int>(cbase, L.e1first); d.e2first = at<int>(cbase, L.e2first);
+  d.pe1 = at<int2>(cbase, L.pe1); d.pe2 = at<int2>(cbase, L.pe2);
+  d.srow = at<int>(cbase, L.srow); d.krow = at<int>(cbase, L.krow); d.kcol = at<int>(cbase, L.kcol);
+  d.kp1 = at<int>(cbase, L.kp1); d.kp2 = at<int>(cbase, L.kp2);
+  d.zfirst = at<int>(cbase, L.zfirst); d.zply = at<int>(cbase, L.zply);
+  d.ztab = at<double>(cbase, L.ztab); d.zw = at<double>(cbase, L.zw);
+  d.zrow = at<int>(cbase, L.zrow); d.zcol = at<int>(cbase, L.zcol); d.zkrow = at<int>(cbase, L.zkrow);
+  d.zcptr = at<int>(cbase, L.zcptr); d.zcell = at<int>(cbase, L.zcell);
+  d.zaptr = at<int>(cbase, L.zaptr); d.zaset = at<int>(cbase, L.zaset);
+  d.set_mat = at<int>(cbase, L.set_mat); d.set_aux = at<int>(cbase, L.set_aux);
+  d.ply_mat = at<int>(cbase, L.ply_mat); d.ply_set = at<int>(cbase, L.ply_set);
+  d.tiles = at<int>(cbase, L.tiles);
+  d.chunk_ptr = at<int>(cbase, L.chunk_ptr);
+  d.chunk_sptr = at<int>(cbase, L.chunk_sptr);
+  d.chunk_set = at<int>(cbase, L.chunk_set);
+  d.zaslot = at<int>(cbase, L.zaslot);
+  d.n_chunks = p->n_chunks;
+  d.chunk_sets = p->chunk_sets;
+  d.kron_lds_q = p->kron_lds_q;
+  d.zchunk = at<int>(cbase, L.zchunk);
+  d.a1f = at<int>(cbase, L.a1f); d.a1c = at<int>(cbase, L.a1c);
+  d.a2f = at<int>(cbase, L.a2f); d.a2c = at<int>(cbase, L.a2c);
+  d.zs_first = at<int>(cbase, L.zs_first); d.zs_cptr = at<int>(cbase, L.zs_cptr); d.zs_cell = at<int>(cbase, L.zs_cell);
+  d.ne1 = p->ne1; d.ne2 = p->ne2; d.nzs = p->nzs;
+  d.Eply = at<double>(sb, L.Eply);
+  d.rowply = at<int>(cbase, L.rowply); d.rowfin = at<int>(cbase, L.rowfin);
+  d.Qp = at<double>(sb, L.Qp); d.adj_part = at<double>(sb, L.adj_part);
+  d.adj_y = at<double>(sb, L.adj_y); d.adj_dD = at<double>(sb, L.adj_dD);
+  d.kron_nsc = p->kron_nsc;
+  d.kron_lds_p = p->kron_lds_p;
+  d.D = at<double>(sb, L.D); d.Ec = at<double>(sb, L.Ec); d.P = at<double>(sb, L.P);
+  d.Qc = at<double>(sb, L.Qc); d.M = at<double>(sb, L.M);
+  return d;
+}
+
+inline Dev make_dev(const lam_plan *p, void *ws) { return make_dev_split(p, ws, ws); }
+
+// ---------------------------------------------------------------------------
+// Material rotation (eq. D).  With R[i][k] = e_i . a_k (material axes
+// a_1 = (c,s,0), a_2 = (-s,c,0), a_3 = e_3), the Voigt stress transformation
+// is T[I][J] = R[i][k] R[j][l] + [k != l] R[i][l] R[j][k] for I = (ij),
+// J = (kl); engineering strains transform with T^T, so D = T C T^T.
+static __constant__ int kVi[6] = {0, 1, 2, 0, 0, 1};
+static __constant__ int kVj[6] = {0, 1, 2, 1, 2, 2};
+
+__device__ inline void voigt_rotation(double c, double s, double T[6][6]) {
+  const double R[3][3] = {{c, -s, 0.0}, {s, c, 0.0}, {0.0, 0.0, 1.0}};
+  for (int I = 0; I < 6; ++I)
+    for (int J = 0; J < 6; ++J) {
+      int i = kVi[I], j = kVj[I], k = kVi[J], l = kVj[J];
+      double t = R[i][k] * R[j][l];
+      if (k != l) t += R[i][l] * R[j][k];
+      T[I][J] = t;
+    }
+}
+
+__device__ inline void rotate_c(const double *C, double c, double s, double D[6][6]) {
+  double T[6][6], TC[6][6];
+  voigt_rotation(c, s, T);
+  for (int I = 0; I < 6; ++I)
+    for (int J = 0; J < 6; ++J) {
+      double a = 0.0;
+      for (int K = 0; K < 6; ++K) a += T[I][K] * C[K * 6 + J];
+      TC[I][J] = a;
+    }
+  for (int I = 0; I < 6; ++I)
+    for (int J = 0; J < 6; ++J) {
+      double a = 0.0;
+      for (int K = 0; K < 6; ++K) a += TC[I][K] * T[J][K];
+      D[I][J] = a;
+    }
+}
+
+// Harmonic h of a set: order and kind (0 constant, 1 cosine, 2 sine).
+__device__ inline void harmonic(int n_harm, int h, int &order, int &kind) {
+  if (h == 0) { order = 0; kind = 0; return; }
+  if (n_harm == 5) { order = 2 * ((h + 1) / 2); kind = (h & 1) ? 1 : 2; return; }
+  order = (h + 1) / 2;
+  kind = (h & 1) ? 1 : 2;
+}
+
+__device__ inline double harmonic_weight(int n_harm, int h, double theta) {
+  int order, kind;
+  harmonic(n_harm, h, order, kind);
+  if (kind == 0) return 1.0;
+  return kind == 1 ? cos(order * theta) : sin(order * theta);
+}
+
+// Voigt strain of the displacement e_r * phi for a unit gradient e_k:
+// column r of B(e_k) (eq. B_1 with the gamma_23 entry of the u_3 column
+// taking the 2-derivative).
+__device__ inline double bunit(int k, int I, int r) {
+  // B(g)[I][r]: rows 11,22,33,12,13,23
+  switch (I) {
+    case 0: return (r == 0 && k == 0) ? 1.0 : 0.0;
+    case 1: return (r == 1 && k == 1) ? 1.0 : 0.0;
+    case 2: return (r == 2 && k == 2) ? 1.0 : 0.0;
+    case 3: return ((r == 0 && k == 1) || (r == 1 && k == 0)) ? 1.0 : 0.0;
+    case 4: return ((r == 0 && k == 2) || (r == 2 && k == 0)) ? 1.0 : 0.0;
+    default: return ((r == 1 && k == 2) || (r == 2 && k == 1)) ? 1.0 : 0.0;
+  }
+}
+
+// E[k][l][r][t] = sum_IJ B(e_k)[I][r] D[I][J] B(e_l)[J][t]: the 3x3 block
+// B(a)^T D B(b) of two gradients is sum_kl a_k b_l E[k][l].
+__device__ inline void bracket_coefficients(const double D[6][6], double *E) {
+  for (int k = 0; k < 3; ++k)
+    for (int l = 0; l < 3; ++l)
+      for (int r = 0; r < 3; ++r)
+        for (int t = 0; t < 3; ++t) {
+          double a = 0.0;
+          for (int I = 0; I < 6; ++I) {
+            double bi = bunit(k, I, r);
+            if (bi == 0.0) continue;
+            for (int J = 0; J < 6; ++J) a += bi * D[I][J] * bunit(l, J, t);
+          }
+          E[((k * 3 + l) * 3 + r) * 3 + t] = a;
+        }
+}
+
+// One thread per set.  Harmonic sets: the Fourier coefficient of D(phi)
+// sampled at NH equispaced angles (exact for trigonometric polynomials of
+// degree <= 4 once NH >= 9).
+constexpr int NH = 12;
+
+__device__ inline void item_rotate_set(const Dev &d, const double *__restrict__ C, const double *__restrict__ theta, int s) {
+  const double *Cm = C + 36 * d.set_mat[s];
+  double D[6][6];
+  if (d.set_mode == LAM_SETS_BUCKET) {
+    double th = theta[d.set_aux[s]];
+    rotate_c(Cm, cos(th), sin(th), D);
+  } else {
+    int order, kind;
+    harmonic(d.n_harm, d.set_aux[s], order, kind);
+    for (int I = 0; I < 6; ++I)
+      for (int J = 0; J < 6; ++J) D[I][J] = 0.0;
+    for (int j = 0; j < NH; ++j) {
+      double phi = 2.0 * M_PI * j / NH;
+      double wgt = kind == 0 ? 1.0 / NH : (kind == 1 ? 2.0 * cos(order * phi) : 2.0 * sin(order * phi)) / NH;
+      double Dj[6][6];
+      rotate_c(Cm, cos(phi), sin(phi), Dj);
+      for (int I = 0; I < 6; ++I)
+        for (int J = 0; J < 6; ++J) D[I][J] += wgt * Dj[I][J];
+    }
+  }
+  for (int I = 0; I < 6; ++I)
+    for (int J = 0; J < 6; ++J) d.D[36 * s + 6 * I + J] = D[I][J];
+  bracket_coefficients(D, d.Ec + 81 * s);
+}
+
+
+// ---------------------------------------------------------------------------
+// 2D operators (eq. P).  For in-plane pair k = (is, js), the 2D Gauss sum
+// over the elements shared by both supports of the parametric moments
+//   m11[a][b] = sum w dS^i/dxi_a dS^j/dxi_b,  m12[a] = sum w dS^i/dxi_a S^j,
+//   m21[b]    = sum w S^i dS^j/dxi_b,         m22    = sum w S^i S^j,
+// pushed through DF^{-T} (grad V = DF^{-T}(dS1,dS2,0), W = DF^{-T}(0,0,S))
+// into M_ab[k][l] = int (G_a^i)_k (G_b^j)_l |DF|.  Because each set's
+// material is constant over the plane, P_{s,ab}[r][t] = sum_kl M_ab[k][l] E_s[k][l][r][t].
+__device__ inline void item_p2d(const Dev &d, const double *__restrict__ Ec, double *__restrict__ Pt,
+                                double *__restrict__ Mt, int64_t k, int write_p) {
+  const int is = d.krow[k], js = d.kcol[k];
+  const int i1 = is % d.n1, i2 = is / d.n1, j1 = js % d.n1, j2 = js / d.n1;
+  const int2 ra = d.pe1[d.kp1[k]], rb = d.pe2[d.kp2[k]];
+  const int P1 = d.p1 + 1, P2 = d.p2 + 1;
+  double m11[2][2] = {{0, 0}, {0, 0}}, m12[2] = {0, 0}, m21[2] = {0, 0}, m22 = 0.0;
+  for (int e2 = rb.x; e2 < rb.x + rb.y; ++e2) {
+    const int f2 = d.e2first[e2];
+    const int ai2 = i2 - f2, aj2 = j2 - f2;
+    for (int e1 = ra.x; e1 < ra.x + ra.y; ++e1) {
+      const int f1 = d.e1first[e1];
+      const int ai1 = i1 - f1, aj1 = j1 - f1;
+      for (int g2 = 0; g2 < d.ng2; ++g2) {
+        const double *t2 = d.tab2 + ((int64_t)e2 * d.ng2 + g2) * P2 * 2;
+        const double Ni2 = t2[2 * ai2], dNi2 = t2[2 * ai2 + 1];
+        const double Nj2 = t2[2 * aj2], dNj2 = t2[2 * aj2 + 1];
+        const double wg2 = d.w2[(int64_t)e2 * d.ng2 + g2];
+        for (int g1 = 0; g1 < d.ng1; ++g1) {
+          const double *t1 = d.tab1 + ((int64_t)e1 * d.ng1 + g1) * P1 * 2;
+          const double Ni1 = t1[2 * ai1], dNi1 = t1[2 * ai1 + 1];
+          const double Nj1 = t1[2 * aj1], dNj1 = t1[2 * aj1 + 1];
+          const double w = wg2 * d.w1[(int64_t)e1 * d.ng1 + g1];
+          const double gi[2] = {dNi1 * Ni2, Ni1 * dNi2}, gj[2] = {dNj1 * Nj2, Nj1 * dNj2};
+          const double Si = Ni1 * Ni2, Sj = Nj1 * Nj2;
+          const double wSi = w * Si, wSj = w * Sj;
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            const double wgi = w * gi[a];
+            m11[a][0] += wgi * gj[0];
+            m11[a][1] += wgi * gj[1];
+            m12[a] += wgi * Sj;
+            m21[a] += wSi * gj[a];
+          }
+          m22 += wSi * Sj;
+        }
+      }
+    }
+  }
+  // M_ab[k][l], ab = 11, 12, 21, 22
+  double M[4][3][3];
+  const double *J = d.jit;
+#pragma unroll
+  for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+    for (int ll = 0; ll < 3; ++ll) {
+      double v11 = 0.0, v12 = 0.0, v21 = 0.0;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        v12 += J[kk * 3 + a] * m12[a];
+        v21 += J[ll * 3 + a] * m21[a];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) v11 += J[kk * 3 + a] * J[ll * 3 + b] * m11[a][b];
+      }
+      M[0][kk][ll] = d.detj * v11;
+      M[1][kk][ll] = d.detj * v12 * J[ll * 3 + 2];
+      M[2][kk][ll] = d.detj * J[kk * 3 + 2] * v21;
+      M[3][kk][ll] = d.detj * J[kk * 3 + 2] * J[ll * 3 + 2] * m22;
+    }
+  // component-major tables: consecutive threads (k) store consecutive addresses
+#pragma unroll
+  for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+    for (int e = 0; e < 9; ++e) Mt[(int64_t)(ab * 9 + e) * d.nnz2 + k] = M[ab][e / 3][e % 3];
+  for (int s = 0; s < (write_p ? d.n_sets : 0); ++s) {
+    const double *E = Ec + 81 * s;
+    double *Po = Pt + (int64_t)s * 36 * d.nnz2 + k;
+#pragma unroll
+    for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+      for (int rt = 0; rt < 9; ++rt) {
+        double a = 0.0;
+#pragma unroll
+        for (int kl = 0; kl < 9; ++kl) a += M[ab][kl / 3][kl % 3] * E[kl * 9 + rt];
+        Po[(int64_t)(ab * 9 + rt) * d.nnz2] = a;
+      }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// 1D operators (eq. Q) folded into the sets: for thickness pair zk = (it, jt)
+// and the j-th set active on row it,
+//   Qc[zk][j][ab] = sum_{cells c shared by it, jt} w_{s,ply(c)} sum_g w_g tau_a^{it} tau_b^{jt}
+// with tau_1 = T, tau_2 = dT/dxi3, a on the test function it, and
+// w_{s,l} = [set of l == s] (bucket) or [mat(l) == mat(s)] * harmonic_s(theta_l).
+// register mode: one entry per chunk set slot (zeros where the slot's set
+// does not act on the pair); LDS mode: one per set active on the row
+__device__ inline int q1d_width(const Dev &d) { return d.kron_nsc > 0 ? d.kron_nsc : d.maxact; }
+
+__device__ inline void item_q1d(const Dev &d, const double *__restrict__ theta, int64_t idx) {
+  const int width = q1d_width(d);
+  const int zk = (int)(idx / width), j = (int)(idx % width);
+  const int it = d.zkrow[zk], jt = d.zcol[zk];
+  int s = -1;
+  if (d.kron_nsc > 0) {
+    const int ch = d.zchunk[it], c0 = d.chunk_sptr[ch];
+    if (j < d.chunk_sptr[ch + 1] - c0) s = d.chunk_set[c0 + j];
+  } else {
+    const int a0 = d.zaptr[it];
+    if (j < d.zaptr[it + 1] - a0) s = d.zaset[a0 + j];
+  }
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (s >= 0) {
+    const int Q1 = d.q + 1;
+    for (int ci = d.zcptr[zk]; ci < d.zcptr[zk + 1]; ++ci) {
+      const int c = d.zcell[ci], l = d.zply[c];
+      double wgt;
+      if (d.set_mode == LAM_SETS_BUCKET) {
+        wgt = d.ply_set[l] == s ? 1.0 : 0.0;
+      } else {
+        wgt = d.ply_mat[l] == d.set_mat[s] ? harmonic_weight(d.n_harm, d.set_aux[s], theta[l]) : 0.0;
+      }
+      if (wgt == 0.0) continue;
+      const int ai = it - d.zfirst[c], aj = jt - d.zfirst[c];
+      double q11 = 0.0, q12 = 0.0, q21 = 0.0, q22 = 0.0;
+      for (int g = 0; g < d.ngz; ++g) {
+        const double *t = d.ztab + ((int64_t)c * d.ngz + g) * Q1 * 2;
+        const double Ti = t[2 * ai], dTi = t[2 * ai + 1], Tj = t[2 * aj], dTj = t[2 * aj + 1];
+        const double w = d.zw[(int64_t)c * d.ngz + g];
+        q11 += w * Ti * Tj;
+        q12 += w * Ti * dTj;
+        q21 += w * dTi * Tj;
+        q22 += w * dTi * dTj;
+      }
+      acc[0] += wgt * q11;
+      acc[1] += wgt * q12;
+      acc[2] += wgt * q21;
+      acc[3] += wgt * q22;
+    }
+  }
+  double *o = d.Qc + 4 * idx;
+  o[0] = acc[0];
+  o[1] = acc[1];
+  o[2] = acc[2];
+  o[3] = acc[3];
+}
+
+
+constexpr int KRON_THREADS = 256;  // 3 * tile_k <= KRON_THREADS
+constexpr int KRON_AB = 5;         // thickness columns per register block
+
+// Register mode of the scatter: each thread loads P of the chunk's NSC set
+// slots for its (k, t) once into registers and reads the chunk's slot-dense
+// coefficients Qd[zk][slot][ab] from LDS (staged once per item), so the row
+// loop issues no vector loads at all and the stores stream.  Block-cooperative:
+// every thread of the block calls it (it contains a barrier); lq holds at
+// least 4*NSC*(rows of the chunk) doubles.
+template <int NSC>
+__device__ inline void item_kron_reg(const Dev &d, const double *__restrict__ qd, double *__restrict__ vals, int tile,
+                                     int ch, double *lq, int sig, int nthreads) {
+  const int k0 = d.tiles[tile], tk = d.tiles[tile + 1] - k0;
+  const int it0 = d.chunk_ptr[ch], it1 = d.chunk_ptr[ch + 1];
+  const int zk0 = d.zrow[it0], nq = 4 * NSC * (d.zrow[it1] - zk0);
+  const bool act = sig < 3 * tk;
+  const int kk = act ? sig / 3 : 0, t = act ? sig - 3 * kk : 0, k = k0 + kk;
+  const int c0 = d.chunk_sptr[ch], nsc = d.chunk_sptr[ch + 1] - c0;
+  double pr[NSC][4][3];
+#pragma unroll
+  for (int u = 0; u < NSC; ++u) {
+    const double *Pp = d.P + (int64_t)(u < nsc ? d.chunk_set[c0 + u] : 0) * 36 * d.nnz2 + k;
+#pragma unroll
+    for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) pr[u][ab][r] = u < nsc ? Pp[(int64_t)(ab * 9 + 3 * r + t) * d.nnz2] : 0.0;
+  }
+  for (int e = sig; e < nq; e += nthreads) lq[e] = qd[4 * (int64_t)NSC * zk0 + e];
+  __syncthreads();
+  if (act) {
+    const int is = d.krow[k], sr = d.srow[is];
+    const int Ls = d.srow[is + 1] - sr, off = 3 * (k - sr) + t;
+    const int64_t astride = 3 * (int64_t)Ls;
+    for (int it = it0; it < it1; ++it) {
+      const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
+      double *out = vals + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
+      const int64_t rstride = 3 * (int64_t)Lz * Ls;
+      for (int ab0 = 0; ab0 < Lz; ab0 += KRON_AB) {
+        double acc[KRON_AB][3];
+#pragma unroll
+        for (int x = 0; x < KRON_AB; ++x) {
+          acc[x][0] = acc[x][1] = acc[x][2] = 0.0;
+          if (ab0 + x < Lz) {
+            const double *qq = lq + 4 * NSC * (zb + ab0 + x - zk0);
+#pragma unroll
+            for (int u = 0; u < NSC; ++u) {
+              const double q0 = qq[4 * u], q1 = qq[4 * u + 1], q2 = qq[4 * u + 2], q3 = qq[4 * u + 3];
+#pragma unroll
+              for (int r = 0; r < 3; ++r)
+                acc[x][r] += q0 * pr[u][0][r] + q1 * pr[u][1][r] + q2 * pr[u][2][r] + q3 * pr[u][3][r];
+            }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int x = 0; x < KRON_AB; ++x)
+            if (ab0 + x < Lz) out[r * rstride + (int64_t)(ab0 + x) * astride] = acc[x][r];
+      }
+    }
+  }
+}
+
+}  // namespace lamdev

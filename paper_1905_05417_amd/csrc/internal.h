@@ -48,8 +48,10 @@ struct Layout {
   // active set of a row its LDS slot in the row's chunk (zaslot, parallel to zaset)
   Region tiles, chunk_ptr, chunk_sptr, chunk_set, zaslot, zchunk;
   int64_t const_bytes = 0;  // end of the constant part
-  // scratch
+  // scratch: the fast assembly uses [const_bytes, fwd_end); the standard
+  // assembly and the adjoint use the regions after it
   Region D, Ec, P, Qc, M, Eply, Qp, adj_part, adj_y, adj_dD;
+  int64_t fwd_end = 0;
   int64_t total = 0;
 };
 

@@ -594,6 +594,11 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
   for (int l = 0; l < d->n_ply; ++l) {
     if (last_row[l] < 0) continue;
     rowfin[last_row[l]] |= 1 << (l & 1);
+    // a ply whose slot another ply took on every row it touches: unsupported
+    if (first_row[l] < 0) {
+      P->adj_ok = 0;
+      continue;
+    }
     // while ply l accumulates, no other ply may use its slot
     for (int it = first_row[l]; it <= last_row[l]; ++it) {
       const int o = rowply[2 * it + (l & 1)];
@@ -655,6 +660,7 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
   L.P = B.take(sizeof(double) * 36 * (int64_t)P->n_sets * P->nnz2);
   L.Qc = B.take(sizeof(double) * 4 * (int64_t)std::max(P->maxact, P->kron_nsc) * P->nnzz);
   L.M = B.take(sizeof(double) * 36 * P->nnz2);
+  L.fwd_end = B.cur;  // scratch of the fast assembly ends here
   L.Eply = B.take(sizeof(double) * 81 * P->n_ply);
   // adjoint scratch: per-ply 1D operators by slot, per (tile, ply) partial sums,
   // per-ply totals and dL/dD_l

@@ -46,8 +46,10 @@ class _Desc(ctypes.Structure):
 _lib = None
 
 EXPORTED = ("lam_plan_create", "lam_plan_destroy", "lam_plan_info", "lam_plan_upload", "lam_pattern",
-            "lam_assemble", "lam_assemble_standard", "lam_adjoint", "lam_profile_enable", "lam_profile_read",
-            "lam_status_string", "lam_version")
+            "lam_assemble", "lam_assemble_standard", "lam_adjoint",
+            "lam_batch_create", "lam_batch_destroy", "lam_batch_info", "lam_batch_laminate", "lam_batch_upload",
+            "lam_batch_pattern", "lam_batch_assemble", "lam_batch_check",
+            "lam_profile_enable", "lam_profile_read", "lam_status_string", "lam_version")
 
 
 def lib():
@@ -67,6 +69,15 @@ def lib():
         L.lam_assemble.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
         L.lam_assemble_standard.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
         L.lam_adjoint.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
+        L.lam_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(_Desc), i64, ctypes.POINTER(vp)]
+        L.lam_batch_destroy.argtypes = [vp]
+        L.lam_batch_destroy.restype = None
+        L.lam_batch_info.argtypes = [vp, _i32p, i64p, i64p, i64p]
+        L.lam_batch_laminate.argtypes = [vp, ctypes.c_int32, _i32p, i64p, i64p, i64p, i64p, i64p]
+        L.lam_batch_upload.argtypes = [vp, vp, i64, vp]
+        L.lam_batch_pattern.argtypes = [vp, vp, i64, ctypes.c_int32, vp, vp, vp]
+        L.lam_batch_assemble.argtypes = [vp, vp, i64, ctypes.c_int32, vp, vp, vp, i64, vp]
+        L.lam_batch_check.argtypes = [vp, vp, i64, _i32p, vp]
         L.lam_profile_enable.argtypes = [ctypes.c_int32]
         L.lam_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.lam_status_string.argtypes = [ctypes.c_int32]
@@ -98,6 +109,32 @@ def default_set_mode(lam) -> str:
     return "bucket" if len(keys) <= 5 * n_mat else "harmonic9"
 
 
+def _make_desc(lam, set_mode):
+    """lam_laminate_desc for a laminate; returns it and the arrays it points into."""
+    keep = [np.ascontiguousarray(lam.k1, dtype=np.float64),
+            np.ascontiguousarray(lam.k2, dtype=np.float64),
+            np.ascontiguousarray(lam.k3, dtype=np.float64),
+            np.ascontiguousarray(lam.iface, dtype=np.float64),
+            np.ascontiguousarray(lam.ply_mat, dtype=np.int32),
+            np.ascontiguousarray(lam.theta, dtype=np.float64)]
+    k1, k2, k3, iface, pm, th = keep
+    d = _Desc()
+    d.p1, d.nk1, d.k1 = int(lam.p1), len(k1), k1.ctypes.data_as(_dp)
+    d.p2, d.nk2, d.k2 = int(lam.p2), len(k2), k2.ctypes.data_as(_dp)
+    d.q, d.nk3, d.k3 = int(lam.q), len(k3), k3.ctypes.data_as(_dp)
+    J = np.asarray(lam.jac, dtype=np.float64).reshape(9)
+    for a in range(9):
+        d.jac[a] = float(J[a])
+    d.n_ply = len(th)
+    d.iface = iface.ctypes.data_as(_dp)
+    d.ply_mat = pm.ctypes.data_as(_i32p)
+    d.n_mat = int(np.asarray(lam.C).shape[0])
+    d.ply_theta = th.ctypes.data_as(_dp)
+    d.ng1, d.ng2, d.ngz = (int(g) for g in getattr(lam, "ng", (0, 0, 0)))
+    d.set_mode = LAM_SETS[set_mode]
+    return d, keep
+
+
 class Plan:
     """Host plan and device workspace for one laminate discretisation."""
 
@@ -105,27 +142,7 @@ class Plan:
         set_mode = set_mode or default_set_mode(lam)
         self.lam = lam
         self.set_mode = set_mode
-        self._keep = [np.ascontiguousarray(lam.k1, dtype=np.float64),
-                      np.ascontiguousarray(lam.k2, dtype=np.float64),
-                      np.ascontiguousarray(lam.k3, dtype=np.float64),
-                      np.ascontiguousarray(lam.iface, dtype=np.float64),
-                      np.ascontiguousarray(lam.ply_mat, dtype=np.int32),
-                      np.ascontiguousarray(lam.theta, dtype=np.float64)]
-        k1, k2, k3, iface, pm, th = self._keep
-        d = _Desc()
-        d.p1, d.nk1, d.k1 = int(lam.p1), len(k1), k1.ctypes.data_as(_dp)
-        d.p2, d.nk2, d.k2 = int(lam.p2), len(k2), k2.ctypes.data_as(_dp)
-        d.q, d.nk3, d.k3 = int(lam.q), len(k3), k3.ctypes.data_as(_dp)
-        J = np.asarray(lam.jac, dtype=np.float64).reshape(9)
-        for a in range(9):
-            d.jac[a] = float(J[a])
-        d.n_ply = len(th)
-        d.iface = iface.ctypes.data_as(_dp)
-        d.ply_mat = pm.ctypes.data_as(_i32p)
-        d.n_mat = int(np.asarray(lam.C).shape[0])
-        d.ply_theta = th.ctypes.data_as(_dp)
-        d.ng1, d.ng2, d.ngz = (int(g) for g in getattr(lam, "ng", (0, 0, 0)))
-        d.set_mode = LAM_SETS[set_mode]
+        d, self._keep = _make_desc(lam, set_mode)
         self._desc = d
         h = ctypes.c_void_p()
         _check(lib().lam_plan_create(ctypes.byref(d), ctypes.byref(h)), "lam_plan_create")
@@ -205,11 +222,107 @@ def profile_enable(on: bool = True):
 
 
 def profile_read():
-    """{'assemble'|'standard'|'adjoint': (ms_total, launches)} since the last read."""
-    ms = (ctypes.c_double * 3)()
-    n = (ctypes.c_int64 * 3)()
+    """{'assemble'|'standard'|'adjoint'|'batch': (ms_total, launches)} since the last read."""
+    ms = (ctypes.c_double * 4)()
+    n = (ctypes.c_int64 * 4)()
     _check(lib().lam_profile_read(ms, n), "lam_profile_read")
-    return {k: (ms[i], n[i]) for i, k in enumerate(("assemble", "standard", "adjoint"))}
+    return {k: (ms[i], n[i]) for i, k in enumerate(("assemble", "standard", "adjoint", "batch"))}
+
+
+class BatchPlan:
+    """Many laminates assembled by one persistent kernel per memory wave.
+
+    Laminate i's values are exactly those of Plan(lams[i]).assemble.  Waves
+    are runs of consecutive laminates whose values plus scratch fit
+    wave_bytes (0: everything in one wave)."""
+
+    def __init__(self, lams, set_mode: str | None = "bucket", wave_bytes: int = 0, device="cuda"):
+        self.lams = list(lams)
+        n = len(self.lams)
+        descs = (_Desc * n)()
+        self._keep = []
+        for i, lam in enumerate(self.lams):
+            d, keep = _make_desc(lam, set_mode or default_set_mode(lam))
+            descs[i] = d
+            self._keep.append(keep)
+        h = ctypes.c_void_p()
+        _check(lib().lam_batch_create(n, descs, int(wave_bytes), ctypes.byref(h)), "lam_batch_create")
+        self._h = h
+        nw, wb, mv, tn = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().lam_batch_info(h, ctypes.byref(nw), ctypes.byref(wb), ctypes.byref(mv), ctypes.byref(tn)),
+               "lam_batch_info")
+        self.n, self.n_waves, self.ws_bytes = n, nw.value, wb.value
+        self.max_wave_vals, self.total_nnz = mv.value, tn.value
+        self.wave, self.vals_offset, self.nnz, self.n_rows, self.c_offset, self.t_offset = ([] for _ in range(6))
+        for i in range(n):
+            w, vo, nz, nr, co, to = (ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(),
+                                     ctypes.c_int64(), ctypes.c_int64())
+            _check(lib().lam_batch_laminate(h, i, ctypes.byref(w), ctypes.byref(vo), ctypes.byref(nz),
+                                            ctypes.byref(nr), ctypes.byref(co), ctypes.byref(to)),
+                   "lam_batch_laminate")
+            for lst, v in ((self.wave, w), (self.vals_offset, vo), (self.nnz, nz), (self.n_rows, nr),
+                           (self.c_offset, co), (self.t_offset, to)):
+                lst.append(v.value)
+        self.wave_vals = [0] * self.n_waves
+        for i in range(n):
+            self.wave_vals[self.wave[i]] = max(self.wave_vals[self.wave[i]], self.vals_offset[i] + self.nnz[i])
+        self.device = torch.device(device)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        _check(lib().lam_batch_upload(h, self.ws.data_ptr(), self.ws_bytes, _stream()), "lam_batch_upload")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.lam_batch_destroy(h)
+            self._h = None
+
+    def pack(self, Cs=None, thetas=None):
+        """Device C_all and theta_all from per-laminate tensors (default: the laminates' own)."""
+        Cs = [lam.C for lam in self.lams] if Cs is None else Cs
+        thetas = [lam.theta for lam in self.lams] if thetas is None else thetas
+        C_all = torch.cat([torch.as_tensor(np.asarray(c, dtype=np.float64)).reshape(-1) for c in Cs])
+        th_all = torch.cat([torch.as_tensor(np.asarray(t, dtype=np.float64)).reshape(-1) for t in thetas])
+        return C_all.to(self.device), th_all.to(self.device)
+
+    def pattern(self, i):
+        rowptr = torch.empty(self.n_rows[i] + 1, dtype=torch.int64, device=self.device)
+        colind = torch.empty(self.nnz[i], dtype=torch.int32, device=self.device)
+        _check(lib().lam_batch_pattern(self._h, self.ws.data_ptr(), self.ws_bytes, i, rowptr.data_ptr(),
+                                       colind.data_ptr(), _stream()), "lam_batch_pattern")
+        return rowptr, colind
+
+    def assemble_wave(self, wave, C_all, th_all, out):
+        """Enqueue wave `wave` into out (device float64, >= wave_vals[wave])."""
+        _check(lib().lam_batch_assemble(self._h, self.ws.data_ptr(), self.ws_bytes, int(wave), C_all.data_ptr(),
+                                        th_all.data_ptr(), out.data_ptr(), out.numel(), _stream()),
+               "lam_batch_assemble")
+        return out
+
+    def check(self):
+        """Raises if a dependency wait of the last wave gave up."""
+        e = ctypes.c_int32()
+        _check(lib().lam_batch_check(self._h, self.ws.data_ptr(), self.ws_bytes, ctypes.byref(e), _stream()),
+               "lam_batch_check")
+        if e.value:
+            raise RuntimeError("batched assembly: a dependency wait timed out; values incomplete")
+
+    def laminate_vals(self, i, wave_buf):
+        o = self.vals_offset[i]
+        return wave_buf[o:o + self.nnz[i]]
+
+    def assemble(self, C_all=None, th_all=None):
+        """All laminates, wave by wave; returns a list of per-laminate value tensors (copies)."""
+        if C_all is None:
+            C_all, th_all = self.pack()
+        out = [None] * self.n
+        buf = torch.empty(self.max_wave_vals, dtype=torch.float64, device=self.device)
+        for w in range(self.n_waves):
+            self.assemble_wave(w, C_all, th_all, buf)
+            self.check()
+            for i in range(self.n):
+                if self.wave[i] == w:
+                    out[i] = self.laminate_vals(i, buf).clone()
+        return out
 
 
 class _Assemble(torch.autograd.Function):
