@@ -40,6 +40,8 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extra", action="store_true", help="only the headline workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-laminate batch")
+    ap.add_argument("--batch-wave-gib", type=int, default=150)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     return ap.parse_args()
@@ -112,6 +114,56 @@ def _fast_workload(torch, np, L, O, lam, mode, steps, warmup):
            "k_kron_hbm_frac": 8.0 * plan.nnz / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "parity_sample_relF": _sample_parity(O, lam, plan, vals, rowptr, n_rows=100)}
     del vals, rowptr, colind
+    torch.cuda.empty_cache()
+    return res
+
+
+def _batch_workload(torch, np, L, W, O, wave_gb, reps):
+    """The 256 uneven laminates, bucket sets, waves of at most wave_gb GiB of
+    values + scratch, every wave captured in one HIP graph; one replay = the
+    whole batch (each wave's values land in the same buffer, in turn)."""
+    lams = W.batch_laminates()
+    t0 = time.perf_counter()
+    B = L.BatchPlan(lams, set_mode="bucket", wave_bytes=wave_gb << 30)
+    C_all, th_all = B.pack()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    buf = torch.empty(B.max_wave_vals, dtype=torch.float64, device="cuda")
+    for w in range(B.n_waves):
+        B.assemble_wave(w, C_all, th_all, buf)
+    B.check()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for w in range(B.n_waves):
+            B.assemble_wave(w, C_all, th_all, buf)
+    g.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    B.check()
+    # sampled rows of three laminates of the last wave (the buffer holds it)
+    rng = np.random.default_rng(11)
+    last = [i for i in range(B.n) if B.wave[i] == B.n_waves - 1]
+    errs = []
+    for i in [last[0], last[len(last) // 2], last[-1]]:
+        rp, _ = B.pattern(i)
+        rp = rp.cpu().numpy()
+        rows = np.unique(rng.choice(B.n_rows[i], size=30, replace=False))
+        _, _, ref = O.assemble_rows(lams[i], rows)
+        idx = np.concatenate([np.arange(rp[r], rp[r + 1]) for r in rows]) + B.vals_offset[i]
+        got = buf[torch.tensor(idx, device="cuda")].cpu().numpy()
+        errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+    res = {"laminates": B.n, "waves": B.n_waves, "wave_gib": wave_gb, "nnz": B.total_nnz,
+           "ms_per_batch": ms, "nnz_per_s": B.total_nnz / (ms * 1e-3),
+           "hbm_frac_of_value_writes": 8.0 * B.total_nnz / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "setup_s": round(setup_s, 2), "graph": True, "parity_sample_relF": max(errs)}
+    del g, buf, B, C_all, th_all
     torch.cuda.empty_cache()
     return res
 
@@ -198,6 +250,8 @@ def main():
     if not args.no_extra:
         extra["p3_128x128_128ply"] = _fast_workload(torch, np, L, O, W.config_p3_128x128_128ply(), "bucket",
                                                      max(5, args.steps // 2), args.warmup)
+    if not args.no_extra and not args.no_batch:
+        extra["batch_256_uneven"] = _batch_workload(torch, np, L, W, O, args.batch_wave_gib, max(2, args.steps // 10))
     out["extra"] = extra
 
     if args.calibrate_copy_mib:

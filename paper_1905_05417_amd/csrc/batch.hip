@@ -21,8 +21,8 @@
 // scatter item whose laminate's 2D items are not all finished waits on that
 // laminate's completion counter.  Those items are earlier in the queue, so
 // they were taken by running blocks, which wait on nothing; every wait ends.
-// The wait is also bounded: if the bound is ever reached the batch error flag
-// is set and the item skipped.  Completion is released and acquired at agent
+// The wait is also bounded in time: past the bound the batch error flag is set,
+// the item skipped, and every later wait of the launch returns at once.  Completion is released and acquired at agent
 // scope (the per-XCD L2s are written back / invalidated by those fences).
 #include <hip/hip_runtime.h>
 
@@ -55,11 +55,13 @@ struct lam_batch {
   std::vector<int4> items;               // all waves, concatenated
   int64_t lds_bytes = 0;
   int grid = 2048;  // persistent blocks
+  mutable long long wall_khz = 100000;  // device constant-clock rate, read at upload
 };
 
 namespace {
 
 constexpr int BATCH_THREADS = 256;
+constexpr int LAM_BATCH_WAIT_MS = 500;  // a dependency wait longer than this is an error
 constexpr int ITEM_ROTATE = 0, ITEM_Q1D = 1, ITEM_P2D = 2, ITEM_KRON = 3;
 
 int64_t a256(int64_t x) { return (x + 255) & ~int64_t(255); }
@@ -79,17 +81,24 @@ struct BatchArgs {
   int *counters;  // [0] queue head, [1] error flag, then per laminate: 2D items done
   const double *C_all, *th_all;
   double *vals;
-  int spin_limit;
+  long long wait_ticks;  // longest wait of one item, in wall-clock ticks
 };
 
 __device__ inline int *lam_counter(const BatchArgs &a, int lam) { return a.counters + 2 + lam; }
 
-// Thread 0: wait until *c >= target (bounded); returns 0 if the bound was hit.
-__device__ inline int wait_at_least(int *c, int target, int limit) {
-  int spins = 0;
-  while (__hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-    __builtin_amdgcn_s_sleep(4);
-    if (++spins > limit) return 0;
+// Thread 0: wait until *c >= target.  Polls with relaxed loads (no cache
+// invalidation per poll: the caller's block issues one acquire fence after
+// the wait) and gives up, setting the sticky error flag, after `ticks` of the
+// constant-rate clock or as soon as any other wait of the launch has given up.
+__device__ inline int wait_at_least(int *c, int target, int *err, long long ticks) {
+  const long long t0 = wall_clock64();
+  while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return 0;
+    if (wall_clock64() - t0 > ticks) {
+      atomicOr(err, 1);
+      return 0;
+    }
+    __builtin_amdgcn_s_sleep(2);
   }
   return 1;
 }
@@ -112,41 +121,47 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_prep(BatchArgs a, const
   }
 }
 
+// Control flow around every barrier is uniform and visibly so to the
+// compiler: the item index, its fields and the wait result are broadcast
+// through LDS and read into scalar registers (readfirstlane), and each
+// iteration starts with a barrier, so the single-thread regions (the queue
+// and counter atomics) never sit next to each other across the loop's
+// back-edge.  Otherwise the structurizer may turn the loop into nested
+// exec-masked loops in which the other lanes of thread 0's wave re-enter the
+// loop-top barrier without thread 0.
 __global__ void __launch_bounds__(BATCH_THREADS) k_batch(BatchArgs a) {
   extern __shared__ double lds[];
   __shared__ int s_item, s_ok;
   const int tid = threadIdx.x;
   for (;;) {
+    __syncthreads();  // the previous item is finished by every thread (LDS reuse)
     if (tid == 0) s_item = atomicAdd(a.counters, 1);
     __syncthreads();
-    const int it = s_item;
-    if (it >= a.n_items) break;  // uniform: every thread read the same s_item
-    const int4 w = a.items[it];
-    const int lam = w.x;
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    if (it >= a.n_items) break;
+    const int4 wv = a.items[it];
+    const int lam = __builtin_amdgcn_readfirstlane(wv.x), type = __builtin_amdgcn_readfirstlane(wv.y);
+    const int wz = __builtin_amdgcn_readfirstlane(wv.z), ww = __builtin_amdgcn_readfirstlane(wv.w);
     const Dev &d = a.devs[lam];
-    if (w.y == ITEM_P2D) {
-      const int64_t k = (int64_t)w.z * BATCH_THREADS + tid;
+    if (type == ITEM_P2D) {
+      const int64_t k = (int64_t)wz * BATCH_THREADS + tid;
       if (k < d.nnz2) lamdev::item_p2d(d, d.Ec, d.P, d.M, k, 1);
       // completion: this thread's P writes visible device-wide, then count the item
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __syncthreads();
       if (tid == 0) __hip_atomic_fetch_add(lam_counter(a, lam), 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      if (tid == 0) {
-        const int ok = wait_at_least(lam_counter(a, lam), a.meta[lam].n_p_items, a.spin_limit);
-        if (!ok) atomicOr(a.counters + 1, 1);
-        s_ok = ok;
-      }
+      if (tid == 0) s_ok = wait_at_least(lam_counter(a, lam), a.meta[lam].n_p_items, a.counters + 1, a.wait_ticks);
       __syncthreads();
+      const int ok = __builtin_amdgcn_readfirstlane(s_ok);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      if (s_ok) {
+      if (ok) {
         double *vals = a.vals + a.meta[lam].vals_off;
         if (d.kron_nsc == 1)
-          lamdev::item_kron_reg<1>(d, d.Qc, vals, w.z, w.w, lds, tid, BATCH_THREADS);
+          lamdev::item_kron_reg<1>(d, d.Qc, vals, wz, ww, lds, tid, BATCH_THREADS);
         else
-          lamdev::item_kron_reg<2>(d, d.Qc, vals, w.z, w.w, lds, tid, BATCH_THREADS);
+          lamdev::item_kron_reg<2>(d, d.Qc, vals, wz, ww, lds, tid, BATCH_THREADS);
       }
-      __syncthreads();  // LDS staging and s_ok are reused by the next item
     }
   }
 }
@@ -236,9 +251,10 @@ extern "C" LAM_API lam_status lam_batch_create(int32_t n, const lam_laminate_des
       for (int t = 0; t < p->n_tiles; ++t)
         for (int ch = 0; ch < p->n_chunks; ++ch) B->items.push_back(make_int4(i, ITEM_KRON, t, ch));
     };
-    p2d(f);
+    // 2D items run two laminates ahead of the scatter that needs them
+    for (int i = f; i < std::min(f + 2, f + c); ++i) p2d(i);
     for (int i = f; i < f + c; ++i) {
-      if (i + 1 < f + c) p2d(i + 1);
+      if (i + 2 < f + c) p2d(i + 2);
       kron(i);
     }
     B->wave_items_n.push_back((int)((int64_t)B->items.size() - B->wave_items_off.back()));
@@ -305,6 +321,11 @@ extern "C" LAM_API lam_status lam_batch_upload(const lam_batch *b, void *ws, int
     meta[i].n_p_items = (int)((p->nnz2 + BATCH_THREADS - 1) / BATCH_THREADS);
     meta[i].pad = 0;
   }
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+      khz <= 0)
+    return LAM_EHIP;
+  b->wall_khz = khz;
   // host arrays must outlive the asynchronous copies: copy synchronously
   if (hipMemcpyAsync(base + b->devs_off, devs.data(), sizeof(Dev) * devs.size(), hipMemcpyHostToDevice, s) !=
           hipSuccess ||
@@ -342,7 +363,7 @@ extern "C" LAM_API lam_status lam_batch_assemble(const lam_batch *b, void *ws, i
   a.C_all = C_all;
   a.th_all = theta_all;
   a.vals = vals_wave;
-  a.spin_limit = 1 << 24;
+  a.wait_ticks = (long long)b->wall_khz * LAM_BATCH_WAIT_MS;
   const int nc = 2 + b->n;
   hipLaunchKernelGGL(k_batch_reset, dim3((nc + 255) / 256), dim3(256), 0, s, a.counters, nc);
   void *prof = lam::profile_begin(3, stream);
