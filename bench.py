@@ -31,6 +31,12 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, spec
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector / matrix, spec
+# Algorithmic flops of the standard 3D assembly (Sec. 2.4): per 3D element
+# with n_f local functions and n_q Gauss points, 2 n_q (54 n_f + 27 n_f (n_f+1)/2)
+# (D B for every function, then B^T (D B) for the symmetric half of the local
+# pairs).  Degree 2 in-plane, layerwise degree 2, 3x3x3 points on the 64x64
+# 32-ply plate: 131,072 elements x 629,856 = 8.26e10 flops, 340 per nonzero.
+STD_FLOPS_PER_NNZ_P2Q2 = 340.0
 
 
 def _parse():
@@ -114,6 +120,45 @@ def _fast_workload(torch, np, L, O, lam, mode, steps, warmup):
            "k_kron_hbm_frac": 8.0 * plan.nnz / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "parity_sample_relF": _sample_parity(O, lam, plan, vals, rowptr, n_rows=100)}
     del vals, rowptr, colind
+    torch.cuda.empty_cache()
+    return res
+
+
+def _adjoint_workload(torch, np, L, W, O, steps, warmup):
+    """96x96 degree-2 plate, 64 plies of seeded angles and 4 materials: fast
+    forward (bucket and harmonic5 sets) and lam_adjoint for L = u^T K u with
+    G = u[row] u[col] formed beforehand (not timed)."""
+    lam = W.config_adjoint_p2_96x96_64ply()
+    C = torch.tensor(np.asarray(lam.C), device="cuda")
+    th = torch.tensor(np.asarray(lam.theta), device="cuda")
+    res = {"workload": lam.name}
+    for mode in ("bucket", "harmonic5"):
+        plan = L.Plan(lam, set_mode=mode)
+        vals = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
+        ms, ms_k = _time_steps(torch, lambda: plan.assemble(C, th, out=vals), steps, warmup, L, "assemble")
+        res["forward_" + mode] = {"sets": plan.n_sets, "ms_per_step": ms, "nnz_per_s": plan.nnz / (ms * 1e-3),
+                                  "k_kron_ms": ms_k}
+        del vals, plan
+        torch.cuda.empty_cache()
+    plan = L.Plan(lam, set_mode="bucket")
+    rowptr, colind = plan.pattern()
+    u = torch.tensor(np.random.default_rng(W.SEED_U).standard_normal(plan.n_rows), device="cuda")
+    rows = torch.repeat_interleave(torch.arange(plan.n_rows, device="cuda"), rowptr[1:] - rowptr[:-1])
+    G = u[rows] * u[colind.long()]
+    del rows, colind
+    torch.cuda.empty_cache()
+    out = {}
+    ms, ms_k = _time_steps(torch, lambda: out.update(g=plan.adjoint(C, th, G)), steps, warmup, L, "adjoint")
+    gC, gT = out["g"]
+    dD = O.grad_D_uu(lam, u.cpu().numpy())
+    gC_ref, gT_ref = O.grad_material(lam, dD)
+    err = max(float(np.abs(gC.cpu().numpy() - gC_ref).max() / np.abs(gC_ref).max()),
+              float(np.abs(gT.cpu().numpy() - gT_ref).max() / np.abs(gT_ref).max()))
+    res.update({"nnz": plan.nnz, "adjoint_ms": ms, "adjoint_stream_kernel_ms": ms_k,
+                "adjoint_grad_read_GBps": 8.0 * plan.nnz / (ms_k * 1e-3) / 1e9,
+                "adjoint_hbm_frac": 8.0 * plan.nnz / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "adjoint_rel_err_vs_oracle": err})
+    del G, u, plan, rowptr
     torch.cuda.empty_cache()
     return res
 
@@ -241,8 +286,12 @@ def main():
         try:
             ms_std, ms_std_k = _time_steps(torch, lambda: plan.assemble_standard(C, th, out=vals),
                                            max(3, args.steps // 4), 1, L, "standard")
+            flops = STD_FLOPS_PER_NNZ_P2Q2 * plan.nnz
             extra["standard_same_plate"] = {"nnz_per_s": plan.nnz / (ms_std * 1e-3), "ms_per_step": ms_std,
-                                            "speedup_fast_vs_standard": ms_std / ms_step}
+                                            "speedup_fast_vs_standard": ms_std / ms_step,
+                                            "element_kernel_ms": ms_std_k,
+                                            "fp64_tflops_algorithmic": flops / (ms_std * 1e-3) / 1e12,
+                                            "fp64_frac": flops / (ms_std * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
         except L.LamError as e:
             extra["standard_same_plate"] = {"skipped": str(e)}
     del vals, rowptr, colind
@@ -250,6 +299,8 @@ def main():
     if not args.no_extra:
         extra["p3_128x128_128ply"] = _fast_workload(torch, np, L, O, W.config_p3_128x128_128ply(), "bucket",
                                                      max(5, args.steps // 2), args.warmup)
+    if not args.no_extra:
+        extra["adjoint_p2_96x96_64ply"] = _adjoint_workload(torch, np, L, W, O, max(5, args.steps // 2), args.warmup)
     if not args.no_extra and not args.no_batch:
         extra["batch_256_uneven"] = _batch_workload(torch, np, L, W, O, args.batch_wave_gib, max(2, args.steps // 10))
     out["extra"] = extra

@@ -181,16 +181,17 @@ LAM_API lam_status lam_batch_upload(const lam_batch *batch, void *ws, int64_t ws
 /* CSR pattern of laminate i, as lam_pattern. */
 LAM_API lam_status lam_batch_pattern(const lam_batch *batch, const void *ws, int64_t ws_bytes, int32_t i,
                                      int64_t *rowptr, int32_t *colind, void *stream);
-/* Assembles every laminate of wave `wave`: a small kernel clearing the queue
- * counters, then the persistent kernel.  Asynchronous; may be captured in a
- * HIP graph (no memset, no allocation, no host synchronization).  Waves
- * share the scratch arena: waves on different streams must not overlap. */
+/* Assembles every laminate of wave `wave`: a kernel clearing the queue heads,
+ * the rotation / 1D-coefficient kernel, the 2D-operator kernel over all the
+ * wave's laminates, then the persistent scatter kernel.  Asynchronous; may be
+ * captured in a HIP graph (no memset, no allocation, no host
+ * synchronization).  Waves share the scratch arena: waves on different
+ * streams must not overlap. */
 LAM_API lam_status lam_batch_assemble(const lam_batch *batch, void *ws, int64_t ws_bytes, int32_t wave,
                                       const double *C_all, const double *theta_all, double *vals_wave,
                                       int64_t vals_len, void *stream);
-/* Reads the batch error flag of the last wave (synchronizes stream): nonzero
- * if any dependency wait of the persistent kernel gave up (its item was
- * skipped and that wave's values are incomplete). */
+/* Checks the last assembled wave (synchronizes stream): *error is nonzero if
+ * the persistent scatter left any of the wave's items untaken. */
 LAM_API lam_status lam_batch_check(const lam_batch *batch, const void *ws, int64_t ws_bytes, int32_t *error,
                                    void *stream);
 

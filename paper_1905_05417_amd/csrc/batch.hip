@@ -1,5 +1,5 @@
-// batch.hip -- many laminates of uneven size, degree and ply count assembled
-// by one persistent kernel per memory wave.
+// batch.hip -- many laminates of uneven size, degree and ply count,
+// assembled wave by wave with one persistent scatter launch per memory wave.
 //
 // Every laminate keeps its own plan (tables, tiles, chunks, sets).  Its
 // constant tables sit in the batch workspace for the whole batch; its scratch
@@ -7,26 +7,26 @@
 // reused by every wave; its CSR values go to the caller's wave buffer.  A
 // wave is a run of laminates whose values and scratch fit the budget.
 //
-// A wave runs as three launches on one stream (all capturable in a HIP graph):
-//   k_batch_reset  clears the queue head, error flag and completion counters;
+// A wave runs as four launches on one stream (all capturable in a HIP graph):
+//   k_batch_reset  clears the eight queue heads (a kernel, not a memset);
 //   k_batch_prep   one block per small item: rotated tensors / harmonics of a
-//                  laminate's sets, and 256 of its folded 1D coefficients;
-//   k_batch        the persistent kernel, over a queue of
-//                    p2d(b, i)  - 256 in-plane nonzeros of laminate b's 2D operators
-//                    kron(b, L) - one scatter tile x chunk of b (needs every p2d(b, .))
-//                  ordered p2d(b0), p2d(b1), kron(b0), p2d(b2), kron(b1), ...
-//                  so the 2D work (arithmetic bound) of the next laminate
-//                  overlaps the scatter (store bound) of the previous one.
-// Blocks of the persistent kernel take items from an atomic head counter; a
-// scatter item whose laminate's 2D items are not all finished waits on that
-// laminate's completion counter.  Those items are earlier in the queue, so
-// they were taken by running blocks, which wait on nothing; every wait ends.
-// The wait is also bounded in time: past the bound the batch error flag is set,
-// the item skipped, and every later wait of the launch returns at once.  Completion is released and acquired at agent
-// scope (the per-XCD L2s are written back / invalidated by those fences).
+//                  laminate's sets, or 256 of its folded 1D coefficients;
+//   k_batch_p2d    one block per 256 in-plane nonzeros of any laminate: the 2D
+//                  operators P of every set;
+//   k_batch_kron   the persistent scatter.  The wave's scatter items (one tile
+//                  of whole in-plane rows x one chunk of thickness rows of one
+//                  laminate, in laminate, tile, chunk order) are cut into eight
+//                  contiguous ranges of equal output bytes, one per XCD; the
+//                  blocks of an XCD take items of their range from that range's
+//                  atomic head, so each XCD writes long contiguous runs of the
+//                  CSR values (no cache line written from two L2s) and the
+//                  hardware dispatcher plus the heads balance uneven items.
+// Dependencies between the phases are stream order only: no block waits on
+// another, so the persistent kernel needs no spin or fence.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -50,66 +50,56 @@ struct lam_batch {
   // device layout of the batch workspace
   int64_t tables_bytes = 0, arena_off = 0, arena_bytes = 0;
   int64_t devs_off = 0, meta_off = 0, items_off = 0, counters_off = 0, total = 0;
-  std::vector<int64_t> wave_prep_off, wave_items_off;  // first prep / queue item of each wave
-  std::vector<int> wave_prep_n, wave_items_n;
-  std::vector<int4> items;               // all waves, concatenated
+  // per wave: first item and count of the prep, 2D and scatter lists, and the
+  // scatter list's eight per-XCD ranges (9 bounds, relative to its first item)
+  std::vector<int64_t> wave_prep_off, wave_p2d_off, wave_kron_off;
+  std::vector<int> wave_prep_n, wave_p2d_n, wave_kron_n;
+  std::vector<int> wave_xcd;  // 9 per wave
+  std::vector<int4> items;    // all lists of all waves, concatenated
   int64_t lds_bytes = 0;
-  int grid = 2048;  // persistent blocks
-  mutable long long wall_khz = 100000;  // device constant-clock rate, read at upload
+  int grid = 1024;  // persistent scatter blocks (a multiple of 8)
+  bool persistent = false;  // scatter as a persistent queue kernel (else one block per item)
+  mutable int last_wave = -1;  // wave of the last lam_batch_assemble (for lam_batch_check)
 };
 
 namespace {
 
 constexpr int BATCH_THREADS = 256;
-constexpr int LAM_BATCH_WAIT_MS = 500;  // a dependency wait longer than this is an error
-constexpr int ITEM_ROTATE = 0, ITEM_Q1D = 1, ITEM_P2D = 2, ITEM_KRON = 3;
+constexpr int ITEM_ROTATE = 0, ITEM_Q1D = 1;
+constexpr int N_XCD = 8;  // blocks are dispatched round-robin over the 8 XCDs
+constexpr int N_GROUPS = 4;  // scatter block sizes 64, 128, 192, 256
 
 int64_t a256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
+// Host view of a plan table (the image uploaded to the workspace).
+template <class T>
+const T *table(const lam_plan *p, const lam::Region &r) {
+  return reinterpret_cast<const T *>(p->image.data() + r.off);
+}
+
 // Per-laminate metadata the kernel reads next to its Dev.
 struct Meta {
-  int64_t c_off, t_off, vals_off;
-  int n_p_items;
-  int pad;
+  int64_t c_off, t_off, vals_off, pad;
 };
 
 struct BatchArgs {
   const Dev *__restrict__ devs;
   const Meta *__restrict__ meta;
-  const int4 *__restrict__ items;
+  const int4 *__restrict__ items;  // this launch's list
   int n_items;
-  int *counters;  // [0] queue head, [1] error flag, then per laminate: 2D items done
+  int xcd_bound[N_XCD + 1];        // scatter: per-XCD item ranges
+  int *heads;                      // scatter: one head per XCD
   const double *C_all, *th_all;
   double *vals;
-  long long wait_ticks;  // longest wait of one item, in wall-clock ticks
 };
 
-__device__ inline int *lam_counter(const BatchArgs &a, int lam) { return a.counters + 2 + lam; }
-
-// Thread 0: wait until *c >= target.  Polls with relaxed loads (no cache
-// invalidation per poll: the caller's block issues one acquire fence after
-// the wait) and gives up, setting the sticky error flag, after `ticks` of the
-// constant-rate clock or as soon as any other wait of the launch has given up.
-__device__ inline int wait_at_least(int *c, int target, int *err, long long ticks) {
-  const long long t0 = wall_clock64();
-  while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return 0;
-    if (wall_clock64() - t0 > ticks) {
-      atomicOr(err, 1);
-      return 0;
-    }
-    __builtin_amdgcn_s_sleep(2);
-  }
-  return 1;
-}
-
-__global__ void k_batch_reset(int *counters, int n) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) counters[i] = 0;
+__global__ void k_batch_reset(int *heads) {
+  if (threadIdx.x < N_XCD) heads[threadIdx.x] = 0;
 }
 
 // One block per prep item: {lam, ITEM_ROTATE, 0, 0} or {lam, ITEM_Q1D, i, 0}.
-__global__ void __launch_bounds__(BATCH_THREADS) k_batch_prep(BatchArgs a, const int4 *__restrict__ items) {
-  const int4 w = items[blockIdx.x];
+__global__ void __launch_bounds__(BATCH_THREADS) k_batch_prep(BatchArgs a) {
+  const int4 w = a.items[blockIdx.x];
   const Dev &d = a.devs[w.x];
   const Meta m = a.meta[w.x];
   const double *th = a.th_all + m.t_off;
@@ -121,49 +111,51 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_prep(BatchArgs a, const
   }
 }
 
-// Control flow around every barrier is uniform and visibly so to the
-// compiler: the item index, its fields and the wait result are broadcast
-// through LDS and read into scalar registers (readfirstlane), and each
-// iteration starts with a barrier, so the single-thread regions (the queue
-// and counter atomics) never sit next to each other across the loop's
-// back-edge.  Otherwise the structurizer may turn the loop into nested
-// exec-masked loops in which the other lanes of thread 0's wave re-enter the
-// loop-top barrier without thread 0.
-__global__ void __launch_bounds__(BATCH_THREADS) k_batch(BatchArgs a) {
+// One block per 2D item {lam, i, 0, 0}: in-plane nonzeros 256 i .. 256 i + 255.
+__global__ void __launch_bounds__(BATCH_THREADS) k_batch_p2d(BatchArgs a) {
+  const int4 w = a.items[blockIdx.x];
+  const Dev &d = a.devs[w.x];
+  const int64_t k = (int64_t)w.y * BATCH_THREADS + threadIdx.x;
+  if (k < d.nnz2) lamdev::item_p2d(d, d.Ec, d.P, d.M, k, 1);
+}
+
+// Persistent scatter over items {lam, tile, chunk, 0}.  Control flow around
+// the barriers is uniform and visibly so to the compiler (the item index and
+// fields are read into scalar registers, each iteration opens with a
+// barrier): otherwise the loop may be compiled into nested exec-masked loops
+// in which lanes re-enter the loop-top barrier without the thread that
+// refreshes the item index.
+__global__ void __launch_bounds__(BATCH_THREADS) k_batch_kron(BatchArgs a) {
   extern __shared__ double lds[];
-  __shared__ int s_item, s_ok;
+  __shared__ int s_item;
   const int tid = threadIdx.x;
+  const int x = (int)(blockIdx.x % N_XCD);
+  const int first = a.xcd_bound[x], count = a.xcd_bound[x + 1] - first;
   for (;;) {
-    __syncthreads();  // the previous item is finished by every thread (LDS reuse)
-    if (tid == 0) s_item = atomicAdd(a.counters, 1);
+    __syncthreads();  // the previous item's LDS staging is no longer read
+    if (tid == 0) s_item = atomicAdd(a.heads + x, 1);
     __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(s_item);
-    if (it >= a.n_items) break;
-    const int4 wv = a.items[it];
-    const int lam = __builtin_amdgcn_readfirstlane(wv.x), type = __builtin_amdgcn_readfirstlane(wv.y);
-    const int wz = __builtin_amdgcn_readfirstlane(wv.z), ww = __builtin_amdgcn_readfirstlane(wv.w);
+    const int j = __builtin_amdgcn_readfirstlane(s_item);
+    if (j >= count) break;
+    const int4 wv = a.items[first + j];
+    const int lam = __builtin_amdgcn_readfirstlane(wv.x);
+    const int tile = __builtin_amdgcn_readfirstlane(wv.y), ch = __builtin_amdgcn_readfirstlane(wv.z);
     const Dev &d = a.devs[lam];
-    if (type == ITEM_P2D) {
-      const int64_t k = (int64_t)wz * BATCH_THREADS + tid;
-      if (k < d.nnz2) lamdev::item_p2d(d, d.Ec, d.P, d.M, k, 1);
-      // completion: this thread's P writes visible device-wide, then count the item
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __syncthreads();
-      if (tid == 0) __hip_atomic_fetch_add(lam_counter(a, lam), 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      if (tid == 0) s_ok = wait_at_least(lam_counter(a, lam), a.meta[lam].n_p_items, a.counters + 1, a.wait_ticks);
-      __syncthreads();
-      const int ok = __builtin_amdgcn_readfirstlane(s_ok);
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      if (ok) {
-        double *vals = a.vals + a.meta[lam].vals_off;
-        if (d.kron_nsc == 1)
-          lamdev::item_kron_reg<1>(d, d.Qc, vals, wz, ww, lds, tid, BATCH_THREADS);
-        else
-          lamdev::item_kron_reg<2>(d, d.Qc, vals, wz, ww, lds, tid, BATCH_THREADS);
-      }
-    }
+    double *vals = a.vals + a.meta[lam].vals_off;
+    lamdev::item_kron_reg<2>(d, d.Qc, vals, tile, ch, lds, tid, (int)blockDim.x);
   }
+}
+
+// The same scatter without a queue loop: block b takes item b / 8 of XCD
+// b % 8's range, the hardware dispatcher being the queue.
+__global__ void __launch_bounds__(BATCH_THREADS) k_batch_kron_grid(BatchArgs a) {
+  extern __shared__ double lds[];
+  const int x = (int)(blockIdx.x % N_XCD), j = (int)(blockIdx.x / N_XCD);
+  const int first = a.xcd_bound[x], count = a.xcd_bound[x + 1] - first;
+  if (j >= count) return;
+  const int4 wv = a.items[first + j];
+  const Dev &d = a.devs[wv.x];
+  lamdev::item_kron_reg<2>(d, d.Qc, a.vals + a.meta[wv.x].vals_off, wv.y, wv.z, lds, threadIdx.x, (int)blockDim.x);
 }
 
 }  // namespace
@@ -181,17 +173,18 @@ extern "C" LAM_API lam_status lam_batch_create(int32_t n, const lam_laminate_des
   lam_batch *B = new (std::nothrow) lam_batch();
   if (!B) return LAM_EINVAL;
   B->n = n;
+  if (const char *e = std::getenv("LAMASM_BATCH_KRON")) B->persistent = std::strcmp(e, "persistent") == 0;
   int64_t cbytes = 0, ctot = 0, ttot = 0;
   for (int i = 0; i < n; ++i) {
     lam_plan *p = nullptr;
-    lam_status st = lam_plan_create(&descs[i], &p);
+    lam_status st = lam::plan_create(&descs[i], 2, &p);
     if (st != LAM_OK) {
       lam_batch_destroy(B);
       return st;
     }
     B->plans.push_back(p);
-    // the fused kernel holds at most two set slots per scatter thread
-    if (p->kron_nsc < 1 || p->kron_nsc > 2 || 3 * p->tile_k > BATCH_THREADS) {
+    // the scatter kernel holds exactly two set slots per thread
+    if (p->kron_nsc != 2 || 3 * p->tile_k > BATCH_THREADS) {
       lam_batch_destroy(B);
       return LAM_EUNSUP;
     }
@@ -229,7 +222,7 @@ extern "C" LAM_API lam_status lam_batch_create(int32_t n, const lam_laminate_des
     B->wave_count.back() += 1;
     arena = std::max(arena, scur);
   }
-  // work items per wave: the prep items, then the persistent queue
+  // work lists per wave: prep items, 2D items, scatter items (+ per-XCD ranges)
   for (int w = 0; w < B->n_waves; ++w) {
     const int f = B->wave_first[w], c = B->wave_count[w];
     B->wave_prep_off.push_back((int64_t)B->items.size());
@@ -241,25 +234,39 @@ extern "C" LAM_API lam_status lam_batch_create(int32_t n, const lam_laminate_des
         B->items.push_back(make_int4(i, ITEM_Q1D, (int)j, 0));
     }
     B->wave_prep_n.push_back((int)((int64_t)B->items.size() - B->wave_prep_off.back()));
-    B->wave_items_off.push_back((int64_t)B->items.size());
-    auto p2d = [&](int i) {
-      const int np = (int)((B->plans[i]->nnz2 + BATCH_THREADS - 1) / BATCH_THREADS);
-      for (int j = 0; j < np; ++j) B->items.push_back(make_int4(i, ITEM_P2D, j, 0));
-    };
-    auto kron = [&](int i) {
-      const lam_plan *p = B->plans[i];
-      for (int t = 0; t < p->n_tiles; ++t)
-        for (int ch = 0; ch < p->n_chunks; ++ch) B->items.push_back(make_int4(i, ITEM_KRON, t, ch));
-    };
-    // 2D items run two laminates ahead of the scatter that needs them
-    for (int i = f; i < std::min(f + 2, f + c); ++i) p2d(i);
+    B->wave_p2d_off.push_back((int64_t)B->items.size());
     for (int i = f; i < f + c; ++i) {
-      if (i + 2 < f + c) p2d(i + 2);
-      kron(i);
+      const int np = (int)((B->plans[i]->nnz2 + BATCH_THREADS - 1) / BATCH_THREADS);
+      for (int j = 0; j < np; ++j) B->items.push_back(make_int4(i, j, 0, 0));
     }
-    B->wave_items_n.push_back((int)((int64_t)B->items.size() - B->wave_items_off.back()));
+    B->wave_p2d_n.push_back((int)((int64_t)B->items.size() - B->wave_p2d_off.back()));
+    // scatter items grouped by block size (the laminate's scatter threads),
+    // each group cut into eight ranges of equal output bytes
+    for (int T = 64; T <= BATCH_THREADS; T += 64) {
+      B->wave_kron_off.push_back((int64_t)B->items.size());
+      std::vector<double> cum(1, 0.0);  // output doubles before each item
+      for (int i = f; i < f + c; ++i) {
+        const lam_plan *p = B->plans[i];
+        if (p->kron_threads != T) continue;
+        const int *tiles = table<int>(p, p->L.tiles), *zrow = table<int>(p, p->L.zrow);
+        const int *chunk = table<int>(p, p->L.chunk_ptr);
+        for (int t = 0; t < p->n_tiles; ++t)
+          for (int ch = 0; ch < p->n_chunks; ++ch) {
+            B->items.push_back(make_int4(i, t, ch, 0));
+            cum.push_back(cum.back() + 9.0 * (tiles[t + 1] - tiles[t]) * (zrow[chunk[ch + 1]] - zrow[chunk[ch]]));
+          }
+      }
+      const int nk = (int)cum.size() - 1;
+      B->wave_kron_n.push_back(nk);
+      int j = 0;
+      for (int x = 0; x <= N_XCD; ++x) {
+        const double target = cum.back() * x / N_XCD;
+        while (j < nk && cum[j] < target) ++j;
+        B->wave_xcd.push_back(x == N_XCD ? nk : j);
+      }
+    }
   }
-  // batch workspace: tables | arena | Dev[n] | Meta[n] | items | counters
+  // batch workspace: tables | arena | Dev[n] | Meta[n] | items | queue heads
   int64_t off = a256(B->tables_bytes);
   B->arena_off = off;
   B->arena_bytes = a256(arena);
@@ -271,7 +278,7 @@ extern "C" LAM_API lam_status lam_batch_create(int32_t n, const lam_laminate_des
   B->items_off = off;
   off = a256(off + (int64_t)sizeof(int4) * B->items.size());
   B->counters_off = off;
-  off = a256(off + (int64_t)sizeof(int) * (2 + n));
+  off = a256(off + (int64_t)sizeof(int) * N_XCD);
   B->total = off;
   *out = B;
   return LAM_OK;
@@ -318,14 +325,8 @@ extern "C" LAM_API lam_status lam_batch_upload(const lam_batch *b, void *ws, int
     meta[i].c_off = b->c_off[i];
     meta[i].t_off = b->t_off[i];
     meta[i].vals_off = b->vals_off[i];
-    meta[i].n_p_items = (int)((p->nnz2 + BATCH_THREADS - 1) / BATCH_THREADS);
     meta[i].pad = 0;
   }
-  int dev = 0, khz = 0;
-  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
-      khz <= 0)
-    return LAM_EHIP;
-  b->wall_khz = khz;
   // host arrays must outlive the asynchronous copies: copy synchronously
   if (hipMemcpyAsync(base + b->devs_off, devs.data(), sizeof(Dev) * devs.size(), hipMemcpyHostToDevice, s) !=
           hipSuccess ||
@@ -354,23 +355,39 @@ extern "C" LAM_API lam_status lam_batch_assemble(const lam_batch *b, void *ws, i
   if (ws_bytes < b->total || vals_len < b->wave_vals[wave]) return LAM_ESIZE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   char *base = static_cast<char *>(ws);
+  const int4 *items = reinterpret_cast<const int4 *>(base + b->items_off);
   BatchArgs a;
   a.devs = reinterpret_cast<const Dev *>(base + b->devs_off);
   a.meta = reinterpret_cast<const Meta *>(base + b->meta_off);
-  a.items = reinterpret_cast<const int4 *>(base + b->items_off) + b->wave_items_off[wave];
-  a.n_items = b->wave_items_n[wave];
-  a.counters = reinterpret_cast<int *>(base + b->counters_off);
+  a.heads = reinterpret_cast<int *>(base + b->counters_off);
   a.C_all = C_all;
   a.th_all = theta_all;
   a.vals = vals_wave;
-  a.wait_ticks = (long long)b->wall_khz * LAM_BATCH_WAIT_MS;
-  const int nc = 2 + b->n;
-  hipLaunchKernelGGL(k_batch_reset, dim3((nc + 255) / 256), dim3(256), 0, s, a.counters, nc);
   void *prof = lam::profile_begin(3, stream);
-  hipLaunchKernelGGL(k_batch_prep, dim3(b->wave_prep_n[wave]), dim3(BATCH_THREADS), 0, s, a,
-                     reinterpret_cast<const int4 *>(base + b->items_off) + b->wave_prep_off[wave]);
-  hipLaunchKernelGGL(k_batch, dim3(b->grid), dim3(BATCH_THREADS), (size_t)b->lds_bytes, s, a);
+  a.items = items + b->wave_prep_off[wave];
+  a.n_items = b->wave_prep_n[wave];
+  hipLaunchKernelGGL(k_batch_prep, dim3(a.n_items), dim3(BATCH_THREADS), 0, s, a);
+  a.items = items + b->wave_p2d_off[wave];
+  a.n_items = b->wave_p2d_n[wave];
+  hipLaunchKernelGGL(k_batch_p2d, dim3(a.n_items), dim3(BATCH_THREADS), 0, s, a);
+  for (int g = 0; g < N_GROUPS; ++g) {
+    const int gi = N_GROUPS * wave + g;
+    if (b->wave_kron_n[gi] == 0) continue;
+    a.items = items + b->wave_kron_off[gi];
+    a.n_items = b->wave_kron_n[gi];
+    for (int x = 0; x <= N_XCD; ++x) a.xcd_bound[x] = b->wave_xcd[(N_XCD + 1) * gi + x];
+    const dim3 block(64 * (g + 1));
+    if (b->persistent) {
+      hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, a.heads);
+      hipLaunchKernelGGL(k_batch_kron, dim3(b->grid), block, (size_t)b->lds_bytes, s, a);
+    } else {
+      int most = 0;
+      for (int x = 0; x < N_XCD; ++x) most = std::max(most, a.xcd_bound[x + 1] - a.xcd_bound[x]);
+      hipLaunchKernelGGL(k_batch_kron_grid, dim3(N_XCD * most), block, (size_t)b->lds_bytes, s, a);
+    }
+  }
   lam::profile_end(prof, stream);
+  b->last_wave = wave;
   return hipGetLastError() == hipSuccess ? LAM_OK : LAM_EHIP;
 }
 
@@ -379,11 +396,19 @@ extern "C" LAM_API lam_status lam_batch_check(const lam_batch *b, const void *ws
   if (!b || !ws || !error) return LAM_EINVAL;
   if (ws_bytes < b->total) return LAM_ESIZE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  int v = 0;
-  if (hipMemcpyAsync(&v, static_cast<const char *>(ws) + b->counters_off + sizeof(int), sizeof(int),
-                     hipMemcpyDeviceToHost, s) != hipSuccess ||
+  int heads[N_XCD] = {0};
+  if (hipMemcpyAsync(heads, static_cast<const char *>(ws) + b->counters_off, sizeof(heads), hipMemcpyDeviceToHost,
+                     s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return LAM_EHIP;
-  *error = v;
+  // every scatter item of the last wave must have been taken from its range
+  *error = 0;
+  if (b->persistent && b->last_wave >= 0) {
+    int g = N_GROUPS - 1;  // the last group launched in that wave
+    while (g > 0 && b->wave_kron_n[N_GROUPS * b->last_wave + g] == 0) --g;
+    const int *xb = &b->wave_xcd[(N_XCD + 1) * (N_GROUPS * b->last_wave + g)];
+    for (int x = 0; x < N_XCD; ++x)
+      if (heads[x] < xb[x + 1] - xb[x]) *error = 1;
+  }
   return LAM_OK;
 }

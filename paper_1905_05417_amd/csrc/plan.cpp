@@ -207,7 +207,11 @@ void put(std::vector<uint8_t> &img, const lam::Region &r, const std::vector<T> &
 
 }  // namespace
 
-extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_plan **out) {
+namespace lam {
+
+// min_nsc: smallest number of set slots of the register-mode scatter (the
+// batched path compiles one slot count for every laminate).
+lam_status plan_create(const lam_laminate_desc *d, int min_nsc, lam_plan **out) {
   if (!d || !out) return LAM_EINVAL;
   *out = nullptr;
   lam_status st;
@@ -431,7 +435,7 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
   int64_t qbudget = 8 * 1024, lds_budget = 80 * 1024;
   if (const char *e = std::getenv("LAMASM_KRON_LDS")) lds_budget = std::max<int64_t>(16 * 1024, std::atoll(e) * 1024);
   if (reg_mode) {
-    int want = std::max(P->maxact, std::min(P->n_sets, nsc_cap));
+    int want = std::max(std::max(P->maxact, std::min(P->n_sets, nsc_cap)), min_nsc);
     sc = want <= 1 ? 1 : want <= 2 ? 2 : want <= 4 ? 4 : 8;
     P->kron_nsc = sc;
   } else {
@@ -735,6 +739,12 @@ extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_pl
   put(img, L.zaslot, zaslot);
   *out = P;
   return LAM_OK;
+}
+
+}  // namespace lam
+
+extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_plan **out) {
+  return lam::plan_create(d, 1, out);
 }
 
 extern "C" LAM_API void lam_plan_destroy(lam_plan *p) { delete p; }
