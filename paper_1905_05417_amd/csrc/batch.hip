@@ -11,8 +11,8 @@
 //   k_batch_reset  clears the eight queue heads (a kernel, not a memset);
 //   k_batch_prep   one block per small item: rotated tensors / harmonics of a
 //                  laminate's sets, or 256 of its folded 1D coefficients;
-//   k_batch_p2d    one block per 256 in-plane nonzeros of any laminate: the 2D
-//                  operators P of every set;
+//   k_batch_p2d    one block per 256 in-plane nonzeros of any laminate: the
+//                  set-independent 2D moments (the scatter contracts P from them);
 //   k_batch_kron   the persistent scatter.  The wave's scatter items (one tile
 //                  of whole in-plane rows x one chunk of thickness rows of one
 //                  laminate, in laminate, tile, chunk order) are cut into eight
@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_p2d(BatchArgs a) {
   const int4 w = a.items[blockIdx.x];
   const Dev &d = a.devs[w.x];
   const int64_t k = (int64_t)w.y * BATCH_THREADS + threadIdx.x;
-  if (k < d.nnz2) lamdev::item_p2d(d, d.Ec, d.P, d.M, k, 1);
+  if (k < d.nnz2) lamdev::item_p2d(d, d.Ec, d.P, d.M, k, 0);  // moments only
 }
 
 // Persistent scatter over items {lam, tile, chunk, 0}.  Control flow around

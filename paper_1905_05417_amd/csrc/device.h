@@ -191,7 +191,7 @@ __device__ inline void bracket_coefficients(const double D[6][6], double *E) {
 // degree <= 4 once NH >= 9).
 constexpr int NH = 12;
 
-__device__ inline void item_rotate_set(const Dev &d, const double *__restrict__ C, const double *__restrict__ theta, int s) {
+__device__ __forceinline__ void item_rotate_set(const Dev &d, const double *__restrict__ C, const double *__restrict__ theta, int s) {
   const double *Cm = C + 36 * d.set_mat[s];
   double D[6][6];
   if (d.set_mode == LAM_SETS_BUCKET) {
@@ -225,7 +225,7 @@ __device__ inline void item_rotate_set(const Dev &d, const double *__restrict__ 
 // pushed through DF^{-T} (grad V = DF^{-T}(dS1,dS2,0), W = DF^{-T}(0,0,S))
 // into M_ab[k][l] = int (G_a^i)_k (G_b^j)_l |DF|.  Because each set's
 // material is constant over the plane, P_{s,ab}[r][t] = sum_kl M_ab[k][l] E_s[k][l][r][t].
-__device__ inline void item_p2d(const Dev &d, const double *__restrict__ Ec, double *__restrict__ Pt,
+__device__ __forceinline__ void item_p2d(const Dev &d, const double *__restrict__ Ec, double *__restrict__ Pt,
                                 double *__restrict__ Mt, int64_t k, int write_p) {
   const int is = d.krow[k], js = d.kcol[k];
   const int i1 = is % d.n1, i2 = is / d.n1, j1 = js % d.n1, j2 = js / d.n1;
@@ -315,7 +315,7 @@ __device__ inline void item_p2d(const Dev &d, const double *__restrict__ Ec, dou
 // does not act on the pair); LDS mode: one per set active on the row
 __device__ inline int q1d_width(const Dev &d) { return d.kron_nsc > 0 ? d.kron_nsc : d.maxact; }
 
-__device__ inline void item_q1d(const Dev &d, const double *__restrict__ theta, int64_t idx) {
+__device__ __forceinline__ void item_q1d(const Dev &d, const double *__restrict__ theta, int64_t idx) {
   const int width = q1d_width(d);
   const int zk = (int)(idx / width), j = (int)(idx % width);
   const int it = d.zkrow[zk], jt = d.zcol[zk];
@@ -371,10 +371,10 @@ constexpr int KRON_AB = 5;         // thickness columns per register block
 // slots for its (k, t) once into registers and reads the chunk's slot-dense
 // coefficients Qd[zk][slot][ab] from LDS (staged once per item), so the row
 // loop issues no vector loads at all and the stores stream.  Block-cooperative:
-// every thread of the block calls it (it contains a barrier); lq holds at
-// least 4*NSC*(rows of the chunk) doubles.
+// every thread of the block calls it (it contains a barrier); lq holds the
+// chunk's coefficients (kron_lds_q bytes) followed by NSC*81 doubles.
 template <int NSC>
-__device__ inline void item_kron_reg(const Dev &d, const double *__restrict__ qd, double *__restrict__ vals, int tile,
+__device__ __forceinline__ void item_kron_reg(const Dev &d, const double *__restrict__ qd, double *__restrict__ vals, int tile,
                                      int ch, double *lq, int sig, int nthreads) {
   const int k0 = d.tiles[tile], tk = d.tiles[tile + 1] - k0;
   const int it0 = d.chunk_ptr[ch], it1 = d.chunk_ptr[ch + 1];
@@ -382,18 +382,33 @@ __device__ inline void item_kron_reg(const Dev &d, const double *__restrict__ qd
   const bool act = sig < 3 * tk;
   const int kk = act ? sig / 3 : 0, t = act ? sig - 3 * kk : 0, k = k0 + kk;
   const int c0 = d.chunk_sptr[ch], nsc = d.chunk_sptr[ch + 1] - c0;
-  double pr[NSC][4][3];
+  // P of the chunk's set slots at (k, t) from the set-independent moments and
+  // each slot's bracket coefficients staged in LDS (eq. P); P is never stored
+  double mv[4][9];
 #pragma unroll
-  for (int u = 0; u < NSC; ++u) {
-    const double *Pp = d.P + (int64_t)(u < nsc ? d.chunk_set[c0 + u] : 0) * 36 * d.nnz2 + k;
+  for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
-    for (int ab = 0; ab < 4; ++ab)
-#pragma unroll
-      for (int r = 0; r < 3; ++r) pr[u][ab][r] = u < nsc ? Pp[(int64_t)(ab * 9 + 3 * r + t) * d.nnz2] : 0.0;
+    for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[(int64_t)(ab * 9 + kl) * d.nnz2 + k];
+  double *le = lq + d.kron_lds_q / 8;  // [NSC][81]
+  for (int e = sig; e < NSC * 81; e += nthreads) {
+    const int u = e / 81;
+    le[e] = u < nsc ? d.Ec[81 * (int64_t)d.chunk_set[c0 + u] + (e - 81 * u)] : 0.0;
   }
   for (int e = sig; e < nq; e += nthreads) lq[e] = qd[4 * (int64_t)NSC * zk0 + e];
   __syncthreads();
   if (act) {
+    double pr[NSC][4][3];
+#pragma unroll
+    for (int u = 0; u < NSC; ++u)
+#pragma unroll
+      for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          double a = 0.0;
+#pragma unroll
+          for (int kl = 0; kl < 9; ++kl) a += mv[ab][kl] * le[81 * u + kl * 9 + 3 * r + t];
+          pr[u][ab][r] = a;
+        }
     const int is = d.krow[k], sr = d.srow[is];
     const int Ls = d.srow[is + 1] - sr, off = 3 * (k - sr) + t;
     const int64_t astride = 3 * (int64_t)Ls;

@@ -497,18 +497,34 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron_reg(Dev d, const double *
   const bool act = sig < 3 * tk;
   const int kk = act ? sig / 3 : 0, t = act ? sig - 3 * kk : 0, k = k0 + kk;
   const int c0 = d.chunk_sptr[ch], nsc = d.chunk_sptr[ch + 1] - c0;
-  double pr[NSC][4][3];
+  // P of the chunk's set slots at (k, t) is contracted here from the
+  // set-independent moments M_ab[kl] (one table for all sets) and each slot's
+  // bracket coefficients E_s[kl][rt] staged in LDS (eq. P): P is never stored.
+  double mv[4][9];
 #pragma unroll
-  for (int u = 0; u < NSC; ++u) {
-    const double *Pp = d.P + (int64_t)(u < nsc ? d.chunk_set[c0 + u] : 0) * 36 * d.nnz2 + k;
+  for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
-    for (int ab = 0; ab < 4; ++ab)
-#pragma unroll
-      for (int r = 0; r < 3; ++r) pr[u][ab][r] = u < nsc ? Pp[(int64_t)(ab * 9 + 3 * r + t) * d.nnz2] : 0.0;
+    for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[(int64_t)(ab * 9 + kl) * d.nnz2 + k];
+  double *le = lq + d.kron_lds_q / 8;  // [NSC][81]
+  for (int e = sig; e < NSC * 81; e += blockDim.x) {
+    const int u = e / 81;
+    le[e] = u < nsc ? d.Ec[81 * (int64_t)d.chunk_set[c0 + u] + (e - 81 * u)] : 0.0;
   }
   for (int e = sig; e < nq; e += blockDim.x) lq[e] = qd[4 * (int64_t)NSC * zk0 + e];
   __syncthreads();
   if (!act) return;
+  double pr[NSC][4][3];
+#pragma unroll
+  for (int u = 0; u < NSC; ++u)
+#pragma unroll
+    for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        double a = 0.0;
+#pragma unroll
+        for (int kl = 0; kl < 9; ++kl) a += mv[ab][kl] * le[81 * u + kl * 9 + 3 * r + t];
+        pr[u][ab][r] = a;
+      }
   const int is = d.krow[k], sr = d.srow[is];
   const int Ls = d.srow[is + 1] - sr, off = 3 * (k - sr) + t;
   const int64_t astride = 3 * (int64_t)Ls;
@@ -925,7 +941,9 @@ extern "C" LAM_API lam_status lam_assemble(const lam_plan *p, void *ws, int64_t 
   hipStream_t s = static_cast<hipStream_t>(stream);
   Dev d = make_dev(p, ws);
   hipLaunchKernelGGL(k_rotate, dim3((p->n_sets + 63) / 64), dim3(64), 0, s, d, C, theta);
-  hipLaunchKernelGGL(k_p2d, dim3((unsigned)((p->nnz2 + 255) / 256)), dim3(256), 0, s, d, d.Ec, d.P, d.M, 1);
+  // register-mode scatter contracts P itself from the moments; LDS mode reads P
+  hipLaunchKernelGGL(k_p2d, dim3((unsigned)((p->nnz2 + 255) / 256)), dim3(256), 0, s, d, d.Ec, d.P, d.M,
+                     p->kron_nsc > 0 ? 0 : 1);
   int64_t nq = p->nnzz * (p->kron_nsc > 0 ? p->kron_nsc : p->maxact);
   hipLaunchKernelGGL(k_q1d, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, d, theta);
   void *prof = lam::profile_begin(0, stream);

@@ -546,8 +546,8 @@ lam_status plan_create(const lam_laminate_desc *d, int min_nsc, lam_plan **out) 
     max_chunk_zk = std::max(max_chunk_zk, zrow[chunk_ptr[c + 1]] - zrow[chunk_ptr[c]]);
   if (reg_mode) {
     P->kron_lds_q = 4 * (int64_t)sizeof(double) * P->kron_nsc * max_chunk_zk;
-    P->kron_lds_p = 0;
-    P->kron_lds = P->kron_lds_q;
+    P->kron_lds_p = 81 * (int64_t)sizeof(double) * P->kron_nsc;  // bracket coefficients of the slots
+    P->kron_lds = P->kron_lds_q + P->kron_lds_p;
     if (P->kron_lds > 64 * 1024) {
       delete P;
       return LAM_EUNSUP;
