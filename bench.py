@@ -107,18 +107,30 @@ def _sample_parity(oracle, lam, plan, vals, rowptr, n_rows=200, seed=3):
     return float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
 
 
-def _fast_workload(torch, np, L, O, lam, mode, steps, warmup):
+def _fast_workload(torch, np, L, O, lam, mode, steps, warmup, standard_steps=0):
     """Fast assembly of another plate: nnz/s, scatter roofline, sampled parity."""
-    plan = L.Plan(lam, set_mode=mode)
+    from paper_1905_05417_amd import autotune
+    tuning = autotune.lookup(lam, mode)
+    plan = L.Plan(lam, set_mode=mode, tuning=tuning)
     rowptr, colind = plan.pattern()
     C = torch.tensor(np.asarray(lam.C), device="cuda")
     th = torch.tensor(np.asarray(lam.theta), device="cuda")
     vals = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
     ms_step, ms_k = _time_steps(torch, lambda: plan.assemble(C, th, out=vals), steps, warmup, L, "assemble")
-    res = {"nnz": plan.nnz, "sets": plan.n_sets, "set_mode": mode, "ms_per_step": ms_step,
+    res = {"nnz": plan.nnz, "sets": plan.n_sets, "set_mode": mode, "scatter_tuning": tuning or "automatic",
+           "ms_per_step": ms_step,
            "nnz_per_s": plan.nnz / (ms_step * 1e-3), "k_kron_ms": ms_k,
            "k_kron_hbm_frac": 8.0 * plan.nnz / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "parity_sample_relF": _sample_parity(O, lam, plan, vals, rowptr, n_rows=100)}
+    if standard_steps:
+        try:
+            ms_std, _ = _time_steps(torch, lambda: plan.assemble_standard(C, th, out=vals), standard_steps, 1, L,
+                                    "standard")
+            res["standard"] = {"ms_per_step": ms_std, "nnz_per_s": plan.nnz / (ms_std * 1e-3),
+                               "speedup_fast_vs_standard": ms_std / ms_step,
+                               "parity_sample_relF": _sample_parity(O, lam, plan, vals, rowptr, n_rows=50)}
+        except L.LamError as e:
+            res["standard"] = {"skipped": str(e)}
     del vals, rowptr, colind
     torch.cuda.empty_cache()
     return res
@@ -132,12 +144,17 @@ def _adjoint_workload(torch, np, L, W, O, steps, warmup):
     C = torch.tensor(np.asarray(lam.C), device="cuda")
     th = torch.tensor(np.asarray(lam.theta), device="cuda")
     res = {"workload": lam.name}
-    for mode in ("bucket", "harmonic5"):
-        plan = L.Plan(lam, set_mode=mode)
+    from paper_1905_05417_amd import autotune
+    for mode in ("bucket", "ply", "harmonic5"):
+        plan = L.Plan(lam, set_mode=mode, tuning=autotune.lookup(lam, "bucket") if mode != "harmonic5" else None)
         vals = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
         ms, ms_k = _time_steps(torch, lambda: plan.assemble(C, th, out=vals), steps, warmup, L, "assemble")
         res["forward_" + mode] = {"sets": plan.n_sets, "ms_per_step": ms, "nnz_per_s": plan.nnz / (ms * 1e-3),
                                   "k_kron_ms": ms_k}
+        if mode == "bucket":
+            ms_std, _ = _time_steps(torch, lambda: plan.assemble_standard(C, th, out=vals), 3, 1, L, "standard")
+            res["standard"] = {"ms_per_step": ms_std, "nnz_per_s": plan.nnz / (ms_std * 1e-3),
+                               "speedup_fast_vs_standard": ms_std / ms}
         del vals, plan
         torch.cuda.empty_cache()
     plan = L.Plan(lam, set_mode="bucket")
@@ -167,9 +184,12 @@ def _batch_workload(torch, np, L, W, O, wave_gb, reps):
     """The 256 uneven laminates, bucket sets, waves of at most wave_gb GiB of
     values + scratch, every wave captured in one HIP graph; one replay = the
     whole batch (each wave's values land in the same buffer, in turn)."""
+    from paper_1905_05417_amd import autotune
     lams = W.batch_laminates()
+    cache = autotune.load_cache()
+    tunings = [autotune.lookup(lam, "bucket", cache) for lam in lams]
     t0 = time.perf_counter()
-    B = L.BatchPlan(lams, set_mode="bucket", wave_bytes=wave_gb << 30)
+    B = L.BatchPlan(lams, set_mode="bucket", wave_bytes=wave_gb << 30, tunings=tunings)
     C_all, th_all = B.pack()
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
@@ -207,7 +227,8 @@ def _batch_workload(torch, np, L, W, O, wave_gb, reps):
     res = {"laminates": B.n, "waves": B.n_waves, "wave_gib": wave_gb, "nnz": B.total_nnz,
            "ms_per_batch": ms, "nnz_per_s": B.total_nnz / (ms * 1e-3),
            "hbm_frac_of_value_writes": 8.0 * B.total_nnz / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-           "setup_s": round(setup_s, 2), "graph": True, "parity_sample_relF": max(errs)}
+           "setup_s": round(setup_s, 2), "graph": True, "autotuned": any(t for t in tunings),
+           "parity_sample_relF": max(errs)}
     del g, buf, B, C_all, th_all
     torch.cuda.empty_cache()
     return res
@@ -246,9 +267,12 @@ def main():
     torch.cuda.init()
     L.lib()
 
+    from paper_1905_05417_amd import autotune
+    tuning_cache = autotune.load_cache()
     lam = W.config_p2_64x64_32ply()
+    tuning = autotune.lookup(lam, "bucket", tuning_cache)
     t0 = time.perf_counter()
-    plan = L.Plan(lam, set_mode="bucket")
+    plan = L.Plan(lam, set_mode="bucket", tuning=tuning)
     rowptr, colind = plan.pattern()
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
@@ -271,7 +295,8 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": lam.name, "nnz": plan.nnz, "dof": plan.n_rows, "plies": lam.n_ply,
                    "degree_inplane": lam.p1, "degree_thickness": lam.q, "elements_inplane": "64x64",
-                   "sets": plan.n_sets, "set_mode": plan.set_mode, "parallelism": "single GPU"},
+                   "sets": plan.n_sets, "set_mode": plan.set_mode, "scatter_tuning": tuning or "automatic",
+                   "parallelism": "single GPU"},
         "roofline": roofline,
         "setup_s": round(setup_s, 3),
     }
@@ -298,7 +323,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_extra:
         extra["p3_128x128_128ply"] = _fast_workload(torch, np, L, O, W.config_p3_128x128_128ply(), "bucket",
-                                                     max(5, args.steps // 2), args.warmup)
+                                                     max(5, args.steps // 2), args.warmup, standard_steps=2)
     if not args.no_extra:
         extra["adjoint_p2_96x96_64ply"] = _adjoint_workload(torch, np, L, W, O, max(5, args.steps // 2), args.warmup)
     if not args.no_extra and not args.no_batch:

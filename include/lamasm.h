@@ -74,10 +74,14 @@ typedef int32_t lam_status;
  *              material has no coupling between {11,22,33,12} and {13,23}
  *              (orthotropic or monoclinic about the ply plane), Remark 3.
  *  HARMONIC9:  harmonics up to order 4 including odd ones: exact for any 6x6.
+ *  PLY:        one set per ply: exact for any angles passed at assembly
+ *              (no plan-time angles needed).  The scatter forms each set's 2D
+ *              operator from set-independent moments, so many sets cost little.
  */
 #define LAM_SETS_BUCKET 0
 #define LAM_SETS_HARMONIC5 1
 #define LAM_SETS_HARMONIC9 2
+#define LAM_SETS_PLY 3
 
 /* Limits of this build: 1 <= p1, p2 <= 4, 1 <= q <= 4, Gauss points per
  * direction 1..8, n_ply <= 4096, n_mat <= 64, nnz < 2^62, columns < 2^31. */
@@ -107,6 +111,21 @@ typedef struct lam_plan lam_plan;
  * grouping).  Host only; copies everything it needs from desc. */
 LAM_API lam_status lam_plan_create(const lam_laminate_desc *desc, lam_plan **out);
 LAM_API void lam_plan_destroy(lam_plan *plan);
+
+/* Scatter tuning (performance only: the values of K do not depend on it).
+ * Zero fields select the automatic choice. */
+typedef struct {
+  int32_t tile_k;         /* in-plane nonzeros per scatter tile, <= 85 (tiles hold whole rows, so
+                             it is widened to the longest row); automatic: about 85 */
+  int32_t set_slots;      /* register-mode set slots per chunk of thickness rows: 1, 2, 4 or 8;
+                             automatic: 2 (raised to the most sets active on one row) */
+  int32_t target_blocks;  /* thickness rows are chunked so the scatter has about this many
+                             blocks; automatic: 6144 */
+  int32_t lds_kib;        /* LDS budget of the LDS-mode scatter, <= 160; automatic: 80 */
+} lam_tuning;
+
+/* lam_plan_create with explicit scatter tuning (tuning may be NULL). */
+LAM_API lam_status lam_plan_create_tuned(const lam_laminate_desc *desc, const lam_tuning *tuning, lam_plan **out);
 
 /* Sizes: rows of K (3*n), nonzeros, workspace bytes, number of sets, and the
  * number of plies and materials the device arrays must hold.  Any pointer may be NULL. */
@@ -169,6 +188,10 @@ LAM_API lam_status lam_adjoint(const lam_plan *plan, void *ws, int64_t ws_bytes,
 typedef struct lam_batch lam_batch;
 
 LAM_API lam_status lam_batch_create(int32_t n, const lam_laminate_desc *descs, int64_t wave_bytes, lam_batch **out);
+/* The same with per-laminate scatter tuning (tunings: n entries, or NULL);
+ * set_slots is fixed at 2 by the batched scatter. */
+LAM_API lam_status lam_batch_create_tuned(int32_t n, const lam_laminate_desc *descs, const lam_tuning *tunings,
+                                          int64_t wave_bytes, lam_batch **out);
 LAM_API void lam_batch_destroy(lam_batch *batch);
 LAM_API lam_status lam_batch_info(const lam_batch *batch, int32_t *n_waves, int64_t *ws_bytes,
                                   int64_t *max_wave_vals, int64_t *total_nnz);

@@ -168,6 +168,11 @@ extern "C" LAM_API void lam_batch_destroy(lam_batch *b) {
 
 extern "C" LAM_API lam_status lam_batch_create(int32_t n, const lam_laminate_desc *descs, int64_t wave_bytes,
                                                lam_batch **out) {
+  return lam_batch_create_tuned(n, descs, nullptr, wave_bytes, out);
+}
+
+extern "C" LAM_API lam_status lam_batch_create_tuned(int32_t n, const lam_laminate_desc *descs,
+                                                     const lam_tuning *tunings, int64_t wave_bytes, lam_batch **out) {
   if (!out || !descs || n < 1) return LAM_EINVAL;
   *out = nullptr;
   lam_batch *B = new (std::nothrow) lam_batch();
@@ -177,7 +182,9 @@ extern "C" LAM_API lam_status lam_batch_create(int32_t n, const lam_laminate_des
   int64_t cbytes = 0, ctot = 0, ttot = 0;
   for (int i = 0; i < n; ++i) {
     lam_plan *p = nullptr;
-    lam_status st = lam::plan_create(&descs[i], 2, &p);
+    lam_tuning t = tunings ? tunings[i] : lam_tuning{0, 0, 0, 0};
+    t.set_slots = 2;
+    lam_status st = lam::plan_create(&descs[i], &t, 2, &p);
     if (st != LAM_OK) {
       lam_batch_destroy(B);
       return st;

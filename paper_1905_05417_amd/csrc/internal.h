@@ -55,8 +55,9 @@ struct Layout {
   int64_t total = 0;
 };
 
-// Host plan construction (plan.cpp); lam_plan_create uses min_nsc = 1.
-lam_status plan_create(const lam_laminate_desc *d, int min_nsc, lam_plan **out);
+// Host plan construction (plan.cpp); lam_plan_create uses no tuning and
+// min_nsc = 1.
+lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int min_nsc, lam_plan **out);
 
 // Kernel timing hooks (profile.cpp): a slot recorded around the dominant
 // kernel of entry point `which` (0 assemble, 1 standard, 2 adjoint).

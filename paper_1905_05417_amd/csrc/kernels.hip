@@ -689,12 +689,15 @@ __global__ void k_q1d_ply(Dev d) {
 }
 
 // One block per scatter tile (whole in-plane rows), one thread per
-// (in-plane nonzero k, component t).  Thickness rows are streamed in order;
+// (in-plane nonzero k, component t).  Thickness rows are streamed in order
+// (the next row's loads issued before the current row is used);
 // Z of the (at most two) plies a row touches accumulates in registers; when
 // a ply's last row is done the block contracts Z with its moments and sums
 // over its nonzeros in LDS: adj_part[tile][ply][kl][rt].
 constexpr int ADJ_THREADS = 256;
 
+// LZ: the longest thickness row, 2q + 1
+template <int LZ>
 __global__ void __launch_bounds__(ADJ_THREADS) k_adj_stream(Dev d, const double *__restrict__ G,
                                                             const double *__restrict__ qp) {
   __shared__ double red[ADJ_THREADS * 27];
@@ -716,23 +719,36 @@ __global__ void __launch_bounds__(ADJ_THREADS) k_adj_stream(Dev d, const double 
 #pragma unroll
     for (int ab = 0; ab < 4; ++ab) z[sl][ab][0] = z[sl][ab][1] = z[sl][ab][2] = 0.0;
   const int64_t astride = 3 * (int64_t)Ls;
-  for (int it = 0; it < d.nt; ++it) {
+  // software pipeline over row pairs: the G values of the next row are in
+  // flight while a row is contracted (one row's loads alone leave the stream
+  // latency bound).  Inactive threads load their block's first nonzero (in
+  // bounds) so that the loads need no divergent branch.
+  auto load_row = [&](int it, double (&g)[LZ][3]) {
+    const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
+    const double *row = G + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
+    const int64_t rstride = 3 * (int64_t)Lz * Ls;
+#pragma unroll
+    for (int a = 0; a < LZ; ++a) {
+      const int64_t ac = a < Lz ? a : Lz - 1;  // past the row: a valid address, weighted by 0
+      g[a][0] = row[ac * astride];
+      g[a][1] = row[rstride + ac * astride];
+      g[a][2] = row[2 * rstride + ac * astride];
+    }
+  };
+  auto use_row = [&](int it, const double (&g)[LZ][3]) {
     const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
     if (act) {
-      const double *row = G + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
-      const int64_t rstride = 3 * (int64_t)Lz * Ls;
-      for (int a = 0; a < Lz; ++a) {
-        const double g0 = row[(int64_t)a * astride], g1 = row[rstride + (int64_t)a * astride],
-                     g2 = row[2 * rstride + (int64_t)a * astride];
-        const double *q = qp + 8 * (int64_t)(zb + a);
+#pragma unroll
+      for (int a = 0; a < LZ; ++a) {
+        const double *q = qp + 8 * (int64_t)(zb + (a < Lz ? a : 0));
 #pragma unroll
         for (int sl = 0; sl < 2; ++sl)
 #pragma unroll
           for (int ab = 0; ab < 4; ++ab) {
-            const double qq = q[4 * sl + ab];
-            z[sl][ab][0] += qq * g0;
-            z[sl][ab][1] += qq * g1;
-            z[sl][ab][2] += qq * g2;
+            const double qq = a < Lz ? q[4 * sl + ab] : 0.0;
+            z[sl][ab][0] += qq * g[a][0];
+            z[sl][ab][1] += qq * g[a][1];
+            z[sl][ab][2] += qq * g[a][2];
           }
       }
     }
@@ -758,6 +774,16 @@ __global__ void __launch_bounds__(ADJ_THREADS) k_adj_stream(Dev d, const double 
         d.adj_part[((int64_t)tile * d.n_ply + ply) * 81 + sig] = acc;
       }
       __syncthreads();
+    }
+  };
+  double ga[LZ][3], gb[LZ][3];
+  load_row(0, ga);
+  for (int it = 0; it < d.nt; it += 2) {
+    if (it + 1 < d.nt) load_row(it + 1, gb);
+    use_row(it, ga);
+    if (it + 1 < d.nt) {
+      if (it + 2 < d.nt) load_row(it + 2, ga);
+      use_row(it + 1, gb);
     }
   }
 }
@@ -993,7 +1019,12 @@ extern "C" LAM_API lam_status lam_adjoint(const lam_plan *p, void *ws, int64_t w
   hipLaunchKernelGGL(k_p2d, dim3((unsigned)((p->nnz2 + 255) / 256)), dim3(256), 0, s, d, d.Ec, d.P, d.M, 0);
   hipLaunchKernelGGL(k_q1d_ply, dim3((unsigned)((2 * p->nnzz + 255) / 256)), dim3(256), 0, s, d);
   void *prof = lam::profile_begin(2, stream);
-  hipLaunchKernelGGL(k_adj_stream, dim3(p->n_tiles), dim3(ADJ_THREADS), 0, s, d, grad_vals, d.Qp);
+  switch (p->q) {
+    case 1: hipLaunchKernelGGL(k_adj_stream<3>, dim3(p->n_tiles), dim3(ADJ_THREADS), 0, s, d, grad_vals, d.Qp); break;
+    case 2: hipLaunchKernelGGL(k_adj_stream<5>, dim3(p->n_tiles), dim3(ADJ_THREADS), 0, s, d, grad_vals, d.Qp); break;
+    case 3: hipLaunchKernelGGL(k_adj_stream<7>, dim3(p->n_tiles), dim3(ADJ_THREADS), 0, s, d, grad_vals, d.Qp); break;
+    default: hipLaunchKernelGGL(k_adj_stream<9>, dim3(p->n_tiles), dim3(ADJ_THREADS), 0, s, d, grad_vals, d.Qp); break;
+  }
   lam::profile_end(prof, stream);
   hipLaunchKernelGGL(k_adj_reduce, dim3((81 * p->n_ply + 255) / 256), dim3(256), 0, s, d);
   hipLaunchKernelGGL(k_adj_ply, dim3((p->n_ply + 63) / 64), dim3(64), 0, s, d, C, theta, grad_theta);

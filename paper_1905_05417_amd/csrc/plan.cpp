@@ -211,14 +211,14 @@ namespace lam {
 
 // min_nsc: smallest number of set slots of the register-mode scatter (the
 // batched path compiles one slot count for every laminate).
-lam_status plan_create(const lam_laminate_desc *d, int min_nsc, lam_plan **out) {
+lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int min_nsc, lam_plan **out) {
   if (!d || !out) return LAM_EINVAL;
   *out = nullptr;
   lam_status st;
   if ((st = check_open_knots(d->p1, d->nk1, d->k1)) != LAM_OK) return st;
   if ((st = check_open_knots(d->p2, d->nk2, d->k2)) != LAM_OK) return st;
   if ((st = check_open_knots(d->q, d->nk3, d->k3)) != LAM_OK) return st;
-  if (d->set_mode < LAM_SETS_BUCKET || d->set_mode > LAM_SETS_HARMONIC9) return LAM_EINVAL;
+  if (d->set_mode < LAM_SETS_BUCKET || d->set_mode > LAM_SETS_PLY) return LAM_EINVAL;
   if (d->n_ply < 1 || d->n_ply > 4096 || !d->iface || !d->ply_mat) return LAM_EPLY;
   if (d->n_mat < 1 || d->n_mat > 64) return LAM_EINVAL;
   if (d->set_mode == LAM_SETS_BUCKET && !d->ply_theta) return LAM_EINVAL;
@@ -252,7 +252,8 @@ lam_status plan_create(const lam_laminate_desc *d, int min_nsc, lam_plan **out) 
   P->ngz = ngz;
   P->n_ply = d->n_ply;
   P->n_mat = d->n_mat;
-  P->set_mode = d->set_mode;
+  // one set per ply is bucket grouping with every ply its own bucket
+  P->set_mode = d->set_mode == LAM_SETS_PLY ? LAM_SETS_BUCKET : d->set_mode;
 
   Dir d1, d2, dz;
   build_dir(d1, d->p1, d->nk1, d->k1, ng1);
@@ -349,7 +350,14 @@ lam_status plan_create(const lam_laminate_desc *d, int min_nsc, lam_plan **out) 
 
   // ---- sets
   std::vector<int> set_mat, set_aux, ply_set(d->n_ply, -1);
-  if (d->set_mode == LAM_SETS_BUCKET) {
+  if (d->set_mode == LAM_SETS_PLY) {
+    for (int l = 0; l < d->n_ply; ++l) {
+      ply_set[l] = (int)set_mat.size();
+      set_mat.push_back(d->ply_mat[l]);
+      set_aux.push_back(l);
+    }
+    P->n_harm = 0;
+  } else if (d->set_mode == LAM_SETS_BUCKET) {
     std::map<std::pair<int, uint64_t>, int> key;
     for (int l = 0; l < d->n_ply; ++l) {
       uint64_t bits;
@@ -392,7 +400,7 @@ lam_status plan_create(const lam_laminate_desc *d, int min_nsc, lam_plan **out) 
     for (int c = 0; c < P->nzc; ++c) {
       if (it < zfirst[c] || it > zfirst[c] + d->q) continue;
       int l = zply[c];
-      if (d->set_mode == LAM_SETS_BUCKET) {
+      if (P->set_mode == LAM_SETS_BUCKET) {
         act.push_back(ply_set[l]);
       } else {
         for (int h = 0; h < P->n_harm; ++h) act.push_back(ply_set[l] + h);
@@ -422,18 +430,18 @@ lam_status plan_create(const lam_laminate_desc *d, int min_nsc, lam_plan **out) 
   for (int is = 0; is < P->ns; ++is) max_ls = std::max(max_ls, srow[is + 1] - srow[is]);
   // whole rows of the typical (interior) length fill a 256-thread block best
   int tk_target = max_ls > 0 ? max_ls * std::max(1, 85 / max_ls) : 85;
-  if (const char *e = std::getenv("LAMASM_KRON_TK")) tk_target = std::min(85, std::max(1, std::atoi(e)));
+  if (tune && tune->tile_k > 0) tk_target = std::min(85, tune->tile_k);
   tk_target = std::max(tk_target, max_ls);
   if (tk_target > 85) {
     delete P;
     return LAM_EUNSUP;
   }
   int nsc_cap = 2;  // fewer slots keep more waves resident; chunks reload P from cache
-  if (const char *e = std::getenv("LAMASM_KRON_NSC")) nsc_cap = std::max(1, std::atoi(e));
+  if (tune && tune->set_slots > 0) nsc_cap = tune->set_slots;
   const bool reg_mode = P->maxact <= 8;
   int sc, tkmax = tk_target;
   int64_t qbudget = 8 * 1024, lds_budget = 80 * 1024;
-  if (const char *e = std::getenv("LAMASM_KRON_LDS")) lds_budget = std::max<int64_t>(16 * 1024, std::atoll(e) * 1024);
+  if (tune && tune->lds_kib > 0) lds_budget = std::max<int64_t>(16 * 1024, (int64_t)tune->lds_kib * 1024);
   if (reg_mode) {
     int want = std::max(std::max(P->maxact, std::min(P->n_sets, nsc_cap)), min_nsc);
     sc = want <= 1 ? 1 : want <= 2 ? 2 : want <= 4 ? 4 : 8;
@@ -520,7 +528,7 @@ lam_status plan_create(const lam_laminate_desc *d, int min_nsc, lam_plan **out) 
   // set list (and so the slots of zaslot)
   {
     int64_t target_blocks = 6144;
-    if (const char *e = std::getenv("LAMASM_KRON_BLOCKS")) target_blocks = std::max(1, std::atoi(e));
+    if (tune && tune->target_blocks > 0) target_blocks = tune->target_blocks;
     const int64_t per_tile = (target_blocks + P->n_tiles - 1) / P->n_tiles;
     const int max_rows = (int)std::max<int64_t>(1, (P->nt + per_tile - 1) / per_tile);
     std::vector<int> cp(1, 0), csp(1, 0), cs;
@@ -744,7 +752,17 @@ lam_status plan_create(const lam_laminate_desc *d, int min_nsc, lam_plan **out) 
 }  // namespace lam
 
 extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_plan **out) {
-  return lam::plan_create(d, 1, out);
+  return lam::plan_create(d, nullptr, 1, out);
+}
+
+extern "C" LAM_API lam_status lam_plan_create_tuned(const lam_laminate_desc *d, const lam_tuning *tuning,
+                                                   lam_plan **out) {
+  if (tuning && (tuning->tile_k < 0 || tuning->tile_k > 85 || tuning->target_blocks < 0 || tuning->lds_kib < 0 ||
+                 tuning->lds_kib > 160 ||
+                 (tuning->set_slots != 0 && tuning->set_slots != 1 && tuning->set_slots != 2 &&
+                  tuning->set_slots != 4 && tuning->set_slots != 8)))
+    return LAM_EINVAL;
+  return lam::plan_create(d, tuning, 1, out);
 }
 
 extern "C" LAM_API void lam_plan_destroy(lam_plan *p) { delete p; }

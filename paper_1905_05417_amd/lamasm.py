@@ -21,7 +21,7 @@ import torch  # loads the HIP runtime the library shares
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblamasm.so")
 
-LAM_SETS = {"bucket": 0, "harmonic5": 1, "harmonic9": 2}
+LAM_SETS = {"bucket": 0, "harmonic5": 1, "harmonic9": 2, "ply": 3}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -43,11 +43,26 @@ class _Desc(ctypes.Structure):
     ]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("tile_k", ctypes.c_int32), ("set_slots", ctypes.c_int32), ("target_blocks", ctypes.c_int32),
+                ("lds_kib", ctypes.c_int32)]
+
+
+def _make_tuning(t):
+    """lam_tuning from a dict (missing keys: automatic), or None."""
+    if t is None:
+        return None
+    x = _Tuning()
+    for k in ("tile_k", "set_slots", "target_blocks", "lds_kib"):
+        setattr(x, k, int(t.get(k, 0) or 0))
+    return x
+
+
 _lib = None
 
-EXPORTED = ("lam_plan_create", "lam_plan_destroy", "lam_plan_info", "lam_plan_upload", "lam_pattern",
+EXPORTED = ("lam_plan_create", "lam_plan_create_tuned", "lam_plan_destroy", "lam_plan_info", "lam_plan_upload", "lam_pattern",
             "lam_assemble", "lam_assemble_standard", "lam_adjoint",
-            "lam_batch_create", "lam_batch_destroy", "lam_batch_info", "lam_batch_laminate", "lam_batch_upload",
+            "lam_batch_create", "lam_batch_create_tuned", "lam_batch_destroy", "lam_batch_info", "lam_batch_laminate", "lam_batch_upload",
             "lam_batch_pattern", "lam_batch_assemble", "lam_batch_check",
             "lam_profile_enable", "lam_profile_read", "lam_status_string", "lam_version")
 
@@ -61,6 +76,9 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp, i64, i64p = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)
         L.lam_plan_create.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(vp)]
+        L.lam_plan_create_tuned.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(_Tuning), ctypes.POINTER(vp)]
+        L.lam_batch_create_tuned.argtypes = [ctypes.c_int32, ctypes.POINTER(_Desc), ctypes.POINTER(_Tuning), i64,
+                                             ctypes.POINTER(vp)]
         L.lam_plan_destroy.argtypes = [vp]
         L.lam_plan_destroy.restype = None
         L.lam_plan_info.argtypes = [vp, i64p, i64p, i64p, _i32p, _i32p, _i32p]
@@ -103,10 +121,9 @@ def _stream():
 
 
 def default_set_mode(lam) -> str:
-    """Bucket sets when plies share few (material, angle) pairs, harmonics otherwise."""
-    keys = {(int(m), float(t)) for m, t in zip(lam.ply_mat, lam.theta)}
-    n_mat = len(set(int(m) for m in lam.ply_mat))
-    return "bucket" if len(keys) <= 5 * n_mat else "harmonic9"
+    """Bucket sets (one per distinct (material, angle) pair of the plan-time
+    angles); the scatter's cost does not grow with the number of sets."""
+    return "bucket"
 
 
 def _make_desc(lam, set_mode):
@@ -138,14 +155,17 @@ def _make_desc(lam, set_mode):
 class Plan:
     """Host plan and device workspace for one laminate discretisation."""
 
-    def __init__(self, lam, set_mode: str | None = None, device="cuda"):
+    def __init__(self, lam, set_mode: str | None = None, device="cuda", tuning: dict | None = None):
         set_mode = set_mode or default_set_mode(lam)
+        self.tuning = tuning
         self.lam = lam
         self.set_mode = set_mode
         d, self._keep = _make_desc(lam, set_mode)
         self._desc = d
         h = ctypes.c_void_p()
-        _check(lib().lam_plan_create(ctypes.byref(d), ctypes.byref(h)), "lam_plan_create")
+        t = _make_tuning(tuning)
+        _check(lib().lam_plan_create_tuned(ctypes.byref(d), ctypes.byref(t) if t is not None else None,
+                                           ctypes.byref(h)), "lam_plan_create")
         self._h = h
         nr, nz, wb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         ns, npl, nm = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
@@ -236,7 +256,7 @@ class BatchPlan:
     are runs of consecutive laminates whose values plus scratch fit
     wave_bytes (0: everything in one wave)."""
 
-    def __init__(self, lams, set_mode: str | None = "bucket", wave_bytes: int = 0, device="cuda"):
+    def __init__(self, lams, set_mode: str | None = "bucket", wave_bytes: int = 0, device="cuda", tunings=None):
         self.lams = list(lams)
         n = len(self.lams)
         descs = (_Desc * n)()
@@ -246,7 +266,12 @@ class BatchPlan:
             descs[i] = d
             self._keep.append(keep)
         h = ctypes.c_void_p()
-        _check(lib().lam_batch_create(n, descs, int(wave_bytes), ctypes.byref(h)), "lam_batch_create")
+        tarr = None
+        if tunings is not None:
+            tarr = (_Tuning * n)()
+            for i, t in enumerate(tunings):
+                tarr[i] = _make_tuning(t or {})
+        _check(lib().lam_batch_create_tuned(n, descs, tarr, int(wave_bytes), ctypes.byref(h)), "lam_batch_create")
         self._h = h
         nw, wb, mv, tn = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib().lam_batch_info(h, ctypes.byref(nw), ctypes.byref(wb), ctypes.byref(mv), ctypes.byref(tn)),

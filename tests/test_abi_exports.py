@@ -82,3 +82,45 @@ def test_plan_validation_errors():
     bad = W.config_q1_8x8()
     bad.p1 = 5
     assert status(bad) in (-2, -7)
+
+
+def test_one_set_per_ply_mode_sizes(L=None):
+    from paper_1905_05417_amd import lamasm, workloads as W
+    try:
+        lamasm.lib()
+    except (RuntimeError, OSError) as e:
+        pytest.skip("library not built: %s" % e)
+    lam = W.config_q1_8x8()
+    for mode, sets in (("bucket", 2), ("ply", 4), ("harmonic5", 5), ("harmonic9", 9)):
+        d, keep = lamasm._make_desc(lam, mode)
+        h = ctypes.c_void_p()
+        assert lamasm.lib().lam_plan_create(ctypes.byref(d), ctypes.byref(h)) == 0
+        ns = ctypes.c_int32()
+        assert lamasm.lib().lam_plan_info(h, None, None, None, ctypes.byref(ns), None, None) == 0
+        lamasm.lib().lam_plan_destroy(h)
+        assert ns.value == sets, (mode, ns.value)
+
+
+def test_tuning_validation_and_cache_lookup():
+    """Scatter tuning is validated on the host; the committed tuning cache
+    resolves every benchmark plate and batch laminate to a tuning."""
+    from paper_1905_05417_amd import autotune, lamasm, workloads as W
+    try:
+        lamasm.lib()
+    except (RuntimeError, OSError) as e:
+        pytest.skip("library not built: %s" % e)
+    lam = W.config_q1_8x8()
+    d, keep = lamasm._make_desc(lam, "bucket")
+    for t, ok in (({"tile_k": 32}, True), ({"set_slots": 4, "target_blocks": 100}, True), ({"tile_k": 86}, False),
+                  ({"set_slots": 3}, False), ({"lds_kib": 200}, False)):
+        h = ctypes.c_void_p()
+        st = lamasm.lib().lam_plan_create_tuned(ctypes.byref(d), ctypes.byref(lamasm._make_tuning(t)), ctypes.byref(h))
+        assert (st == 0) == ok, (t, st)
+        if st == 0:
+            lamasm.lib().lam_plan_destroy(h)
+    cache = autotune.load_cache()
+    if not cache:
+        pytest.skip("no tuning cache")
+    for lam in [W.config_p2_64x64_32ply(), W.config_p3_128x128_128ply()] + W.batch_laminates(16):
+        t = autotune.lookup(lam, "bucket", cache)
+        assert t is not None and set(t) <= {"tile_k", "set_slots", "target_blocks", "lds_kib"}

@@ -35,14 +35,14 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-@pytest.mark.parametrize("case", range(5))
+@pytest.mark.parametrize("case", range(6))
 def test_adjoint_matches_oracle_gradient(oracle, L, case):
     rng = np.random.default_rng(5000 + case)
     if case == 0:
         lam = W.config_q1_8x8()
     else:
         lam = W.random_small(rng, max_ply=5, n_mat=2)
-    mode = "bucket" if case % 2 == 0 else "harmonic9"
+    mode = ("bucket", "harmonic9", "ply")[case % 3]
     print("case", case, mode, lam.p1, lam.p2, lam.q, lam.n_ply, flush=True)
     pat = oracle.pattern(lam)
     G = rng.standard_normal(len(pat[1]))

@@ -64,6 +64,17 @@ def test_random_small_anisotropic(oracle, L, seed):
     _compare_full(oracle, L, lam, "harmonic9")
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_one_set_per_ply(oracle, L, seed):
+    """Every ply its own set, the angles read only at assembly: exact for any
+    angles, including ones that differ from the plan-time values."""
+    rng = np.random.default_rng(1100 + seed)
+    lam = W.random_small(rng, max_ply=6, n_mat=2)
+    _compare_full(oracle, L, lam, "ply")
+    lam.theta = rng.uniform(0, np.pi, size=lam.n_ply)
+    _compare_full(oracle, L, lam, "ply")
+
+
 def test_harmonic5_orthotropic(oracle, L):
     rng = np.random.default_rng(77)
     lam = W.random_small(rng, anisotropic=False, max_ply=5)
