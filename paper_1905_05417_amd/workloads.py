@@ -142,6 +142,21 @@ def plate(p, ne, q, angles_deg, mats, ply_mat, H=0.02, L=(1.0, 1.0), name="", ne
         C=np.stack([np.asarray(c, dtype=np.float64) for c in mats]), name=name)
 
 
+def paper_plate(p: int, ne: int, m: int, layup: str = "0/90", H: float = 0.02) -> Laminate:
+    """The experiment's setting (Sec. 4): one element of degree p through the
+    whole thickness (all m plies inside it), degree p C^{p-1} in-plane with
+    ne x ne elements, m uniform plies of the Pagano-type orthotropic material
+    (moduli as printed), layup 0/90/0/90... or 0/45/-45/90/...; Gauss rules
+    p + 1 per direction per element and per ply."""
+    pattern = {"0/90": [0.0, 90.0], "0/45/-45/90": [0.0, 45.0, -45.0, 90.0]}[layup]
+    angles = [pattern[l % len(pattern)] for l in range(m)]
+    lam = plate(p, ne, p, angles, [material(PAGANO)], [0] * m, H=H,
+                name="paper_p%d_%dx%d_%dply_%s" % (p, ne, ne, m, layup.replace("/", "_")))
+    lam.k3 = open_uniform_knots(p, 1)
+    lam.ng = (p + 1, p + 1, p + 1)
+    return lam
+
+
 def config_q1_8x8() -> Laminate:
     """Trilinear Q1 hexahedra, 8x8 in-plane, 4 plies [0/90/0/90] 1 element each,
     1x1x0.1 plate, carbon, 2x2x2 Gauss: 1215 DOF."""
