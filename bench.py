@@ -48,6 +48,8 @@ def _parse():
     ap.add_argument("--no-extra", action="store_true", help="only the headline workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-laminate batch")
     ap.add_argument("--batch-wave-gib", type=int, default=150)
+    ap.add_argument("--paper-sweep", action="store_true",
+                    help="also sweep the one-element-through-the-thickness setting of the paper's experiment")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     return ap.parse_args()
@@ -234,6 +236,40 @@ def _batch_workload(torch, np, L, W, O, wave_gb, reps):
     return res
 
 
+def _paper_sweep(torch, np, L, W, O, degrees, meshes, plies, layups, reps):
+    """The experiment's setting (one element of degree p through the whole
+    thickness): fast and standard assembly times against the number of plies,
+    in-plane elements and degree, with sampled parity of both."""
+    rows = []
+    for layup in layups:
+        for p in degrees:
+            for ne in meshes:
+                for m in plies:
+                    lam = W.paper_plate(p, ne, m, layup)
+                    plan = L.Plan(lam, set_mode="bucket")
+                    rowptr, _ = plan.pattern()
+                    C = torch.tensor(np.asarray(lam.C), device="cuda")
+                    th = torch.tensor(np.asarray(lam.theta), device="cuda")
+                    vals = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
+                    ms_fast, _ = _time_steps(torch, lambda: plan.assemble(C, th, out=vals), reps, 2, L, "assemble")
+                    rec = {"layup": layup, "p": p, "elements": ne, "plies": m, "nnz": plan.nnz,
+                           "sets": plan.n_sets, "fast_ms": ms_fast,
+                           "fast_relF": _sample_parity(O, lam, plan, vals, rowptr, n_rows=min(20, plan.n_rows))}
+                    try:
+                        ms_std, _ = _time_steps(torch, lambda: plan.assemble_standard(C, th, out=vals), max(2, reps // 4),
+                                                1, L, "standard")
+                        rec.update({"standard_ms": ms_std, "speedup": ms_std / ms_fast,
+                                    "standard_relF": _sample_parity(O, lam, plan, vals, rowptr,
+                                                                    n_rows=min(20, plan.n_rows))})
+                    except L.LamError as e:
+                        rec["standard"] = "unsupported: %s" % e
+                    rows.append(rec)
+                    print("paper sweep: %s" % json.dumps(rec), file=sys.stderr, flush=True)
+                    del vals, plan, rowptr
+    torch.cuda.empty_cache()
+    return rows
+
+
 def _cpu_baseline(oracle, W):
     """Oracle on a slab of the headline plate: 16 x 64 in-plane elements, all
     32 plies, same degrees and Gauss rules."""
@@ -328,6 +364,9 @@ def main():
         extra["adjoint_p2_96x96_64ply"] = _adjoint_workload(torch, np, L, W, O, max(5, args.steps // 2), args.warmup)
     if not args.no_extra and not args.no_batch:
         extra["batch_256_uneven"] = _batch_workload(torch, np, L, W, O, args.batch_wave_gib, max(2, args.steps // 10))
+    if args.paper_sweep:
+        extra["paper_sweep"] = _paper_sweep(torch, np, L, W, O, (1, 2, 3, 4), (2, 8, 32), (1, 2, 4, 16, 64),
+                                            ("0/90", "0/45/-45/90"), 10)
     out["extra"] = extra
 
     if args.calibrate_copy_mib:
