@@ -24,8 +24,8 @@ from . import lamasm as L
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "mi355x.json")
 
 CANDIDATES = ([{}] + [{"tile_k": tk} for tk in (32, 48, 64)]
-              + [{"target_blocks": b} for b in (3072, 12288, 24576)]
-              + [{"tile_k": 48, "target_blocks": 12288}])
+              + [{"target_blocks": b} for b in (1536, 3072, 12288, 24576)]
+              + [{"tile_k": 48, "target_blocks": 12288}, {"tile_k": 64, "target_blocks": 12288}])
 
 
 def class_key(lam, set_mode: str) -> str:
@@ -34,12 +34,14 @@ def class_key(lam, set_mode: str) -> str:
                                   int(round(np.log2(max(lam.n_rows, 1)))))
 
 
-def time_scatter(lam, set_mode: str, tuning: dict, reps: int = 5) -> float:
-    """Mean scatter milliseconds of lam_assemble with this tuning."""
+def time_scatter(lam, set_mode: str, tuning: dict, reps: int = 5, vals=None) -> float:
+    """Mean scatter milliseconds of lam_assemble with this tuning (into `vals` if given)."""
     plan = L.Plan(lam, set_mode=set_mode, tuning=tuning)
     C = torch.tensor(np.asarray(lam.C), device="cuda")
     th = torch.tensor(np.asarray(lam.theta), device="cuda")
-    vals = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
+    own = vals is None
+    if own:
+        vals = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
     plan.assemble(C, th, out=vals)
     torch.cuda.synchronize()
     L.profile_enable(True)
@@ -48,19 +50,33 @@ def time_scatter(lam, set_mode: str, tuning: dict, reps: int = 5) -> float:
         plan.assemble(C, th, out=vals)
     ms, n = L.profile_read()["assemble"]
     L.profile_enable(False)
-    del vals, plan
-    torch.cuda.empty_cache()
+    del plan
+    if own:
+        del vals
+        torch.cuda.empty_cache()
     return ms / max(n, 1)
 
 
-def tune(lam, set_mode: str = "bucket", candidates=None, reps: int = 5):
-    """(best tuning, [(tuning, ms), ...]) over the candidates; infeasible ones are skipped."""
-    results = []
-    for cand in candidates or CANDIDATES:
-        try:
-            results.append((cand, time_scatter(lam, set_mode, cand, reps)))
-        except L.LamError:
-            continue
+def tune(lam, set_mode: str = "bucket", candidates=None, reps: int = 5, rounds: int = 2):
+    """(best tuning, [(tuning, ms), ...]) over the candidates; infeasible ones are skipped.
+
+    The scatter's speed also depends on where its output lands in device
+    memory, so every candidate writes into the same buffer, and the candidates
+    are timed in `rounds` interleaved rounds (the minimum counts)."""
+    cands = list(candidates or CANDIDATES)
+    nnz = L.Plan(lam, set_mode=set_mode).nnz
+    vals = torch.empty(nnz, dtype=torch.float64, device="cuda")
+    best_ms = {}
+    for _ in range(rounds):
+        for i, cand in enumerate(cands):
+            try:
+                ms = time_scatter(lam, set_mode, cand, reps, vals=vals)
+            except L.LamError:
+                continue
+            best_ms[i] = min(best_ms.get(i, ms), ms)
+    del vals
+    torch.cuda.empty_cache()
+    results = [(cands[i], best_ms[i]) for i in sorted(best_ms)]
     best = min(results, key=lambda r: r[1])[0]
     return best, results
 

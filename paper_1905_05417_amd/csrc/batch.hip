@@ -14,8 +14,8 @@
 //   k_batch_p2d    one block per 256 in-plane nonzeros of any laminate: the
 //                  set-independent 2D moments (the scatter contracts P from them);
 //   k_batch_kron   the persistent scatter.  The wave's scatter items (one tile
-//                  of whole in-plane rows x one chunk of thickness rows of one
-//                  laminate, in laminate, tile, chunk order) are cut into eight
+//                  of whole in-plane rows x one group of consecutive thickness
+//                  chunks of one laminate, in laminate, tile, group order) are cut into eight
 //                  contiguous ranges of equal output bytes, one per XCD; the
 //                  blocks of an XCD take items of their range from that range's
 //                  atomic head, so each XCD writes long contiguous runs of the
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_p2d(BatchArgs a) {
   if (k < d.nnz2) lamdev::item_p2d(d, d.Ec, d.P, d.M, k, 0);  // moments only
 }
 
-// Persistent scatter over items {lam, tile, chunk, 0}.  Control flow around
+// Persistent scatter over items {lam, tile, chunk group, 0}.  Control flow around
 // the barriers is uniform and visibly so to the compiler (the item index and
 // fields are read into scalar registers, each iteration opens with a
 // barrier): otherwise the loop may be compiled into nested exec-masked loops
@@ -139,10 +139,10 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_kron(BatchArgs a) {
     if (j >= count) break;
     const int4 wv = a.items[first + j];
     const int lam = __builtin_amdgcn_readfirstlane(wv.x);
-    const int tile = __builtin_amdgcn_readfirstlane(wv.y), ch = __builtin_amdgcn_readfirstlane(wv.z);
+    const int tile = __builtin_amdgcn_readfirstlane(wv.y), g = __builtin_amdgcn_readfirstlane(wv.z);
     const Dev &d = a.devs[lam];
     double *vals = a.vals + a.meta[lam].vals_off;
-    lamdev::item_kron_reg<2>(d, d.Qc, vals, tile, ch, lds, tid, (int)blockDim.x);
+    lamdev::item_kron_reg<2>(d, d.Qc, vals, tile, g, lds, tid, (int)blockDim.x);
   }
 }
 
@@ -256,11 +256,12 @@ extern "C" LAM_API lam_status lam_batch_create_tuned(int32_t n, const lam_lamina
         const lam_plan *p = B->plans[i];
         if (p->kron_threads != T) continue;
         const int *tiles = table<int>(p, p->L.tiles), *zrow = table<int>(p, p->L.zrow);
-        const int *chunk = table<int>(p, p->L.chunk_ptr);
+        const int *chunk = table<int>(p, p->L.chunk_ptr), *group = table<int>(p, p->L.group_ptr);
         for (int t = 0; t < p->n_tiles; ++t)
-          for (int ch = 0; ch < p->n_chunks; ++ch) {
-            B->items.push_back(make_int4(i, t, ch, 0));
-            cum.push_back(cum.back() + 9.0 * (tiles[t + 1] - tiles[t]) * (zrow[chunk[ch + 1]] - zrow[chunk[ch]]));
+          for (int g = 0; g < p->n_groups; ++g) {
+            B->items.push_back(make_int4(i, t, g, 0));
+            cum.push_back(cum.back() + 9.0 * (tiles[t + 1] - tiles[t]) *
+                                           (zrow[chunk[group[g + 1]]] - zrow[chunk[group[g]]]));
           }
       }
       const int nk = (int)cum.size() - 1;

@@ -45,8 +45,11 @@ struct Layout {
   // Kronecker scatter: tiles of whole in-plane rows (first in-plane nonzero
   // of each tile), chunks of thickness rows (first row of each chunk), the
   // sets each chunk keeps in LDS (chunk_sptr, chunk_set), and for every
-  // active set of a row its LDS slot in the row's chunk (zaslot, parallel to zaset)
-  Region tiles, chunk_ptr, chunk_sptr, chunk_set, zaslot, zchunk;
+  // active set of a row its LDS slot in the row's chunk (zaslot, parallel to
+  // zaset); groups of consecutive chunks walked by one block (first chunk of
+  // each), the distinct sets of each group (group_sptr, group_set) and each
+  // chunk slot's index in its group's list (chunk_lset, parallel to chunk_set)
+  Region tiles, chunk_ptr, chunk_sptr, chunk_set, zaslot, zchunk, group_ptr, group_sptr, group_set, chunk_lset;
   int64_t const_bytes = 0;  // end of the constant part
   // scratch: the fast assembly uses [const_bytes, fwd_end); the standard
   // assembly and the adjoint use the regions after it
@@ -78,6 +81,7 @@ struct lam_plan {
   int64_t nnz1 = 0, nnz2 = 0, nnzz = 0, nnz = 0, nrows = 0;
   int n_tiles = 0, tile_k = 0;      // tiles of whole rows, at most tile_k in-plane nonzeros each
   int n_chunks = 0, chunk_sets = 0; // thickness-row chunks, at most chunk_sets sets in LDS each
+  int n_groups = 0;                 // runs of consecutive chunks, one scatter block each
   int64_t kron_lds = 0;             // LDS bytes of the scatter kernel
   int kron_nsc = 0;                 // register mode: set slots per thread (0: LDS mode)
   int kron_threads = 256;           // scatter block size

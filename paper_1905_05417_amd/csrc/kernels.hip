@@ -40,8 +40,8 @@ struct Dev {
   const double *ztab, *zw;
   const int *zrow, *zcol, *zkrow, *zcptr, *zcell, *zaptr, *zaset;
   const int *set_mat, *set_aux, *ply_mat, *ply_set;
-  const int *tiles, *chunk_ptr, *chunk_sptr, *chunk_set, *zaslot;
-  int n_chunks, chunk_sets;
+  const int *tiles, *chunk_ptr, *chunk_sptr, *chunk_set, *zaslot, *group_ptr, *group_sptr, *group_set, *chunk_lset;
+  int n_chunks, chunk_sets, n_groups;
   int64_t kron_lds_q, kron_lds_p;
   const int *zchunk;
   int kron_nsc;
@@ -89,6 +89,11 @@ Dev make_dev(const lam_plan *p, void *ws) {
   d.chunk_set = at<int>(ws, L.chunk_set);
   d.zaslot = at<int>(ws, L.zaslot);
   d.n_chunks = p->n_chunks;
+  d.group_ptr = at<int>(ws, L.group_ptr);
+  d.group_sptr = at<int>(ws, L.group_sptr);
+  d.group_set = at<int>(ws, L.group_set);
+  d.chunk_lset = at<int>(ws, L.chunk_lset);
+  d.n_groups = p->n_groups;
   d.chunk_sets = p->chunk_sets;
   d.kron_lds_q = p->kron_lds_q;
   d.zchunk = at<int>(ws, L.zchunk);
@@ -401,20 +406,24 @@ __global__ void k_q1d(Dev d, const double *__restrict__ theta) {
 constexpr int KRON_THREADS = 256;  // 3 * tile_k <= KRON_THREADS
 constexpr int KRON_AB = 5;         // thickness columns per register block
 
-__device__ inline int kron_block(const Dev &d, int &tile, int &ch) {
-  const int nblk = d.n_tiles * d.n_chunks;
+// Block -> (tile, group of chunks): consecutive blocks go to the eight XCDs in
+// turn, so each XCD takes a contiguous range of tiles and walks its groups in
+// thickness order.
+__device__ inline int kron_block(const Dev &d, int &tile, int &g) {
+  const int nblk = d.n_tiles * d.n_groups;
   const int per = (nblk + 7) / 8;
   const int L = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  tile = L / d.n_chunks;
-  ch = L - tile * d.n_chunks;
+  tile = L / d.n_groups;
+  g = L - tile * d.n_groups;
   return L < nblk;
 }
 
 template <bool USE_LDS>
 __global__ void __launch_bounds__(KRON_THREADS) k_kron_lds(Dev d, double *__restrict__ vals) {
   extern __shared__ double lds[];
-  int tile, ch;
-  if (!kron_block(d, tile, ch)) return;
+  int tile, g;
+  if (!kron_block(d, tile, g)) return;
+  const int ch = d.group_ptr[g];  // the planner gives LDS mode one chunk per group
   const int k0 = d.tiles[tile], tk = d.tiles[tile + 1] - k0;
   const int it0 = d.chunk_ptr[ch], it1 = d.chunk_ptr[ch + 1];
   const int zk0 = d.zrow[it0], nzk = d.zrow[it1] - zk0;
@@ -480,79 +489,180 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron_lds(Dev d, double *__rest
   }
 }
 
-// Register mode of the scatter: each thread loads P of the chunk's NSC set
-// slots for its (k, t) once into registers and reads the slot-dense
-// coefficients Qd[zk][slot][ab] with scalar loads (uniform addresses), so the
-// row loop issues no vector loads at all and the stores stream.
+// One thickness row of the register-mode scatter with its width LZ known at
+// compile time (no per-column predicates): value (x, r) = sum over the
+// chunk's set slots u of Qd[zk + x][u][ab] * P_u[ab][r] (eq. Km_2), the first
+// slot's product starting the sum; stores r-major, x-minor.
+template <int NSC, int LZ>
+__device__ __forceinline__ void kron_row(const double *qq, const double (&pr)[NSC][4][3], double *out,
+                                         int64_t rstride, int64_t astride) {
+  double acc[LZ][3];
+#pragma unroll
+  for (int x = 0; x < LZ; ++x) {
+    const double *q = qq + 4 * NSC * x;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) acc[x][r] = q[0] * pr[0][0][r] + q[1] * pr[0][1][r] + q[2] * pr[0][2][r] + q[3] * pr[0][3][r];
+#pragma unroll
+    for (int u = 1; u < NSC; ++u) {
+      const double q0 = q[4 * u], q1 = q[4 * u + 1], q2 = q[4 * u + 2], q3 = q[4 * u + 3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) acc[x][r] += q0 * pr[u][0][r] + q1 * pr[u][1][r] + q2 * pr[u][2][r] + q3 * pr[u][3][r];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int x = 0; x < LZ; ++x) out[r * rstride + (int64_t)x * astride] = acc[x][r];
+}
+
+// Register mode of the scatter.
+//  - one or two set slots (every bucket and per-ply plan): one block per
+//    (tile, group of chunks).  The block stages the group's slot-dense
+//    coefficients Qd[zk][slot][ab] and the bracket coefficients of the group's
+//    sets in LDS behind one barrier; then per chunk each thread contracts P of
+//    the chunk's slots for its (k, t) into registers and writes the chunk's
+//    rows.  After the barrier the block issues no vector loads, so no wait on a
+//    load also waits for the stores in flight, and the stores stream.
+//  - four or eight slots: one block per (tile, chunk) (the planner gives each
+//    group one chunk), P of the slots in registers, coefficients in LDS.
+// P at (k, t) is contracted from the set-independent moments M_ab[kl] (one
+// table for all sets) and a slot's bracket coefficients E_s[kl][rt] (eq. P):
+// P is never stored.
 template <int NSC>
 __global__ void __launch_bounds__(KRON_THREADS) k_kron_reg(Dev d, const double *__restrict__ qd,
                                                            double *__restrict__ vals) {
-  extern __shared__ double lq[];  // the chunk's slot-dense coefficients [zk - zk0][NSC][4]
-  int tile, ch;
-  if (!kron_block(d, tile, ch)) return;
+  // LDS: slot-dense coefficients [zk - zk0][NSC][4] (kron_lds_q bytes), then
+  // bracket coefficients [81] per set of the group and one zero block (or per slot)
+  extern __shared__ double lq[];
+  int tile, g;
+  if (!kron_block(d, tile, g)) return;
   const int k0 = d.tiles[tile], tk = d.tiles[tile + 1] - k0;
-  const int it0 = d.chunk_ptr[ch], it1 = d.chunk_ptr[ch + 1];
-  const int zk0 = d.zrow[it0], nq = 4 * NSC * (d.zrow[it1] - zk0);
   const int sig = threadIdx.x;
   const bool act = sig < 3 * tk;
   const int kk = act ? sig / 3 : 0, t = act ? sig - 3 * kk : 0, k = k0 + kk;
-  const int c0 = d.chunk_sptr[ch], nsc = d.chunk_sptr[ch + 1] - c0;
-  // P of the chunk's set slots at (k, t) is contracted here from the
-  // set-independent moments M_ab[kl] (one table for all sets) and each slot's
-  // bracket coefficients E_s[kl][rt] staged in LDS (eq. P): P is never stored.
   double mv[4][9];
 #pragma unroll
   for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
     for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[(int64_t)(ab * 9 + kl) * d.nnz2 + k];
-  double *le = lq + d.kron_lds_q / 8;  // [NSC][81]
-  for (int e = sig; e < NSC * 81; e += blockDim.x) {
-    const int u = e / 81;
-    le[e] = u < nsc ? d.Ec[81 * (int64_t)d.chunk_set[c0 + u] + (e - 81 * u)] : 0.0;
-  }
-  for (int e = sig; e < nq; e += blockDim.x) lq[e] = qd[4 * (int64_t)NSC * zk0 + e];
-  __syncthreads();
-  if (!act) return;
-  double pr[NSC][4][3];
-#pragma unroll
-  for (int u = 0; u < NSC; ++u)
-#pragma unroll
-    for (int ab = 0; ab < 4; ++ab)
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        double a = 0.0;
-#pragma unroll
-        for (int kl = 0; kl < 9; ++kl) a += mv[ab][kl] * le[81 * u + kl * 9 + 3 * r + t];
-        pr[u][ab][r] = a;
-      }
   const int is = d.krow[k], sr = d.srow[is];
   const int Ls = d.srow[is + 1] - sr, off = 3 * (k - sr) + t;
   const int64_t astride = 3 * (int64_t)Ls;
-  for (int it = it0; it < it1; ++it) {
-    const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
-    double *out = vals + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
-    const int64_t rstride = 3 * (int64_t)Lz * Ls;
-    for (int ab0 = 0; ab0 < Lz; ab0 += KRON_AB) {
-      double acc[KRON_AB][3];
+  double *le = lq + d.kron_lds_q / 8;
+  if constexpr (NSC <= 2) {
+    const int ch0 = d.group_ptr[g], ch1 = d.group_ptr[g + 1];
+    const int zk0 = d.zrow[d.chunk_ptr[ch0]], nq = 4 * NSC * (d.zrow[d.chunk_ptr[ch1]] - zk0);
+    const int s0 = d.group_sptr[g], ns = d.group_sptr[g + 1] - s0;
+    for (int e = sig; e < 81 * (ns + 1); e += blockDim.x) {
+      const int u = e / 81;
+      le[e] = u < ns ? d.Ec[81 * (int64_t)d.group_set[s0 + u] + (e - 81 * u)] : 0.0;
+    }
+    for (int e = sig; e < nq; e += blockDim.x) lq[e] = qd[4 * (int64_t)NSC * zk0 + e];
+    __syncthreads();
+    if (!act) return;  // no barrier follows
+    for (int ch = ch0; ch < ch1; ++ch) {
+      const int it0 = d.chunk_ptr[ch], it1 = d.chunk_ptr[ch + 1];
+      const int c0 = d.chunk_sptr[ch], nsc = d.chunk_sptr[ch + 1] - c0;
+      double pr[NSC][4][3];
 #pragma unroll
-      for (int x = 0; x < KRON_AB; ++x) {
-        acc[x][0] = acc[x][1] = acc[x][2] = 0.0;
-        if (ab0 + x < Lz) {
-          const double *qq = lq + 4 * NSC * (zb + ab0 + x - zk0);
+      for (int u = 0; u < NSC; ++u) {
+        const double *eu = le + 81 * (u < nsc ? d.chunk_lset[c0 + u] : ns);  // unused slots: zeros
 #pragma unroll
-          for (int u = 0; u < NSC; ++u) {
-            const double q0 = qq[4 * u], q1 = qq[4 * u + 1], q2 = qq[4 * u + 2], q3 = qq[4 * u + 3];
+        for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
-            for (int r = 0; r < 3; ++r)
-              acc[x][r] += q0 * pr[u][0][r] + q1 * pr[u][1][r] + q2 * pr[u][2][r] + q3 * pr[u][3][r];
+          for (int r = 0; r < 3; ++r) {
+            double a = 0.0;
+#pragma unroll
+            for (int kl = 0; kl < 9; ++kl) a += mv[ab][kl] * eu[kl * 9 + 3 * r + t];
+            pr[u][ab][r] = a;
           }
+      }
+      for (int it = it0; it < it1; ++it) {
+        const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
+        double *out = vals + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
+        const int64_t rstride = 3 * (int64_t)Lz * Ls;
+        const double *qz = lq + 4 * NSC * (zb - zk0);
+        switch (Lz) {  // thickness row widths q + 1 and 2q + 1 of q = 1..3, uniform over the block
+          case 2: kron_row<NSC, 2>(qz, pr, out, rstride, astride); break;
+          case 3: kron_row<NSC, 3>(qz, pr, out, rstride, astride); break;
+          case 4: kron_row<NSC, 4>(qz, pr, out, rstride, astride); break;
+          case 5: kron_row<NSC, 5>(qz, pr, out, rstride, astride); break;
+          default:
+            for (int ab0 = 0; ab0 < Lz; ab0 += KRON_AB) {
+              double acc[KRON_AB][3];
+#pragma unroll
+              for (int x = 0; x < KRON_AB; ++x) {
+                acc[x][0] = acc[x][1] = acc[x][2] = 0.0;
+                if (ab0 + x < Lz) {
+                  const double *qq = lq + 4 * NSC * (zb + ab0 + x - zk0);
+#pragma unroll
+                  for (int u = 0; u < NSC; ++u) {
+                    const double q0 = qq[4 * u], q1 = qq[4 * u + 1], q2 = qq[4 * u + 2], q3 = qq[4 * u + 3];
+#pragma unroll
+                    for (int r = 0; r < 3; ++r)
+                      acc[x][r] += q0 * pr[u][0][r] + q1 * pr[u][1][r] + q2 * pr[u][2][r] + q3 * pr[u][3][r];
+                  }
+                }
+              }
+#pragma unroll
+              for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int x = 0; x < KRON_AB; ++x)
+                  if (ab0 + x < Lz) out[r * rstride + (int64_t)(ab0 + x) * astride] = acc[x][r];
+            }
         }
       }
+    }
+  } else {
+    const int ch = d.group_ptr[g];
+    const int it0 = d.chunk_ptr[ch], it1 = d.chunk_ptr[ch + 1];
+    const int zk0 = d.zrow[it0], nq = 4 * NSC * (d.zrow[it1] - zk0);
+    const int c0 = d.chunk_sptr[ch], nsc = d.chunk_sptr[ch + 1] - c0;
+    for (int e = sig; e < NSC * 81; e += blockDim.x) {
+      const int u = e / 81;
+      le[e] = u < nsc ? d.Ec[81 * (int64_t)d.chunk_set[c0 + u] + (e - 81 * u)] : 0.0;
+    }
+    for (int e = sig; e < nq; e += blockDim.x) lq[e] = qd[4 * (int64_t)NSC * zk0 + e];
+    __syncthreads();
+    if (!act) return;
+    double pr[NSC][4][3];
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
+    for (int u = 0; u < NSC; ++u)
 #pragma unroll
-        for (int x = 0; x < KRON_AB; ++x)
-          if (ab0 + x < Lz) out[r * rstride + (int64_t)(ab0 + x) * astride] = acc[x][r];
+      for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          double a = 0.0;
+#pragma unroll
+          for (int kl = 0; kl < 9; ++kl) a += mv[ab][kl] * le[81 * u + kl * 9 + 3 * r + t];
+          pr[u][ab][r] = a;
+        }
+    for (int it = it0; it < it1; ++it) {
+      const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
+      double *out = vals + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
+      const int64_t rstride = 3 * (int64_t)Lz * Ls;
+      for (int ab0 = 0; ab0 < Lz; ab0 += KRON_AB) {
+        double acc[KRON_AB][3];
+#pragma unroll
+        for (int x = 0; x < KRON_AB; ++x) {
+          acc[x][0] = acc[x][1] = acc[x][2] = 0.0;
+          if (ab0 + x < Lz) {
+            const double *qq = lq + 4 * NSC * (zb + ab0 + x - zk0);
+#pragma unroll
+            for (int u = 0; u < NSC; ++u) {
+              const double q0 = qq[4 * u], q1 = qq[4 * u + 1], q2 = qq[4 * u + 2], q3 = qq[4 * u + 3];
+#pragma unroll
+              for (int r = 0; r < 3; ++r)
+                acc[x][r] += q0 * pr[u][0][r] + q1 * pr[u][1][r] + q2 * pr[u][2][r] + q3 * pr[u][3][r];
+            }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int x = 0; x < KRON_AB; ++x)
+            if (ab0 + x < Lz) out[r * rstride + (int64_t)(ab0 + x) * astride] = acc[x][r];
+      }
     }
   }
 }
@@ -882,10 +992,10 @@ __global__ void k_rowptr(Dev d, int64_t *__restrict__ rowptr) {
 }
 
 __global__ void __launch_bounds__(KRON_THREADS) k_colind(Dev d, int32_t *__restrict__ colind) {
-  int tile, ch;
-  if (!kron_block(d, tile, ch)) return;
+  int tile, g;
+  if (!kron_block(d, tile, g)) return;
   const int k0 = d.tiles[tile], tk = d.tiles[tile + 1] - k0;
-  const int it0 = d.chunk_ptr[ch], it1 = d.chunk_ptr[ch + 1];
+  const int it0 = d.chunk_ptr[d.group_ptr[g]], it1 = d.chunk_ptr[d.group_ptr[g + 1]];
   for (int sig = threadIdx.x; sig < 3 * tk; sig += KRON_THREADS) {
     const int kk = sig / 3, t = sig - 3 * kk, k = k0 + kk;
     const int is = d.krow[k], js = d.kcol[k];
@@ -907,7 +1017,7 @@ lam_status hip_status() {
 }
 
 int kron_grid(const lam_plan *p) {
-  int nblk = p->n_tiles * p->n_chunks;
+  int nblk = p->n_tiles * p->n_groups;
   return 8 * ((nblk + 7) / 8);
 }
 

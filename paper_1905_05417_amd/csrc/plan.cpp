@@ -526,11 +526,11 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
   // enough blocks to keep every compute unit busy through the tail: split
   // chunks into pieces of at most max_rows rows; a piece keeps its chunk's
   // set list (and so the slots of zaslot)
+  int64_t target_blocks = 6144;
+  if (tune && tune->target_blocks > 0) target_blocks = tune->target_blocks;
+  const int64_t per_tile = (target_blocks + P->n_tiles - 1) / P->n_tiles;
+  const int max_rows = (int)std::max<int64_t>(1, (P->nt + per_tile - 1) / per_tile);
   {
-    int64_t target_blocks = 6144;
-    if (tune && tune->target_blocks > 0) target_blocks = tune->target_blocks;
-    const int64_t per_tile = (target_blocks + P->n_tiles - 1) / P->n_tiles;
-    const int max_rows = (int)std::max<int64_t>(1, (P->nt + per_tile - 1) / per_tile);
     std::vector<int> cp(1, 0), csp(1, 0), cs;
     for (size_t c = 0; c + 1 < chunk_ptr.size(); ++c) {
       const int a = chunk_ptr[c], b = chunk_ptr[c + 1];
@@ -549,12 +549,58 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
   }
   P->n_chunks = (int)chunk_ptr.size() - 1;
   P->chunk_sets = lds_sets ? sc : 0;
+  // groups: runs of consecutive chunks that one register-mode block walks in
+  // order after staging, once, the coefficients of all their thickness rows and
+  // the bracket coefficients of all their sets; together at most max_rows
+  // thickness rows, kGroupSets distinct sets and kGroupQBytes of coefficients.
+  // Short chunks (a set change at every ply) then share the block's in-plane
+  // moments, and the row loop of a block never waits on a load.  LDS mode and
+  // four or eight slots keep one chunk per group.  chunk_lset: each chunk
+  // slot's index in its group's set list.
+  constexpr int kGroupSets = 16;
+  constexpr int64_t kGroupQBytes = 4 * 1024;
+  std::vector<int> group_ptr(1, 0), group_sptr(1, 0), group_set, chunk_lset(chunk_set.size(), 0);
+  int max_group_zk = 0, max_group_sets = 0;
+  {
+    std::vector<int> gsets;
+    int rows = 0, gzk = 0;
+    auto flush = [&](int end) {
+      for (int c = group_ptr.back(); c < end; ++c)
+        for (int j = chunk_sptr[c]; j < chunk_sptr[c + 1]; ++j)
+          chunk_lset[j] = (int)(std::find(gsets.begin(), gsets.end(), chunk_set[j]) - gsets.begin());
+      group_set.insert(group_set.end(), gsets.begin(), gsets.end());
+      group_sptr.push_back((int)group_set.size());
+      group_ptr.push_back(end);
+      max_group_zk = std::max(max_group_zk, gzk);
+      max_group_sets = std::max(max_group_sets, (int)gsets.size());
+      gsets.clear();
+      rows = gzk = 0;
+    };
+    const int64_t q_per_zk_reg = 4 * (int64_t)sizeof(double) * std::max(P->kron_nsc, 1);
+    for (int c = 0; c < P->n_chunks; ++c) {
+      const int r = chunk_ptr[c + 1] - chunk_ptr[c], zk = zrow[chunk_ptr[c + 1]] - zrow[chunk_ptr[c]];
+      int fresh = 0;
+      for (int j = chunk_sptr[c]; j < chunk_sptr[c + 1]; ++j)
+        fresh += std::find(gsets.begin(), gsets.end(), chunk_set[j]) == gsets.end();
+      if (c > group_ptr.back() && (!reg_mode || P->kron_nsc > 2 || rows + r > max_rows || (int)gsets.size() + fresh > kGroupSets ||
+                                   q_per_zk_reg * (gzk + zk) > kGroupQBytes))
+        flush(c);
+      for (int j = chunk_sptr[c]; j < chunk_sptr[c + 1]; ++j)
+        if (std::find(gsets.begin(), gsets.end(), chunk_set[j]) == gsets.end()) gsets.push_back(chunk_set[j]);
+      rows += r;
+      gzk += zk;
+    }
+    flush(P->n_chunks);
+  }
+  P->n_groups = (int)group_ptr.size() - 1;
   int max_chunk_zk = 0;
   for (int c = 0; c < P->n_chunks; ++c)
     max_chunk_zk = std::max(max_chunk_zk, zrow[chunk_ptr[c + 1]] - zrow[chunk_ptr[c]]);
   if (reg_mode) {
-    P->kron_lds_q = 4 * (int64_t)sizeof(double) * P->kron_nsc * max_chunk_zk;
-    P->kron_lds_p = 81 * (int64_t)sizeof(double) * P->kron_nsc;  // bracket coefficients of the slots
+    // the group's coefficients, then the bracket coefficients of its sets and
+    // one zero block (one or two slots) or of each slot (four or eight)
+    P->kron_lds_q = 4 * (int64_t)sizeof(double) * P->kron_nsc * max_group_zk;
+    P->kron_lds_p = 81 * (int64_t)sizeof(double) * std::max(max_group_sets + 1, P->kron_nsc);
     P->kron_lds = P->kron_lds_q + P->kron_lds_p;
     if (P->kron_lds > 64 * 1024) {
       delete P;
@@ -663,6 +709,10 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
   L.tiles = B.take(sizeof(int) * tiles.size());
   L.zchunk = B.take(sizeof(int) * zchunk.size());
   L.chunk_ptr = B.take(sizeof(int) * chunk_ptr.size());
+  L.group_ptr = B.take(sizeof(int) * group_ptr.size());
+  L.group_sptr = B.take(sizeof(int) * group_sptr.size());
+  L.group_set = B.take(sizeof(int) * group_set.size());
+  L.chunk_lset = B.take(sizeof(int) * chunk_lset.size());
   L.chunk_sptr = B.take(sizeof(int) * chunk_sptr.size());
   L.chunk_set = B.take(sizeof(int) * chunk_set.size());
   L.zaslot = B.take(sizeof(int) * zaslot.size());
@@ -742,6 +792,10 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
   put(img, L.tiles, tiles);
   put(img, L.zchunk, zchunk);
   put(img, L.chunk_ptr, chunk_ptr);
+  put(img, L.group_ptr, group_ptr);
+  put(img, L.group_sptr, group_sptr);
+  put(img, L.group_set, group_set);
+  put(img, L.chunk_lset, chunk_lset);
   put(img, L.chunk_sptr, chunk_sptr);
   put(img, L.chunk_set, chunk_set);
   put(img, L.zaslot, zaslot);
