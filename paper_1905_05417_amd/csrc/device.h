@@ -222,6 +222,29 @@ __device__ __forceinline__ void item_rotate_set(const Dev &d, const double *__re
 }
 
 
+// 1D moments of functions i and j of one in-plane direction over the elements
+// of their common support (range: first element, count), by Gauss quadrature:
+// out = {int N_i N_j, int N_i' N_j, int N_i N_j', int N_i' N_j'} (weights include
+// the element length).
+__device__ __forceinline__ void moments_1d(const double *__restrict__ tab, const double *__restrict__ w,
+                                           const int *__restrict__ efirst, int2 range, int ng, int P, int i, int j,
+                                           double out[4]) {
+  out[0] = out[1] = out[2] = out[3] = 0.0;
+  for (int e = range.x; e < range.x + range.y; ++e) {
+    const int f = efirst[e];
+    const int ai = i - f, aj = j - f;
+    for (int g = 0; g < ng; ++g) {
+      const double *t = tab + ((int64_t)e * ng + g) * P * 2;
+      const double Ni = t[2 * ai], dNi = t[2 * ai + 1], Nj = t[2 * aj], dNj = t[2 * aj + 1];
+      const double wg = w[(int64_t)e * ng + g];
+      out[0] += wg * Ni * Nj;
+      out[1] += wg * dNi * Nj;
+      out[2] += wg * Ni * dNj;
+      out[3] += wg * dNi * dNj;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // 2D operators (eq. P).  For in-plane pair k = (is, js), the 2D Gauss sum
 // over the elements shared by both supports of the parametric moments
@@ -236,39 +259,24 @@ __device__ __forceinline__ void item_p2d(const Dev &d, const double *__restrict_
   const int i1 = is % d.n1, i2 = is / d.n1, j1 = js % d.n1, j2 = js / d.n1;
   const int2 ra = d.pe1[d.kp1[k]], rb = d.pe2[d.kp2[k]];
   const int P1 = d.p1 + 1, P2 = d.p2 + 1;
-  double m11[2][2] = {{0, 0}, {0, 0}}, m12[2] = {0, 0}, m21[2] = {0, 0}, m22 = 0.0;
-  for (int e2 = rb.x; e2 < rb.x + rb.y; ++e2) {
-    const int f2 = d.e2first[e2];
-    const int ai2 = i2 - f2, aj2 = j2 - f2;
-    for (int e1 = ra.x; e1 < ra.x + ra.y; ++e1) {
-      const int f1 = d.e1first[e1];
-      const int ai1 = i1 - f1, aj1 = j1 - f1;
-      for (int g2 = 0; g2 < d.ng2; ++g2) {
-        const double *t2 = d.tab2 + ((int64_t)e2 * d.ng2 + g2) * P2 * 2;
-        const double Ni2 = t2[2 * ai2], dNi2 = t2[2 * ai2 + 1];
-        const double Nj2 = t2[2 * aj2], dNj2 = t2[2 * aj2 + 1];
-        const double wg2 = d.w2[(int64_t)e2 * d.ng2 + g2];
-        for (int g1 = 0; g1 < d.ng1; ++g1) {
-          const double *t1 = d.tab1 + ((int64_t)e1 * d.ng1 + g1) * P1 * 2;
-          const double Ni1 = t1[2 * ai1], dNi1 = t1[2 * ai1 + 1];
-          const double Nj1 = t1[2 * aj1], dNj1 = t1[2 * aj1 + 1];
-          const double w = wg2 * d.w1[(int64_t)e1 * d.ng1 + g1];
-          const double gi[2] = {dNi1 * Ni2, Ni1 * dNi2}, gj[2] = {dNj1 * Nj2, Nj1 * dNj2};
-          const double Si = Ni1 * Ni2, Sj = Nj1 * Nj2;
-          const double wSi = w * Si, wSj = w * Sj;
-#pragma unroll
-          for (int a = 0; a < 2; ++a) {
-            const double wgi = w * gi[a];
-            m11[a][0] += wgi * gj[0];
-            m11[a][1] += wgi * gj[1];
-            m12[a] += wgi * Sj;
-            m21[a] += wSi * gj[a];
-          }
-          m22 += wSi * Sj;
-        }
-      }
-    }
-  }
+  // The in-plane map is affine (eq. extrusion) and the basis a tensor product
+  // (eq. basis_functions), and the 2D Gauss rule is a tensor product too, so
+  // each parametric moment of eq. P is exactly a product of two 1D moments:
+  // u of direction 1, v of direction 2, each {int N_i N_j, int N_i' N_j,
+  // int N_i N_j', int N_i' N_j'} over the common support.
+  double u[4], v[4];
+  moments_1d(d.tab1, d.w1, d.e1first, ra, d.ng1, P1, i1, j1, u);
+  moments_1d(d.tab2, d.w2, d.e2first, rb, d.ng2, P2, i2, j2, v);
+  double m11[2][2], m12[2], m21[2];
+  m11[0][0] = u[3] * v[0];
+  m11[0][1] = u[1] * v[2];
+  m11[1][0] = u[2] * v[1];
+  m11[1][1] = u[0] * v[3];
+  m12[0] = u[1] * v[0];
+  m12[1] = u[0] * v[1];
+  m21[0] = u[2] * v[0];
+  m21[1] = u[0] * v[2];
+  const double m22 = u[0] * v[0];
   // M_ab[k][l], ab = 11, 12, 21, 22
   double M[4][3][3];
   const double *J = d.jit;

@@ -200,8 +200,8 @@ __device__ void bracket_coefficients(const double D[6][6], double *E) {
 // degree <= 4 once NH >= 9).
 constexpr int NH = 12;
 
-__global__ void k_rotate(Dev d, const double *__restrict__ C, const double *__restrict__ theta) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void rotate_one(const Dev &d, const double *__restrict__ C, const double *__restrict__ theta,
+                                           int s) {
   if (s >= d.n_sets) return;
   const double *Cm = C + 36 * d.set_mat[s];
   double D[6][6];
@@ -227,6 +227,10 @@ __global__ void k_rotate(Dev d, const double *__restrict__ C, const double *__re
   bracket_coefficients(D, d.Ec + 81 * s);
 }
 
+__global__ void __launch_bounds__(64) k_rotate(Dev d, const double *__restrict__ C, const double *__restrict__ theta) {
+  rotate_one(d, C, theta, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // Standard assembly: every ply's rotated tensor as bracket coefficients.
 __global__ void k_rotate_plies(Dev d, const double *__restrict__ C, const double *__restrict__ theta) {
   int l = blockIdx.x * blockDim.x + threadIdx.x;
@@ -234,6 +238,29 @@ __global__ void k_rotate_plies(Dev d, const double *__restrict__ C, const double
   double D[6][6];
   rotate_c(C + 36 * d.ply_mat[l], cos(theta[l]), sin(theta[l]), D);
   bracket_coefficients(D, d.Eply + 81 * l);
+}
+
+// 1D moments of functions i and j of one in-plane direction over the elements
+// of their common support (range: first element, count), by Gauss quadrature:
+// out = {int N_i N_j, int N_i' N_j, int N_i N_j', int N_i' N_j'} (weights include
+// the element length).
+__device__ __forceinline__ void moments_1d(const double *__restrict__ tab, const double *__restrict__ w,
+                                           const int *__restrict__ efirst, int2 range, int ng, int P, int i, int j,
+                                           double out[4]) {
+  out[0] = out[1] = out[2] = out[3] = 0.0;
+  for (int e = range.x; e < range.x + range.y; ++e) {
+    const int f = efirst[e];
+    const int ai = i - f, aj = j - f;
+    for (int g = 0; g < ng; ++g) {
+      const double *t = tab + ((int64_t)e * ng + g) * P * 2;
+      const double Ni = t[2 * ai], dNi = t[2 * ai + 1], Nj = t[2 * aj], dNj = t[2 * aj + 1];
+      const double wg = w[(int64_t)e * ng + g];
+      out[0] += wg * Ni * Nj;
+      out[1] += wg * dNi * Nj;
+      out[2] += wg * Ni * dNj;
+      out[3] += wg * dNi * dNj;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -244,47 +271,31 @@ __global__ void k_rotate_plies(Dev d, const double *__restrict__ C, const double
 // pushed through DF^{-T} (grad V = DF^{-T}(dS1,dS2,0), W = DF^{-T}(0,0,S))
 // into M_ab[k][l] = int (G_a^i)_k (G_b^j)_l |DF|.  Because each set's
 // material is constant over the plane, P_{s,ab}[r][t] = sum_kl M_ab[k][l] E_s[k][l][r][t].
-__global__ void __launch_bounds__(256) k_p2d(Dev d, const double *__restrict__ Ec, double *__restrict__ Pt,
-                                             double *__restrict__ Mt, int write_p) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void p2d_one(const Dev &d, const double *__restrict__ Ec, double *__restrict__ Pt,
+                                        double *__restrict__ Mt, int64_t k, int write_p) {
   if (k >= d.nnz2) return;
   const int is = d.krow[k], js = d.kcol[k];
   const int i1 = is % d.n1, i2 = is / d.n1, j1 = js % d.n1, j2 = js / d.n1;
   const int2 ra = d.pe1[d.kp1[k]], rb = d.pe2[d.kp2[k]];
   const int P1 = d.p1 + 1, P2 = d.p2 + 1;
-  double m11[2][2] = {{0, 0}, {0, 0}}, m12[2] = {0, 0}, m21[2] = {0, 0}, m22 = 0.0;
-  for (int e2 = rb.x; e2 < rb.x + rb.y; ++e2) {
-    const int f2 = d.e2first[e2];
-    const int ai2 = i2 - f2, aj2 = j2 - f2;
-    for (int e1 = ra.x; e1 < ra.x + ra.y; ++e1) {
-      const int f1 = d.e1first[e1];
-      const int ai1 = i1 - f1, aj1 = j1 - f1;
-      for (int g2 = 0; g2 < d.ng2; ++g2) {
-        const double *t2 = d.tab2 + ((int64_t)e2 * d.ng2 + g2) * P2 * 2;
-        const double Ni2 = t2[2 * ai2], dNi2 = t2[2 * ai2 + 1];
-        const double Nj2 = t2[2 * aj2], dNj2 = t2[2 * aj2 + 1];
-        const double wg2 = d.w2[(int64_t)e2 * d.ng2 + g2];
-        for (int g1 = 0; g1 < d.ng1; ++g1) {
-          const double *t1 = d.tab1 + ((int64_t)e1 * d.ng1 + g1) * P1 * 2;
-          const double Ni1 = t1[2 * ai1], dNi1 = t1[2 * ai1 + 1];
-          const double Nj1 = t1[2 * aj1], dNj1 = t1[2 * aj1 + 1];
-          const double w = wg2 * d.w1[(int64_t)e1 * d.ng1 + g1];
-          const double gi[2] = {dNi1 * Ni2, Ni1 * dNi2}, gj[2] = {dNj1 * Nj2, Nj1 * dNj2};
-          const double Si = Ni1 * Ni2, Sj = Nj1 * Nj2;
-          const double wSi = w * Si, wSj = w * Sj;
-#pragma unroll
-          for (int a = 0; a < 2; ++a) {
-            const double wgi = w * gi[a];
-            m11[a][0] += wgi * gj[0];
-            m11[a][1] += wgi * gj[1];
-            m12[a] += wgi * Sj;
-            m21[a] += wSi * gj[a];
-          }
-          m22 += wSi * Sj;
-        }
-      }
-    }
-  }
+  // The in-plane map is affine (eq. extrusion) and the basis a tensor product
+  // (eq. basis_functions), and the 2D Gauss rule is a tensor product too, so
+  // each parametric moment of eq. P is exactly a product of two 1D moments:
+  // u of direction 1, v of direction 2, each {int N_i N_j, int N_i' N_j,
+  // int N_i N_j', int N_i' N_j'} over the common support.
+  double u[4], v[4];
+  moments_1d(d.tab1, d.w1, d.e1first, ra, d.ng1, P1, i1, j1, u);
+  moments_1d(d.tab2, d.w2, d.e2first, rb, d.ng2, P2, i2, j2, v);
+  double m11[2][2], m12[2], m21[2];
+  m11[0][0] = u[3] * v[0];
+  m11[0][1] = u[1] * v[2];
+  m11[1][0] = u[2] * v[1];
+  m11[1][1] = u[0] * v[3];
+  m12[0] = u[1] * v[0];
+  m12[1] = u[0] * v[1];
+  m21[0] = u[2] * v[0];
+  m21[1] = u[0] * v[2];
+  const double m22 = u[0] * v[0];
   // M_ab[k][l], ab = 11, 12, 21, 22
   double M[4][3][3];
   const double *J = d.jit;
@@ -325,17 +336,21 @@ __global__ void __launch_bounds__(256) k_p2d(Dev d, const double *__restrict__ E
   }
 }
 
+__global__ void __launch_bounds__(256) k_p2d(Dev d, const double *__restrict__ Ec, double *__restrict__ Pt,
+                                             double *__restrict__ Mt, int write_p) {
+  p2d_one(d, Ec, Pt, Mt, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, write_p);
+}
+
 // ---------------------------------------------------------------------------
 // 1D operators (eq. Q) folded into the sets: for thickness pair zk = (it, jt)
 // and the j-th set active on row it,
 //   Qc[zk][j][ab] = sum_{cells c shared by it, jt} w_{s,ply(c)} sum_g w_g tau_a^{it} tau_b^{jt}
 // with tau_1 = T, tau_2 = dT/dxi3, a on the test function it, and
 // w_{s,l} = [set of l == s] (bucket) or [mat(l) == mat(s)] * harmonic_s(theta_l).
-__global__ void k_q1d(Dev d, const double *__restrict__ theta) {
+__device__ __forceinline__ void q1d_one(const Dev &d, const double *__restrict__ theta, int64_t idx) {
   // register mode: one entry per chunk set slot (zeros where the slot's set
   // does not act on the pair); LDS mode: one per set active on the row
   const int width = d.kron_nsc > 0 ? d.kron_nsc : d.maxact;
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= d.nnzz * width) return;
   const int zk = (int)(idx / width), j = (int)(idx % width);
   const int it = d.zkrow[zk], jt = d.zcol[zk];
@@ -381,6 +396,21 @@ __global__ void k_q1d(Dev d, const double *__restrict__ theta) {
   o[1] = acc[1];
   o[2] = acc[2];
   o[3] = acc[3];
+}
+
+__global__ void k_q1d(Dev d, const double *__restrict__ theta) {
+  q1d_one(d, theta, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Register mode: the 2D moments and the folded 1D coefficients do not depend
+// on each other or on the set tensors, so one launch computes both (blocks
+// [0, nb_m): moments, the rest: 1D coefficients).
+__global__ void __launch_bounds__(256) k_prep(Dev d, const double *__restrict__ theta, int nb_m) {
+  const int b = blockIdx.x;
+  if (b < nb_m)
+    p2d_one(d, nullptr, nullptr, d.M, (int64_t)b * 256 + threadIdx.x, 0);
+  else
+    q1d_one(d, theta, (int64_t)(b - nb_m) * 256 + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -770,14 +800,18 @@ __global__ void __launch_bounds__(STD_THREADS) k_std3d(Dev d, double *__restrict
 // and dL/dD_l[I][J] sums Y_l over the (k,r) with Voigt index I and (l,t) with J.
 // dK is never formed: G is streamed once in the scatter's order.
 
-// Per-ply 1D operators by accumulator slot (ply & 1): Qp[zk][slot][ab].
-__global__ void k_q1d_ply(Dev d) {
+// Per-ply 1D operators by accumulator slot (ply & 1), padded per thickness
+// row to its longest width lz = 2q + 1: Qp[it][a][slot][ab] for the pair
+// (it, a-th nonzero of row it), zeros for a past the row's width.
+__global__ void k_q1d_ply(Dev d, int lz) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 2 * d.nnzz) return;
-  const int zk = (int)(idx >> 1), slot = (int)(idx & 1);
-  const int it = d.zkrow[zk], jt = d.zcol[zk], Q1 = d.q + 1;
+  if (idx >= 2 * (int64_t)d.nt * lz) return;
+  const int slot = (int)(idx & 1), a = (int)((idx >> 1) % lz), it = (int)((idx >> 1) / lz);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int ci = d.zcptr[zk]; ci < d.zcptr[zk + 1]; ++ci) {
+  const int zk = d.zrow[it] + a;
+  const bool in_row = zk < d.zrow[it + 1];
+  const int jt = in_row ? d.zcol[zk] : 0, Q1 = d.q + 1;
+  for (int ci = in_row ? d.zcptr[zk] : 0; ci < (in_row ? d.zcptr[zk + 1] : 0); ++ci) {
     const int c = d.zcell[ci];
     if ((d.zply[c] & 1) != slot) continue;
     const int ai = it - d.zfirst[c], aj = jt - d.zfirst[c];
@@ -803,8 +837,17 @@ __global__ void k_q1d_ply(Dev d) {
 // (the next row's loads issued before the current row is used);
 // Z of the (at most two) plies a row touches accumulates in registers; when
 // a ply's last row is done the block contracts Z with its moments and sums
-// over its nonzeros in LDS: adj_part[tile][ply][kl][rt].
+// over its nonzeros in LDS: adj_part[ply][kl][rt][tile].
 constexpr int ADJ_THREADS = 256;
+
+// Workgroup barrier that orders LDS accesses only: loads from global memory
+// issued before it stay in flight (__syncthreads also waits for them, which
+// would drain the stream's prefetch at every ply end).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 // LZ: the longest thickness row, 2q + 1
 template <int LZ>
@@ -822,7 +865,10 @@ __global__ void __launch_bounds__(ADJ_THREADS) k_adj_stream(Dev d, const double 
 #pragma unroll
   for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
-    for (int kl = 0; kl < 9; ++kl) m[ab][kl] = act ? d.M[(int64_t)(ab * 9 + kl) * d.nnz2 + k] : 0.0;
+    for (int kl = 0; kl < 9; ++kl) {
+      const double v = d.M[(int64_t)(ab * 9 + kl) * d.nnz2 + k];  // k is valid for every thread
+      m[ab][kl] = act ? v : 0.0;
+    }
   double z[2][4][3];
 #pragma unroll
   for (int sl = 0; sl < 2; ++sl)
@@ -846,22 +892,18 @@ __global__ void __launch_bounds__(ADJ_THREADS) k_adj_stream(Dev d, const double 
     }
   };
   auto use_row = [&](int it, const double (&g)[LZ][3]) {
-    const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
-    if (act) {
+    const double *q = qp + (int64_t)it * LZ * 8;  // padded: zeros past the row's width
 #pragma unroll
-      for (int a = 0; a < LZ; ++a) {
-        const double *q = qp + 8 * (int64_t)(zb + (a < Lz ? a : 0));
+    for (int a = 0; a < LZ; ++a)
 #pragma unroll
-        for (int sl = 0; sl < 2; ++sl)
+      for (int sl = 0; sl < 2; ++sl)
 #pragma unroll
-          for (int ab = 0; ab < 4; ++ab) {
-            const double qq = a < Lz ? q[4 * sl + ab] : 0.0;
-            z[sl][ab][0] += qq * g[a][0];
-            z[sl][ab][1] += qq * g[a][1];
-            z[sl][ab][2] += qq * g[a][2];
-          }
-      }
-    }
+        for (int ab = 0; ab < 4; ++ab) {
+          const double qq = q[8 * a + 4 * sl + ab];
+          z[sl][ab][0] += qq * g[a][0];
+          z[sl][ab][1] += qq * g[a][1];
+          z[sl][ab][2] += qq * g[a][2];
+        }
     const int fin = d.rowfin[it];
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
@@ -876,14 +918,14 @@ __global__ void __launch_bounds__(ADJ_THREADS) k_adj_stream(Dev d, const double 
               m[0][kl] * z[sl][0][r] + m[1][kl] * z[sl][1][r] + m[2][kl] * z[sl][2][r] + m[3][kl] * z[sl][3][r];
 #pragma unroll
       for (int ab = 0; ab < 4; ++ab) z[sl][ab][0] = z[sl][ab][1] = z[sl][ab][2] = 0.0;
-      __syncthreads();
+      lds_barrier();
       if (sig < 81) {
         const int kl = sig / 9, r = (sig / 3) % 3, tt = sig % 3;
         double acc = 0.0;
         for (int q2 = 0; q2 < tk; ++q2) acc += red[(3 * q2 + tt) * 27 + kl * 3 + r];
-        d.adj_part[((int64_t)tile * d.n_ply + ply) * 81 + sig] = acc;
+        d.adj_part[((int64_t)ply * 81 + sig) * d.n_tiles + tile] = acc;
       }
-      __syncthreads();
+      lds_barrier();
     }
   };
   double ga[LZ][3], gb[LZ][3];
@@ -898,14 +940,22 @@ __global__ void __launch_bounds__(ADJ_THREADS) k_adj_stream(Dev d, const double 
   }
 }
 
-// Sum of the tile partials per ply, in tile order (deterministic).
-__global__ void k_adj_reduce(Dev d) {
-  int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 81 * d.n_ply) return;
-  const int ply = idx / 81, e = idx % 81;
+// Sum over the tiles of the partials of one (ply, entry) per block
+// (adj_part[ply][81][tile]): each thread a strided run of tiles, then a tree,
+// so the order is fixed and the result deterministic.
+__global__ void __launch_bounds__(256) k_adj_reduce(Dev d) {
+  __shared__ double part[256];
+  const int idx = blockIdx.x;  // ply * 81 + entry
+  const double *src = d.adj_part + (int64_t)idx * d.n_tiles;
   double acc = 0.0;
-  for (int tile = 0; tile < d.n_tiles; ++tile) acc += d.adj_part[((int64_t)tile * d.n_ply + ply) * 81 + e];
-  d.adj_y[idx] = acc;
+  for (int t = threadIdx.x; t < d.n_tiles; t += 256) acc += src[t];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) d.adj_y[idx] = part[0];
 }
 
 __device__ inline int voigt_pair(int i, int j) {
@@ -1076,12 +1126,18 @@ extern "C" LAM_API lam_status lam_assemble(const lam_plan *p, void *ws, int64_t 
   if (nnz != p->nnz) return LAM_ESIZE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Dev d = make_dev(p, ws);
-  hipLaunchKernelGGL(k_rotate, dim3((p->n_sets + 63) / 64), dim3(64), 0, s, d, C, theta);
-  // register-mode scatter contracts P itself from the moments; LDS mode reads P
-  hipLaunchKernelGGL(k_p2d, dim3((unsigned)((p->nnz2 + 255) / 256)), dim3(256), 0, s, d, d.Ec, d.P, d.M,
-                     p->kron_nsc > 0 ? 0 : 1);
   int64_t nq = p->nnzz * (p->kron_nsc > 0 ? p->kron_nsc : p->maxact);
-  hipLaunchKernelGGL(k_q1d, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, d, theta);
+  hipLaunchKernelGGL(k_rotate, dim3((p->n_sets + 63) / 64), dim3(64), 0, s, d, C, theta);
+  if (p->kron_nsc > 0) {
+    // register-mode scatter contracts P itself from the moments: one launch
+    // for the moments and the 1D coefficients
+    const int nb_m = (int)((p->nnz2 + 255) / 256), nb_q = (int)((nq + 255) / 256);
+    hipLaunchKernelGGL(k_prep, dim3((unsigned)(nb_m + nb_q)), dim3(256), 0, s, d, theta, nb_m);
+  } else {
+    // LDS mode reads P, which needs the set tensors
+    hipLaunchKernelGGL(k_p2d, dim3((unsigned)((p->nnz2 + 255) / 256)), dim3(256), 0, s, d, d.Ec, d.P, d.M, 1);
+    hipLaunchKernelGGL(k_q1d, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, d, theta);
+  }
   void *prof = lam::profile_begin(0, stream);
   launch_kron(p, d, vals, s);
   lam::profile_end(prof, stream);
@@ -1127,7 +1183,8 @@ extern "C" LAM_API lam_status lam_adjoint(const lam_plan *p, void *ws, int64_t w
   hipStream_t s = static_cast<hipStream_t>(stream);
   Dev d = make_dev(p, ws);
   hipLaunchKernelGGL(k_p2d, dim3((unsigned)((p->nnz2 + 255) / 256)), dim3(256), 0, s, d, d.Ec, d.P, d.M, 0);
-  hipLaunchKernelGGL(k_q1d_ply, dim3((unsigned)((2 * p->nnzz + 255) / 256)), dim3(256), 0, s, d);
+  const int lz = 2 * p->q + 1;
+  hipLaunchKernelGGL(k_q1d_ply, dim3((unsigned)((2 * (int64_t)p->nt * lz + 255) / 256)), dim3(256), 0, s, d, lz);
   void *prof = lam::profile_begin(2, stream);
   switch (p->q) {
     case 1: hipLaunchKernelGGL(k_adj_stream<3>, dim3(p->n_tiles), dim3(ADJ_THREADS), 0, s, d, grad_vals, d.Qp); break;
@@ -1136,7 +1193,7 @@ extern "C" LAM_API lam_status lam_adjoint(const lam_plan *p, void *ws, int64_t w
     default: hipLaunchKernelGGL(k_adj_stream<9>, dim3(p->n_tiles), dim3(ADJ_THREADS), 0, s, d, grad_vals, d.Qp); break;
   }
   lam::profile_end(prof, stream);
-  hipLaunchKernelGGL(k_adj_reduce, dim3((81 * p->n_ply + 255) / 256), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_adj_reduce, dim3(81 * p->n_ply), dim3(256), 0, s, d);
   hipLaunchKernelGGL(k_adj_ply, dim3((p->n_ply + 63) / 64), dim3(64), 0, s, d, C, theta, grad_theta);
   hipLaunchKernelGGL(k_adj_mat, dim3((36 * p->n_mat + 63) / 64), dim3(64), 0, s, d, theta, grad_C);
   return hip_status();

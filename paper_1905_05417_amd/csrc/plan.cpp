@@ -724,9 +724,9 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
   L.M = B.take(sizeof(double) * 36 * P->nnz2);
   L.fwd_end = B.cur;  // scratch of the fast assembly ends here
   L.Eply = B.take(sizeof(double) * 81 * P->n_ply);
-  // adjoint scratch: per-ply 1D operators by slot, per (tile, ply) partial sums,
+  // adjoint scratch: per-ply 1D operators by slot (padded per thickness row), per (ply, tile) partial sums,
   // per-ply totals and dL/dD_l
-  L.Qp = B.take(sizeof(double) * 8 * P->nnzz);
+  L.Qp = B.take(sizeof(double) * 8 * std::max<int64_t>(P->nnzz, (int64_t)P->nt * (2 * P->q + 1)));
   L.adj_part = B.take(sizeof(double) * 81 * (int64_t)P->n_tiles * P->n_ply);
   L.adj_y = B.take(sizeof(double) * 81 * P->n_ply);
   L.adj_dD = B.take(sizeof(double) * 36 * P->n_ply);
