@@ -178,7 +178,16 @@ def _adjoint_workload(torch, np, L, W, O, steps, warmup):
                 "adjoint_grad_read_GBps": 8.0 * plan.nnz / (ms_k * 1e-3) / 1e9,
                 "adjoint_hbm_frac": 8.0 * plan.nnz / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 "adjoint_rel_err_vs_oracle": err})
-    del G, u, plan, rowptr
+    del G
+    torch.cuda.empty_cache()
+    # the same gradient with G = u u^T formed from u inside the stream (no G in memory)
+    ms1, ms1_k = _time_steps(torch, lambda: out.update(g=plan.adjoint_rank1(C, th, u)), steps, warmup, L, "adjoint")
+    gC1, gT1 = out["g"]
+    err1 = max(float(np.abs(gC1.cpu().numpy() - gC_ref).max() / np.abs(gC_ref).max()),
+               float(np.abs(gT1.cpu().numpy() - gT_ref).max() / np.abs(gT_ref).max()))
+    res.update({"adjoint_rank1_ms": ms1, "adjoint_rank1_stream_kernel_ms": ms1_k,
+                "adjoint_rank1_rel_err_vs_oracle": err1})
+    del u, plan, rowptr
     torch.cuda.empty_cache()
     return res
 

@@ -164,6 +164,17 @@ LAM_API lam_status lam_adjoint(const lam_plan *plan, void *ws, int64_t ws_bytes,
                                const double *theta, const double *grad_vals, int64_t nnz, double *grad_C,
                                double *grad_theta, void *stream);
 
+/* Rank-one adjoint: the gradient of L = u^T K u (strain energy times two,
+ * compliance) with respect to C and theta, i.e. lam_adjoint with
+ * G = u u^T on the pattern of K, but G is never formed or read: each thread
+ * forms its entries of G from u as it streams.  u: device, n_rows doubles in
+ * the row order of lam_pattern (3 (i_t n_s + i_s) + component); grad_C and
+ * grad_theta as for lam_adjoint.  LAM_ESIZE if n_rows is not the plan's row
+ * count; LAM_EUNSUP where lam_adjoint is unsupported. */
+LAM_API lam_status lam_adjoint_rank1(const lam_plan *plan, void *ws, int64_t ws_bytes, const double *C,
+                                     const double *theta, const double *u, int64_t n_rows, double *grad_C,
+                                     double *grad_theta, void *stream);
+
 /* Batched assembly: many laminates (different meshes, degrees, ply counts,
  * materials) in one persistent kernel launch per memory wave (Sec. 3 applied
  * per laminate; each laminate's values are exactly those of lam_assemble on

@@ -849,9 +849,11 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// LZ: the longest thickness row, 2q + 1
-template <int LZ>
-__global__ void __launch_bounds__(ADJ_THREADS) k_adj_stream(Dev d, const double *__restrict__ G,
+// LZ: the longest thickness row, 2q + 1.  RANK1: G = u u^T on the pattern
+// (L = u^T K u), formed from u on the fly instead of read; src is u (n_rows
+// doubles) then, else G (nnz doubles).
+template <int LZ, bool RANK1>
+__global__ void __launch_bounds__(ADJ_THREADS) k_adj_stream(Dev d, const double *__restrict__ src,
                                                             const double *__restrict__ qp) {
   __shared__ double red[ADJ_THREADS * 27];
   const int tile = blockIdx.x;
@@ -879,16 +881,31 @@ __global__ void __launch_bounds__(ADJ_THREADS) k_adj_stream(Dev d, const double 
   // flight while a row is contracted (one row's loads alone leave the stream
   // latency bound).  Inactive threads load their block's first nonzero (in
   // bounds) so that the loads need no divergent branch.
+  const int js = d.kcol[k];
   auto load_row = [&](int it, double (&g)[LZ][3]) {
     const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
-    const double *row = G + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
-    const int64_t rstride = 3 * (int64_t)Lz * Ls;
+    if constexpr (RANK1) {
+      // G[(it, is, r), (jt, js, t)] = u[3 (it ns + is) + r] u[3 (jt ns + js) + t]
+      const double *ur = src + 3 * ((int64_t)it * d.ns + is);
+      const double u0 = ur[0], u1 = ur[1], u2 = ur[2];
 #pragma unroll
-    for (int a = 0; a < LZ; ++a) {
-      const int64_t ac = a < Lz ? a : Lz - 1;  // past the row: a valid address, weighted by 0
-      g[a][0] = row[ac * astride];
-      g[a][1] = row[rstride + ac * astride];
-      g[a][2] = row[2 * rstride + ac * astride];
+      for (int a = 0; a < LZ; ++a) {
+        const int ac = a < Lz ? a : Lz - 1;  // past the row: a valid address, weighted by 0
+        const double uc = src[3 * ((int64_t)d.zcol[zb + ac] * d.ns + js) + t];
+        g[a][0] = u0 * uc;
+        g[a][1] = u1 * uc;
+        g[a][2] = u2 * uc;
+      }
+    } else {
+      const double *row = src + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
+      const int64_t rstride = 3 * (int64_t)Lz * Ls;
+#pragma unroll
+      for (int a = 0; a < LZ; ++a) {
+        const int64_t ac = a < Lz ? a : Lz - 1;  // past the row: a valid address, weighted by 0
+        g[a][0] = row[ac * astride];
+        g[a][1] = row[rstride + ac * astride];
+        g[a][2] = row[2 * rstride + ac * astride];
+      }
     }
   };
   auto use_row = [&](int it, const double (&g)[LZ][3]) {
@@ -1172,6 +1189,35 @@ extern "C" LAM_API lam_status lam_assemble_standard(const lam_plan *p, void *ws,
   return hip_status();
 }
 
+namespace {
+
+// The adjoint's launches; src is G (nnz doubles) or, rank1, u (n_rows doubles).
+void launch_adjoint(const lam_plan *p, const Dev &d, const double *C, const double *theta, const double *src,
+                    bool rank1, double *grad_C, double *grad_theta, void *stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_p2d, dim3((unsigned)((p->nnz2 + 255) / 256)), dim3(256), 0, s, d, d.Ec, d.P, d.M, 0);
+  const int lz = 2 * p->q + 1;
+  hipLaunchKernelGGL(k_q1d_ply, dim3((unsigned)((2 * (int64_t)p->nt * lz + 255) / 256)), dim3(256), 0, s, d, lz);
+  void *prof = lam::profile_begin(2, stream);
+  const dim3 grid(p->n_tiles), blk(ADJ_THREADS);
+  switch (p->q * 2 + (rank1 ? 1 : 0)) {
+    case 2: hipLaunchKernelGGL((k_adj_stream<3, false>), grid, blk, 0, s, d, src, d.Qp); break;
+    case 3: hipLaunchKernelGGL((k_adj_stream<3, true>), grid, blk, 0, s, d, src, d.Qp); break;
+    case 4: hipLaunchKernelGGL((k_adj_stream<5, false>), grid, blk, 0, s, d, src, d.Qp); break;
+    case 5: hipLaunchKernelGGL((k_adj_stream<5, true>), grid, blk, 0, s, d, src, d.Qp); break;
+    case 6: hipLaunchKernelGGL((k_adj_stream<7, false>), grid, blk, 0, s, d, src, d.Qp); break;
+    case 7: hipLaunchKernelGGL((k_adj_stream<7, true>), grid, blk, 0, s, d, src, d.Qp); break;
+    case 8: hipLaunchKernelGGL((k_adj_stream<9, false>), grid, blk, 0, s, d, src, d.Qp); break;
+    default: hipLaunchKernelGGL((k_adj_stream<9, true>), grid, blk, 0, s, d, src, d.Qp); break;
+  }
+  lam::profile_end(prof, stream);
+  hipLaunchKernelGGL(k_adj_reduce, dim3(81 * p->n_ply), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_adj_ply, dim3((p->n_ply + 63) / 64), dim3(64), 0, s, d, C, theta, grad_theta);
+  hipLaunchKernelGGL(k_adj_mat, dim3((36 * p->n_mat + 63) / 64), dim3(64), 0, s, d, theta, grad_C);
+}
+
+}  // namespace
+
 extern "C" LAM_API lam_status lam_adjoint(const lam_plan *p, void *ws, int64_t ws_bytes, const double *C,
                                           const double *theta, const double *grad_vals, int64_t nnz, double *grad_C,
                                           double *grad_theta, void *stream) {
@@ -1180,21 +1226,20 @@ extern "C" LAM_API lam_status lam_adjoint(const lam_plan *p, void *ws, int64_t w
   if (!C || !theta || !grad_vals || !grad_C || !grad_theta) return LAM_EINVAL;
   if (nnz != p->nnz) return LAM_ESIZE;
   if (!p->adj_ok || 3 * p->tile_k > ADJ_THREADS) return LAM_EUNSUP;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   Dev d = make_dev(p, ws);
-  hipLaunchKernelGGL(k_p2d, dim3((unsigned)((p->nnz2 + 255) / 256)), dim3(256), 0, s, d, d.Ec, d.P, d.M, 0);
-  const int lz = 2 * p->q + 1;
-  hipLaunchKernelGGL(k_q1d_ply, dim3((unsigned)((2 * (int64_t)p->nt * lz + 255) / 256)), dim3(256), 0, s, d, lz);
-  void *prof = lam::profile_begin(2, stream);
-  switch (p->q) {
-    case 1: hipLaunchKernelGGL(k_adj_stream<3>, dim3(p->n_tiles), dim3(ADJ_THREADS), 0, s, d, grad_vals, d.Qp); break;
-    case 2: hipLaunchKernelGGL(k_adj_stream<5>, dim3(p->n_tiles), dim3(ADJ_THREADS), 0, s, d, grad_vals, d.Qp); break;
-    case 3: hipLaunchKernelGGL(k_adj_stream<7>, dim3(p->n_tiles), dim3(ADJ_THREADS), 0, s, d, grad_vals, d.Qp); break;
-    default: hipLaunchKernelGGL(k_adj_stream<9>, dim3(p->n_tiles), dim3(ADJ_THREADS), 0, s, d, grad_vals, d.Qp); break;
-  }
-  lam::profile_end(prof, stream);
-  hipLaunchKernelGGL(k_adj_reduce, dim3(81 * p->n_ply), dim3(256), 0, s, d);
-  hipLaunchKernelGGL(k_adj_ply, dim3((p->n_ply + 63) / 64), dim3(64), 0, s, d, C, theta, grad_theta);
-  hipLaunchKernelGGL(k_adj_mat, dim3((36 * p->n_mat + 63) / 64), dim3(64), 0, s, d, theta, grad_C);
+  launch_adjoint(p, d, C, theta, grad_vals, false, grad_C, grad_theta, stream);
+  return hip_status();
+}
+
+extern "C" LAM_API lam_status lam_adjoint_rank1(const lam_plan *p, void *ws, int64_t ws_bytes, const double *C,
+                                                const double *theta, const double *u, int64_t n_rows,
+                                                double *grad_C, double *grad_theta, void *stream) {
+  lam_status st = check_ws(p, ws, ws_bytes);
+  if (st != LAM_OK) return st;
+  if (!C || !theta || !u || !grad_C || !grad_theta) return LAM_EINVAL;
+  if (n_rows != p->nrows) return LAM_ESIZE;
+  if (!p->adj_ok || 3 * p->tile_k > ADJ_THREADS) return LAM_EUNSUP;
+  Dev d = make_dev(p, ws);
+  launch_adjoint(p, d, C, theta, u, true, grad_C, grad_theta, stream);
   return hip_status();
 }

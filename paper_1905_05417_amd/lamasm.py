@@ -61,7 +61,7 @@ def _make_tuning(t):
 _lib = None
 
 EXPORTED = ("lam_plan_create", "lam_plan_create_tuned", "lam_plan_destroy", "lam_plan_info", "lam_plan_upload", "lam_pattern",
-            "lam_assemble", "lam_assemble_standard", "lam_adjoint",
+            "lam_assemble", "lam_assemble_standard", "lam_adjoint", "lam_adjoint_rank1",
             "lam_batch_create", "lam_batch_create_tuned", "lam_batch_destroy", "lam_batch_info", "lam_batch_laminate", "lam_batch_upload",
             "lam_batch_pattern", "lam_batch_assemble", "lam_batch_check",
             "lam_profile_enable", "lam_profile_read", "lam_status_string", "lam_version")
@@ -87,6 +87,7 @@ def lib():
         L.lam_assemble.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
         L.lam_assemble_standard.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
         L.lam_adjoint.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
+        L.lam_adjoint_rank1.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
         L.lam_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(_Desc), i64, ctypes.POINTER(vp)]
         L.lam_batch_destroy.argtypes = [vp]
         L.lam_batch_destroy.restype = None
@@ -229,6 +230,18 @@ class Plan:
         gT = torch.empty(self.n_ply, dtype=torch.float64, device=self.device)
         _check(lib().lam_adjoint(self._h, ws.data_ptr(), self.ws_bytes, C.data_ptr(), theta.data_ptr(),
                                  G.data_ptr(), G.numel(), gC.data_ptr(), gT.data_ptr(), _stream()), "lam_adjoint")
+        return gC.view(self.n_mat, 6, 6), gT
+
+    def adjoint_rank1(self, C, theta, u):
+        """Gradient of L = u^T K u (lam_adjoint_rank1): G = u u^T is never formed."""
+        ws = self._ws()
+        C, theta = self._inputs(C, theta)
+        u = u.to(dtype=torch.float64).contiguous()
+        gC = torch.empty(self.n_mat * 36, dtype=torch.float64, device=self.device)
+        gT = torch.empty(self.n_ply, dtype=torch.float64, device=self.device)
+        _check(lib().lam_adjoint_rank1(self._h, ws.data_ptr(), self.ws_bytes, C.data_ptr(), theta.data_ptr(),
+                                       u.data_ptr(), u.numel(), gC.data_ptr(), gT.data_ptr(), _stream()),
+               "lam_adjoint_rank1")
         return gC.view(self.n_mat, 6, 6), gT
 
     def csr(self, vals, pattern=None):

@@ -137,7 +137,55 @@ def test_full_size_adjoint_plate_uu(oracle, L):
     eC, eT = _rel(gC, gC_ref), _rel(gT, gT_ref)
     print("full size: dC rel %.3e  dtheta rel %.3e" % (eC, eT), flush=True)
     assert eC <= TOL and eT <= TOL
+    # rank-one entry point: the same gradient with G formed from u on the fly
+    gC1, gT1 = plan.adjoint_rank1(C, th, u)
+    gC1, gT1 = gC1.cpu().numpy(), gT1.cpu().numpy()
+    eC1, eT1 = _rel(gC1, gC_ref), _rel(gT1, gT_ref)
+    print("full size rank one: dC rel %.3e  dtheta rel %.3e" % (eC1, eT1), flush=True)
+    assert eC1 <= TOL and eT1 <= TOL
     # the same L from the forward: Euler identity sum <C, dL/dC> = L
     Lq = _quad(plan, plan.assemble(C, th), rowptr, colind, u)
     euler = float(np.sum(np.asarray(lam.C) * gC))
     assert abs(euler - Lq) <= 1e-9 * abs(Lq)
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_rank1_adjoint_matches_oracle(oracle, L, case):
+    """lam_adjoint_rank1 (G = u u^T never formed) against the oracle's gradient
+    for that G on the pattern, small laminates, all set modes."""
+    rng = np.random.default_rng(6100 + case)
+    lam = W.config_q1_8x8() if case == 0 else W.random_small(rng, max_ply=5, n_mat=2)
+    mode = ("bucket", "ply", "harmonic9")[case % 3]
+    print("case", case, mode, lam.p1, lam.p2, lam.q, lam.n_ply, flush=True)
+    rp, ci = oracle.pattern(lam)
+    u = rng.standard_normal(len(rp) - 1)
+    G = u[np.repeat(np.arange(len(rp) - 1), np.diff(rp))] * u[ci]
+    gC_ref, gT_ref = oracle.grad(lam, G, pattern_=(rp, ci))
+    plan = L.Plan(lam, set_mode=mode)
+    C, th = _mats(lam)
+    gC, gT = plan.adjoint_rank1(C, th, torch.tensor(u, device="cuda"))
+    eC, eT = _rel(gC.cpu().numpy(), gC_ref), _rel(gT.cpu().numpy(), gT_ref)
+    print("  rank one: dC rel %.3e  dtheta rel %.3e" % (eC, eT), flush=True)
+    assert eC <= 1e-10 and eT <= 1e-10
+
+
+def test_rank1_adjoint_rigid_translation(L):
+    """A rigid translation has no strain, so u^T K u = 0 for every material and
+    orientation and its gradient vanishes (relative to the gradient of a
+    random u of the same norm)."""
+    rng = np.random.default_rng(91)
+    lam = W.random_small(rng, max_ply=5, n_mat=2)
+    plan = L.Plan(lam, set_mode="bucket")
+    C, th = _mats(lam)
+    u = torch.zeros(plan.n_rows, dtype=torch.float64, device="cuda")
+    u[0::3] = 1.0
+    u[1::3] = -0.5
+    u[2::3] = 0.25
+    gC0, gT0 = plan.adjoint_rank1(C, th, u)
+    v = torch.tensor(rng.standard_normal(plan.n_rows), device="cuda")
+    v *= u.norm() / v.norm()
+    gC1, gT1 = plan.adjoint_rank1(C, th, v)
+    rC = float(gC0.abs().max() / gC1.abs().max())
+    rT = float(gT0.abs().max() / max(float(gT1.abs().max()), 1e-300))
+    print("translation: dC %.3e  dtheta %.3e (relative)" % (rC, rT), flush=True)
+    assert rC <= 1e-10 and rT <= 1e-10
