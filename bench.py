@@ -192,6 +192,24 @@ def _adjoint_workload(torch, np, L, W, O, steps, warmup):
     return res
 
 
+def _apply_workload(torch, np, L, plan, C, th, vals, rowptr, colind, steps, warmup):
+    """y = K u on the headline plate: matrix-free (lam_apply, K never formed)
+    against multiplying the assembled K (torch's CSR matrix-vector product of
+    the values lam_assemble wrote), and against assembling K and then multiplying."""
+    u = torch.tensor(np.random.default_rng(11).standard_normal(plan.n_rows), device="cuda")
+    y = torch.empty_like(u)
+    ms_apply, ms_apply_k = _time_steps(torch, lambda: plan.apply(C, th, u, out=y), steps, warmup, L, "apply")
+    K = torch.sparse_csr_tensor(rowptr, colind.to(torch.int64), vals, size=(plan.n_rows, plan.n_rows))
+    y2 = torch.mv(K, u)
+    rel = float((y - y2).norm() / y2.norm())
+    ms_spmv, _ = _time_steps(torch, lambda: torch.mv(K, u), steps, warmup, L, "apply")
+    del K
+    torch.cuda.empty_cache()
+    return {"ms": ms_apply, "kernel_ms": ms_apply_k, "spmv_assembled_ms": ms_spmv,
+            "speedup_vs_spmv": ms_spmv / ms_apply, "rel_vs_assembled_spmv": rel,
+            "equivalent_nnz_per_s": plan.nnz / (ms_apply * 1e-3)}
+
+
 def _batch_workload(torch, np, L, W, O, wave_gb, reps):
     """The 256 uneven laminates, bucket sets, waves of at most wave_gb GiB of
     values + scratch, every wave captured in one HIP graph; one replay = the
@@ -370,6 +388,9 @@ def main():
         out["value_invalid"] = "sampled parity above 1e-12"
 
     extra = {}
+    if not args.no_extra:
+        extra["matrix_free_apply"] = _apply_workload(torch, np, L, plan, C, th, vals, rowptr, colind,
+                                                     max(10, args.steps), args.warmup)
     if not args.no_extra:
         try:
             ms_std, ms_std_k = _time_steps(torch, lambda: plan.assemble_standard(C, th, out=vals),

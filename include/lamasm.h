@@ -164,6 +164,16 @@ LAM_API lam_status lam_adjoint(const lam_plan *plan, void *ws, int64_t ws_bytes,
                                const double *theta, const double *grad_vals, int64_t nnz, double *grad_C,
                                double *grad_theta, void *stream);
 
+/* Matrix-free product y = K u (eq. Km_2 applied to a vector): the Kronecker
+ * split of lam_assemble evaluated against u without forming K.  u and y:
+ * device, n_rows doubles in the row order of lam_pattern; y is overwritten.
+ * Register-mode plans with one or two set slots (every bucket and per-ply
+ * plan with the automatic slot count); LAM_EUNSUP otherwise, LAM_ESIZE if
+ * n_rows is not the plan's row count.  The rounding order differs from
+ * multiplying the assembled K. */
+LAM_API lam_status lam_apply(const lam_plan *plan, void *ws, int64_t ws_bytes, const double *C, const double *theta,
+                             const double *u, int64_t n_rows, double *y, void *stream);
+
 /* Rank-one adjoint: the gradient of L = u^T K u (strain energy times two,
  * compliance) with respect to C and theta, i.e. lam_adjoint with
  * G = u u^T on the pattern of K, but G is never formed or read: each thread
@@ -232,14 +242,15 @@ LAM_API lam_status lam_batch_check(const lam_batch *batch, const void *ws, int64
 /* Kernel timing for measurement.  While enabled, every device entry point
  * records a pair of HIP events on its stream around its dominant kernel
  * (the Kronecker scatter of lam_assemble, the element kernel of
- * lam_assemble_standard, the streaming contraction of lam_adjoint, the
- * persistent kernel of lam_batch_assemble); no work is added or skipped.
+ * lam_assemble_standard, the streaming contraction of lam_adjoint and
+ * lam_adjoint_rank1, the scatter of lam_batch_assemble, the product kernel
+ * of lam_apply); no work is added or skipped.
  * lam_profile_read waits for the recorded events and returns the summed
  * milliseconds and the number of timed launches per entry point (index 0
- * assemble, 1 standard, 2 adjoint, 3 batch), then clears them.
+ * assemble, 1 standard, 2 adjoint, 3 batch, 4 apply), then clears them.
  * Up to 4096 launches are kept; later ones are not timed. */
 LAM_API lam_status lam_profile_enable(int32_t on);
-LAM_API lam_status lam_profile_read(double ms[4], int64_t launches[4]);
+LAM_API lam_status lam_profile_read(double ms[5], int64_t launches[5]);
 
 LAM_API const char *lam_status_string(lam_status s);
 

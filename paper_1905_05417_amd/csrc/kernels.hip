@@ -698,6 +698,110 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron_reg(Dev d, const double *
 }
 
 // ---------------------------------------------------------------------------
+// Matrix-free product y = K u (eq. Km_2 applied to a vector; K is never
+// formed).  Same blocks as the register-mode scatter (a tile of whole in-plane
+// rows x a group of thickness chunks, one or two set slots) and the same P in
+// registers per chunk; for every thickness row it of the group each thread
+// (k = (is, js), t) first contracts the row's thickness coefficients with u,
+//   V_u[ab] = sum_x Qd[zk_x][u][ab] u[3 (jt_x n_s + js) + t],
+// then forms its share c_r = sum_u sum_ab P_u[ab][r] V_u[ab] of
+// y[3 (it n_s + is) + r].  The shares of APPLY_ROWS thickness rows go to LDS
+// behind one barrier and are summed per (row, in-plane row, r) by one thread
+// each; every entry of y belongs to exactly one block, so no atomics.
+constexpr int APPLY_ROWS = 8;
+
+template <int NSC>
+__global__ void __launch_bounds__(KRON_THREADS) k_apply(Dev d, const double *__restrict__ qd,
+                                                        const double *__restrict__ u, double *__restrict__ y) {
+  static_assert(NSC <= 2, "the matrix-free product keeps at most two set slots");
+  // LDS: group coefficients (kron_lds_q bytes), set brackets (kron_lds_p
+  // bytes), then the shares c[APPLY_ROWS][3][blockDim]
+  extern __shared__ double lq[];
+  int tile, g;
+  if (!kron_block(d, tile, g)) return;
+  const int k0 = d.tiles[tile], tk = d.tiles[tile + 1] - k0;
+  const int sig = threadIdx.x, nth = blockDim.x;
+  const bool act = sig < 3 * tk;
+  const int kk = act ? sig / 3 : 0, t = act ? sig - 3 * kk : 0, k = k0 + kk;
+  double mv[4][9];
+#pragma unroll
+  for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+    for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[(int64_t)(ab * 9 + kl) * d.nnz2 + k];
+  const int js = d.kcol[k];
+  const int is0 = d.krow[k0], nrow = d.krow[k0 + tk - 1] - is0 + 1;  // the tile's in-plane rows
+  const int ch0 = d.group_ptr[g], ch1 = d.group_ptr[g + 1];
+  const int itg0 = d.chunk_ptr[ch0], itg1 = d.chunk_ptr[ch1];
+  const int zk0 = d.zrow[itg0], nq = 4 * NSC * (d.zrow[itg1] - zk0);
+  const int s0 = d.group_sptr[g], ns = d.group_sptr[g + 1] - s0;
+  double *le = lq + d.kron_lds_q / 8;
+  double *lc = le + d.kron_lds_p / 8;  // [APPLY_ROWS][3][nth]
+  for (int e = sig; e < 81 * (ns + 1); e += nth) {
+    const int w = e / 81;
+    le[e] = w < ns ? d.Ec[81 * (int64_t)d.group_set[s0 + w] + (e - 81 * w)] : 0.0;
+  }
+  for (int e = sig; e < nq; e += nth) lq[e] = qd[4 * (int64_t)NSC * zk0 + e];
+  __syncthreads();
+  double pr[NSC][4][3];
+  int ch = ch0 - 1, ch_end = itg0;  // chunk of the current row; its last row + 1
+  for (int b0 = itg0; b0 < itg1; b0 += APPLY_ROWS) {  // block-uniform trip counts and barriers
+    const int nb = itg1 - b0 < APPLY_ROWS ? itg1 - b0 : APPLY_ROWS;
+    for (int j = 0; j < nb; ++j) {
+      const int it = b0 + j;
+      while (it >= ch_end) {  // entering the next chunk: P of its slots
+        ++ch;
+        ch_end = d.chunk_ptr[ch + 1];
+        const int c0 = d.chunk_sptr[ch], nsc = d.chunk_sptr[ch + 1] - c0;
+#pragma unroll
+        for (int w = 0; w < NSC; ++w) {
+          const double *ew = le + 81 * (w < nsc ? d.chunk_lset[c0 + w] : ns);  // unused slots: zeros
+#pragma unroll
+          for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+              double a = 0.0;
+#pragma unroll
+              for (int kl = 0; kl < 9; ++kl) a += mv[ab][kl] * ew[kl * 9 + 3 * r + t];
+              pr[w][ab][r] = act ? a : 0.0;
+            }
+        }
+      }
+      const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
+      double v[NSC][4];
+#pragma unroll
+      for (int w = 0; w < NSC; ++w) v[w][0] = v[w][1] = v[w][2] = v[w][3] = 0.0;
+      for (int x = 0; x < Lz; ++x) {
+        const double ux = u[3 * ((int64_t)d.zcol[zb + x] * d.ns + js) + t];
+        const double *q = lq + 4 * NSC * (zb + x - zk0);
+#pragma unroll
+        for (int w = 0; w < NSC; ++w)
+#pragma unroll
+          for (int ab = 0; ab < 4; ++ab) v[w][ab] += q[4 * w + ab] * ux;
+      }
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        double c = 0.0;
+#pragma unroll
+        for (int w = 0; w < NSC; ++w)
+#pragma unroll
+          for (int ab = 0; ab < 4; ++ab) c += pr[w][ab][r] * v[w][ab];
+        lc[(3 * j + r) * nth + sig] = c;
+      }
+    }
+    __syncthreads();
+    for (int o = sig; o < 3 * nrow * nb; o += nth) {
+      const int j = o / (3 * nrow), rem = o - 3 * nrow * j, i = rem / 3, r = rem - 3 * i, is = is0 + i;
+      const int a0 = 3 * (d.srow[is] - k0), a1 = 3 * (d.srow[is + 1] - k0);
+      const double *src = lc + (3 * j + r) * nth;
+      double acc = 0.0;
+      for (int a = a0; a < a1; ++a) acc += src[a];
+      y[3 * ((int64_t)(b0 + j) * d.ns + is) + r] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Standard 3D assembly (the comparator of the method, Sec. 2.4).  One block
 // per 3D element = (in-plane element e1, e2) x (thickness knot span), with all
 // the ply cells inside the span; elements of one colour
@@ -1157,6 +1261,30 @@ extern "C" LAM_API lam_status lam_assemble(const lam_plan *p, void *ws, int64_t 
   }
   void *prof = lam::profile_begin(0, stream);
   launch_kron(p, d, vals, s);
+  lam::profile_end(prof, stream);
+  return hip_status();
+}
+
+extern "C" LAM_API lam_status lam_apply(const lam_plan *p, void *ws, int64_t ws_bytes, const double *C,
+                                        const double *theta, const double *u, int64_t n_rows, double *y,
+                                        void *stream) {
+  lam_status st = check_ws(p, ws, ws_bytes);
+  if (st != LAM_OK) return st;
+  if (!C || !theta || !u || !y) return LAM_EINVAL;
+  if (n_rows != p->nrows) return LAM_ESIZE;
+  if (p->kron_nsc < 1 || p->kron_nsc > 2) return LAM_EUNSUP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Dev d = make_dev(p, ws);
+  const int64_t nq = p->nnzz * p->kron_nsc;
+  const int nb_m = (int)((p->nnz2 + 255) / 256), nb_q = (int)((nq + 255) / 256);
+  hipLaunchKernelGGL(k_rotate, dim3((p->n_sets + 63) / 64), dim3(64), 0, s, d, C, theta);
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)(nb_m + nb_q)), dim3(256), 0, s, d, theta, nb_m);
+  const size_t lds = (size_t)(p->kron_lds + APPLY_ROWS * 3 * sizeof(double) * p->kron_threads);
+  void *prof = lam::profile_begin(4, stream);
+  if (p->kron_nsc == 1)
+    hipLaunchKernelGGL((k_apply<1>), dim3(kron_grid(p)), dim3(p->kron_threads), lds, s, d, d.Qc, u, y);
+  else
+    hipLaunchKernelGGL((k_apply<2>), dim3(kron_grid(p)), dim3(p->kron_threads), lds, s, d, d.Qc, u, y);
   lam::profile_end(prof, stream);
   return hip_status();
 }

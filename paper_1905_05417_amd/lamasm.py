@@ -61,7 +61,7 @@ def _make_tuning(t):
 _lib = None
 
 EXPORTED = ("lam_plan_create", "lam_plan_create_tuned", "lam_plan_destroy", "lam_plan_info", "lam_plan_upload", "lam_pattern",
-            "lam_assemble", "lam_assemble_standard", "lam_adjoint", "lam_adjoint_rank1",
+            "lam_assemble", "lam_assemble_standard", "lam_apply", "lam_adjoint", "lam_adjoint_rank1",
             "lam_batch_create", "lam_batch_create_tuned", "lam_batch_destroy", "lam_batch_info", "lam_batch_laminate", "lam_batch_upload",
             "lam_batch_pattern", "lam_batch_assemble", "lam_batch_check",
             "lam_profile_enable", "lam_profile_read", "lam_status_string", "lam_version")
@@ -88,6 +88,7 @@ def lib():
         L.lam_assemble_standard.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
         L.lam_adjoint.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
         L.lam_adjoint_rank1.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
+        L.lam_apply.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp]
         L.lam_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(_Desc), i64, ctypes.POINTER(vp)]
         L.lam_batch_destroy.argtypes = [vp]
         L.lam_batch_destroy.restype = None
@@ -232,6 +233,16 @@ class Plan:
                                  G.data_ptr(), G.numel(), gC.data_ptr(), gT.data_ptr(), _stream()), "lam_adjoint")
         return gC.view(self.n_mat, 6, 6), gT
 
+    def apply(self, C, theta, u, out=None):
+        """Matrix-free y = K u (lam_apply); K is never formed."""
+        ws = self._ws()
+        C, theta = self._inputs(C, theta)
+        u = u.to(dtype=torch.float64).contiguous()
+        y = torch.empty(self.n_rows, dtype=torch.float64, device=self.device) if out is None else out
+        _check(lib().lam_apply(self._h, ws.data_ptr(), self.ws_bytes, C.data_ptr(), theta.data_ptr(), u.data_ptr(),
+                               u.numel(), y.data_ptr(), _stream()), "lam_apply")
+        return y
+
     def adjoint_rank1(self, C, theta, u):
         """Gradient of L = u^T K u (lam_adjoint_rank1): G = u u^T is never formed."""
         ws = self._ws()
@@ -255,11 +266,11 @@ def profile_enable(on: bool = True):
 
 
 def profile_read():
-    """{'assemble'|'standard'|'adjoint'|'batch': (ms_total, launches)} since the last read."""
-    ms = (ctypes.c_double * 4)()
-    n = (ctypes.c_int64 * 4)()
+    """{'assemble'|'standard'|'adjoint'|'batch'|'apply': (ms_total, launches)} since the last read."""
+    ms = (ctypes.c_double * 5)()
+    n = (ctypes.c_int64 * 5)()
     _check(lib().lam_profile_read(ms, n), "lam_profile_read")
-    return {k: (ms[i], n[i]) for i, k in enumerate(("assemble", "standard", "adjoint", "batch"))}
+    return {k: (ms[i], n[i]) for i, k in enumerate(("assemble", "standard", "adjoint", "batch", "apply"))}
 
 
 class BatchPlan:
