@@ -192,7 +192,7 @@ def _adjoint_workload(torch, np, L, W, O, steps, warmup):
     return res
 
 
-def _apply_workload(torch, np, L, plan, C, th, vals, rowptr, colind, steps, warmup):
+def _apply_workload(torch, np, L, lam, plan, C, th, vals, rowptr, colind, steps, warmup):
     """y = K u on the headline plate: matrix-free (lam_apply, K never formed)
     against multiplying the assembled K (torch's CSR matrix-vector product of
     the values lam_assemble wrote), and against assembling K and then multiplying."""
@@ -205,9 +205,23 @@ def _apply_workload(torch, np, L, plan, C, th, vals, rowptr, colind, steps, warm
     ms_spmv, _ = _time_steps(torch, lambda: torch.mv(K, u), steps, warmup, L, "apply")
     del K
     torch.cuda.empty_cache()
+    # CG on the plate clamped along its first in-plane edge: a fixed number of
+    # iterations (tol 0), for the cost of one iteration and the residual reached
+    n1, n2 = len(lam.k1) - lam.p1 - 1, len(lam.k2) - lam.p2 - 1
+    rows = torch.arange(plan.n_rows, device="cuda")
+    fixed = ((rows // 3) % (n1 * n2)) % n1 == 0
+    b = torch.ones(plan.n_rows, dtype=torch.float64, device="cuda")
+    cg_iters = 200
+    plan.cg(C, th, b, fixed=fixed, tol=0.0, max_iter=5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, it, res = plan.cg(C, th, b, fixed=fixed, tol=0.0, max_iter=cg_iters)
+    ms_cg = (time.perf_counter() - t0) * 1e3
     return {"ms": ms_apply, "kernel_ms": ms_apply_k, "spmv_assembled_ms": ms_spmv,
             "speedup_vs_spmv": ms_spmv / ms_apply, "rel_vs_assembled_spmv": rel,
-            "equivalent_nnz_per_s": plan.nnz / (ms_apply * 1e-3)}
+            "equivalent_nnz_per_s": plan.nnz / (ms_apply * 1e-3),
+            "cg_clamped_edge": {"iterations": it, "ms_per_iteration": ms_cg / max(it, 1),
+                                "relative_residual": res, "fixed_rows": int(fixed.sum())}}
 
 
 def _batch_workload(torch, np, L, W, O, wave_gb, reps):
@@ -389,7 +403,7 @@ def main():
 
     extra = {}
     if not args.no_extra:
-        extra["matrix_free_apply"] = _apply_workload(torch, np, L, plan, C, th, vals, rowptr, colind,
+        extra["matrix_free_apply"] = _apply_workload(torch, np, L, lam, plan, C, th, vals, rowptr, colind,
                                                      max(10, args.steps), args.warmup)
     if not args.no_extra:
         try:

@@ -167,12 +167,31 @@ LAM_API lam_status lam_adjoint(const lam_plan *plan, void *ws, int64_t ws_bytes,
 /* Matrix-free product y = K u (eq. Km_2 applied to a vector): the Kronecker
  * split of lam_assemble evaluated against u without forming K.  u and y:
  * device, n_rows doubles in the row order of lam_pattern; y is overwritten.
- * Register-mode plans with one or two set slots (every bucket and per-ply
- * plan with the automatic slot count); LAM_EUNSUP otherwise, LAM_ESIZE if
- * n_rows is not the plan's row count.  The rounding order differs from
- * multiplying the assembled K. */
+ * fixed: NULL, or device bytes per row (nonzero = Dirichlet row) for the
+ * eliminated operator y = P K P u + (I - P) u, P the projection on the free
+ * rows.  Register-mode plans with one or two set slots (every bucket and
+ * per-ply plan with the automatic slot count); LAM_EUNSUP otherwise,
+ * LAM_ESIZE if n_rows is not the plan's row count.  The rounding order
+ * differs from multiplying the assembled K. */
 LAM_API lam_status lam_apply(const lam_plan *plan, void *ws, int64_t ws_bytes, const double *C, const double *theta,
-                             const double *u, int64_t n_rows, double *y, void *stream);
+                             const double *u, const uint8_t *fixed, int64_t n_rows, double *y, void *stream);
+
+/* Conjugate gradients for K x = b with homogeneous Dirichlet rows eliminated:
+ * solves (P K P + I - P) x = P b (fixed as for lam_apply, NULL for none, then
+ * K itself must be nonsingular on the data), starting from the x given
+ * (device, n_rows doubles, overwritten), until ||r|| <= tol ||P b|| or
+ * max_iter iterations.  Every product is lam_apply's; vector updates and dot
+ * products are kernels of their own with device-side scalars.  work: device,
+ * at least lam_cg_work_bytes(plan) bytes, 8-byte aligned.  Unlike the other
+ * entry points it waits on the stream after every iteration (to test the
+ * residual); *iters and *rel_res (host) receive the iteration count and the
+ * final relative residual.  LAM_ESIZE for a short work buffer or a wrong
+ * n_rows; LAM_EUNSUP as for lam_apply. */
+LAM_API int64_t lam_cg_work_bytes(const lam_plan *plan);
+LAM_API lam_status lam_cg(const lam_plan *plan, void *ws, int64_t ws_bytes, const double *C, const double *theta,
+                          const uint8_t *fixed, const double *b, double *x, int64_t n_rows, void *work,
+                          int64_t work_bytes, double tol, int32_t max_iter, int32_t *iters, double *rel_res,
+                          void *stream);
 
 /* Rank-one adjoint: the gradient of L = u^T K u (strain energy times two,
  * compliance) with respect to C and theta, i.e. lam_adjoint with

@@ -708,11 +708,15 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron_reg(Dev d, const double *
 // y[3 (it n_s + is) + r].  The shares of APPLY_ROWS thickness rows go to LDS
 // behind one barrier and are summed per (row, in-plane row, r) by one thread
 // each; every entry of y belongs to exactly one block, so no atomics.
+// fixed (nullable, one byte per row): Dirichlet elimination, y = P K P u +
+// (I - P) u with P the projection on the free rows (fixed entries of u read
+// as 0, fixed rows of y copy u).
 constexpr int APPLY_ROWS = 8;
 
 template <int NSC>
 __global__ void __launch_bounds__(KRON_THREADS) k_apply(Dev d, const double *__restrict__ qd,
-                                                        const double *__restrict__ u, double *__restrict__ y) {
+                                                        const double *__restrict__ u,
+                                                        const uint8_t *__restrict__ fixed, double *__restrict__ y) {
   static_assert(NSC <= 2, "the matrix-free product keeps at most two set slots");
   // LDS: group coefficients (kron_lds_q bytes), set brackets (kron_lds_p
   // bytes), then the shares c[APPLY_ROWS][3][blockDim]
@@ -771,7 +775,8 @@ __global__ void __launch_bounds__(KRON_THREADS) k_apply(Dev d, const double *__r
 #pragma unroll
       for (int w = 0; w < NSC; ++w) v[w][0] = v[w][1] = v[w][2] = v[w][3] = 0.0;
       for (int x = 0; x < Lz; ++x) {
-        const double ux = u[3 * ((int64_t)d.zcol[zb + x] * d.ns + js) + t];
+        const int64_t col = 3 * ((int64_t)d.zcol[zb + x] * d.ns + js) + t;
+        const double ux = fixed && fixed[col] ? 0.0 : u[col];
         const double *q = lq + 4 * NSC * (zb + x - zk0);
 #pragma unroll
         for (int w = 0; w < NSC; ++w)
@@ -795,7 +800,8 @@ __global__ void __launch_bounds__(KRON_THREADS) k_apply(Dev d, const double *__r
       const double *src = lc + (3 * j + r) * nth;
       double acc = 0.0;
       for (int a = a0; a < a1; ++a) acc += src[a];
-      y[3 * ((int64_t)(b0 + j) * d.ns + is) + r] = acc;
+      const int64_t row = 3 * ((int64_t)(b0 + j) * d.ns + is) + r;
+      y[row] = fixed && fixed[row] ? u[row] : acc;
     }
     __syncthreads();
   }
@@ -1265,9 +1271,33 @@ extern "C" LAM_API lam_status lam_assemble(const lam_plan *p, void *ws, int64_t 
   return hip_status();
 }
 
+namespace {
+
+// The set tensors and the moments and 1D coefficients the register-mode
+// scatter and the matrix-free product read.
+void launch_prep(const lam_plan *p, const Dev &d, const double *C, const double *theta, hipStream_t s) {
+  const int64_t nq = p->nnzz * p->kron_nsc;
+  const int nb_m = (int)((p->nnz2 + 255) / 256), nb_q = (int)((nq + 255) / 256);
+  hipLaunchKernelGGL(k_rotate, dim3((p->n_sets + 63) / 64), dim3(64), 0, s, d, C, theta);
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)(nb_m + nb_q)), dim3(256), 0, s, d, theta, nb_m);
+}
+
+void launch_apply(const lam_plan *p, const Dev &d, const double *u, const uint8_t *fixed, double *y, void *stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t lds = (size_t)(p->kron_lds + APPLY_ROWS * 3 * sizeof(double) * p->kron_threads);
+  void *prof = lam::profile_begin(4, stream);
+  if (p->kron_nsc == 1)
+    hipLaunchKernelGGL((k_apply<1>), dim3(kron_grid(p)), dim3(p->kron_threads), lds, s, d, d.Qc, u, fixed, y);
+  else
+    hipLaunchKernelGGL((k_apply<2>), dim3(kron_grid(p)), dim3(p->kron_threads), lds, s, d, d.Qc, u, fixed, y);
+  lam::profile_end(prof, stream);
+}
+
+}  // namespace
+
 extern "C" LAM_API lam_status lam_apply(const lam_plan *p, void *ws, int64_t ws_bytes, const double *C,
-                                        const double *theta, const double *u, int64_t n_rows, double *y,
-                                        void *stream) {
+                                        const double *theta, const double *u, const uint8_t *fixed,
+                                        int64_t n_rows, double *y, void *stream) {
   lam_status st = check_ws(p, ws, ws_bytes);
   if (st != LAM_OK) return st;
   if (!C || !theta || !u || !y) return LAM_EINVAL;
@@ -1275,17 +1305,133 @@ extern "C" LAM_API lam_status lam_apply(const lam_plan *p, void *ws, int64_t ws_
   if (p->kron_nsc < 1 || p->kron_nsc > 2) return LAM_EUNSUP;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Dev d = make_dev(p, ws);
-  const int64_t nq = p->nnzz * p->kron_nsc;
-  const int nb_m = (int)((p->nnz2 + 255) / 256), nb_q = (int)((nq + 255) / 256);
-  hipLaunchKernelGGL(k_rotate, dim3((p->n_sets + 63) / 64), dim3(64), 0, s, d, C, theta);
-  hipLaunchKernelGGL(k_prep, dim3((unsigned)(nb_m + nb_q)), dim3(256), 0, s, d, theta, nb_m);
-  const size_t lds = (size_t)(p->kron_lds + APPLY_ROWS * 3 * sizeof(double) * p->kron_threads);
-  void *prof = lam::profile_begin(4, stream);
-  if (p->kron_nsc == 1)
-    hipLaunchKernelGGL((k_apply<1>), dim3(kron_grid(p)), dim3(p->kron_threads), lds, s, d, d.Qc, u, y);
-  else
-    hipLaunchKernelGGL((k_apply<2>), dim3(kron_grid(p)), dim3(p->kron_threads), lds, s, d, d.Qc, u, y);
-  lam::profile_end(prof, stream);
+  launch_prep(p, d, C, theta, s);
+  launch_apply(p, d, u, fixed, y, stream);
+  return hip_status();
+}
+
+// ---------------------------------------------------------------------------
+// Conjugate gradients on the Dirichlet-eliminated operator A = P K P + (I - P)
+// (P: projection on the free rows) with right-hand side P b, so the fixed
+// entries of the solution go to zero: every vector operation is a kernel,
+// the scalars stay on the device, the dot products are two-stage fixed-order
+// sums (deterministic).  work (doubles): r, p, q = A p (n each), CG_PARTS
+// partial sums, 4 scalars {r.r, p.q, new r.r, P b . P b}.
+constexpr int CG_PARTS = 512;
+
+__global__ void __launch_bounds__(256) k_dot_partial(const double *__restrict__ a, const double *__restrict__ b,
+                                                     const uint8_t *__restrict__ fixed, int64_t n,
+                                                     double *__restrict__ part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    if (!(fixed && fixed[i])) acc += a[i] * b[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_dot_final(const double *__restrict__ part, double *__restrict__ out) {
+  __shared__ double sh[256];
+  sh[threadIdx.x] = part[threadIdx.x] + part[threadIdx.x + 256];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// r = P b - A x, p = r
+__global__ void k_cg_init(int64_t n, const double *__restrict__ b, const double *__restrict__ ax,
+                          const uint8_t *__restrict__ fixed, double *__restrict__ r, double *__restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = (fixed && fixed[i] ? 0.0 : b[i]) - ax[i];
+  r[i] = v;
+  p[i] = v;
+}
+
+// alpha = (r.r) / (p.q); x += alpha p; r -= alpha q
+__global__ void k_cg_step(int64_t n, const double *__restrict__ scal, const double *__restrict__ p,
+                          const double *__restrict__ q, double *__restrict__ x, double *__restrict__ r) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double alpha = scal[0] / scal[1];
+  x[i] += alpha * p[i];
+  r[i] -= alpha * q[i];
+}
+
+// beta = (new r.r) / (r.r); p = r + beta p
+__global__ void k_cg_dir(int64_t n, const double *__restrict__ scal, const double *__restrict__ r,
+                         double *__restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  p[i] = r[i] + (scal[2] / scal[0]) * p[i];
+}
+
+__global__ void k_scalar_copy(double *__restrict__ scal, int to, int from) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) scal[to] = scal[from];
+}
+
+namespace {
+
+void launch_dot(const double *a, const double *b, const uint8_t *fixed, int64_t n, double *part, double *out,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(CG_PARTS), dim3(256), 0, s, a, b, fixed, n, part);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, part, out);
+}
+
+}  // namespace
+
+extern "C" LAM_API int64_t lam_cg_work_bytes(const lam_plan *p) {
+  return p ? (int64_t)sizeof(double) * (3 * p->nrows + CG_PARTS + 4) : 0;
+}
+
+extern "C" LAM_API lam_status lam_cg(const lam_plan *p, void *ws, int64_t ws_bytes, const double *C,
+                                     const double *theta, const uint8_t *fixed, const double *b, double *x,
+                                     int64_t n_rows, void *work, int64_t work_bytes, double tol, int32_t max_iter,
+                                     int32_t *iters, double *rel_res, void *stream) {
+  lam_status st = check_ws(p, ws, ws_bytes);
+  if (st != LAM_OK) return st;
+  if (!C || !theta || !b || !x || !work || !iters || !rel_res || max_iter < 0 || !(tol >= 0.0)) return LAM_EINVAL;
+  if (n_rows != p->nrows || work_bytes < lam_cg_work_bytes(p)) return LAM_ESIZE;
+  if (p->kron_nsc < 1 || p->kron_nsc > 2) return LAM_EUNSUP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Dev d = make_dev(p, ws);
+  const int64_t n = n_rows;
+  double *r = static_cast<double *>(work), *pv = r + n, *q = pv + n, *part = q + n, *scal = part + CG_PARTS;
+  const dim3 vg((unsigned)((n + 255) / 256)), vb(256);
+  launch_prep(p, d, C, theta, s);
+  launch_apply(p, d, x, fixed, q, stream);
+  hipLaunchKernelGGL(k_cg_init, vg, vb, 0, s, n, b, q, fixed, r, pv);
+  launch_dot(b, b, fixed, n, part, scal + 3, s);
+  launch_dot(r, r, nullptr, n, part, scal + 0, s);
+  double host[4];
+  if (hipMemcpyAsync(host, scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return LAM_EHIP;
+  const double bb = host[3];
+  double rr = host[0];
+  int it = 0;
+  while (it < max_iter && !(bb > 0.0 ? rr <= tol * tol * bb : rr == 0.0)) {
+    launch_apply(p, d, pv, fixed, q, stream);
+    launch_dot(pv, q, nullptr, n, part, scal + 1, s);
+    hipLaunchKernelGGL(k_cg_step, vg, vb, 0, s, n, scal, pv, q, x, r);
+    launch_dot(r, r, nullptr, n, part, scal + 2, s);
+    hipLaunchKernelGGL(k_cg_dir, vg, vb, 0, s, n, scal, r, pv);
+    hipLaunchKernelGGL(k_scalar_copy, dim3(1), dim3(64), 0, s, scal, 0, 2);
+    if (hipMemcpyAsync(&rr, scal + 2, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return LAM_EHIP;
+    ++it;
+  }
+  *iters = it;
+  *rel_res = bb > 0.0 ? sqrt(rr / bb) : sqrt(rr);
   return hip_status();
 }
 

@@ -61,7 +61,7 @@ def _make_tuning(t):
 _lib = None
 
 EXPORTED = ("lam_plan_create", "lam_plan_create_tuned", "lam_plan_destroy", "lam_plan_info", "lam_plan_upload", "lam_pattern",
-            "lam_assemble", "lam_assemble_standard", "lam_apply", "lam_adjoint", "lam_adjoint_rank1",
+            "lam_assemble", "lam_assemble_standard", "lam_apply", "lam_cg", "lam_cg_work_bytes", "lam_adjoint", "lam_adjoint_rank1",
             "lam_batch_create", "lam_batch_create_tuned", "lam_batch_destroy", "lam_batch_info", "lam_batch_laminate", "lam_batch_upload",
             "lam_batch_pattern", "lam_batch_assemble", "lam_batch_check",
             "lam_profile_enable", "lam_profile_read", "lam_status_string", "lam_version")
@@ -88,7 +88,11 @@ def lib():
         L.lam_assemble_standard.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
         L.lam_adjoint.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
         L.lam_adjoint_rank1.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
-        L.lam_apply.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp]
+        L.lam_apply.argtypes = [vp, vp, i64, vp, vp, vp, vp, i64, vp, vp]
+        L.lam_cg_work_bytes.argtypes = [vp]
+        L.lam_cg_work_bytes.restype = i64
+        L.lam_cg.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, i64, vp, i64, ctypes.c_double, ctypes.c_int32,
+                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), vp]
         L.lam_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(_Desc), i64, ctypes.POINTER(vp)]
         L.lam_batch_destroy.argtypes = [vp]
         L.lam_batch_destroy.restype = None
@@ -233,15 +237,36 @@ class Plan:
                                  G.data_ptr(), G.numel(), gC.data_ptr(), gT.data_ptr(), _stream()), "lam_adjoint")
         return gC.view(self.n_mat, 6, 6), gT
 
-    def apply(self, C, theta, u, out=None):
-        """Matrix-free y = K u (lam_apply); K is never formed."""
+    def apply(self, C, theta, u, out=None, fixed=None):
+        """Matrix-free y = K u (lam_apply); K is never formed.  fixed: optional
+        bool/uint8 tensor per row, Dirichlet rows (y = P K P u + (I - P) u)."""
         ws = self._ws()
         C, theta = self._inputs(C, theta)
         u = u.to(dtype=torch.float64).contiguous()
+        fx = None if fixed is None else fixed.to(device=self.device, dtype=torch.uint8).contiguous()
         y = torch.empty(self.n_rows, dtype=torch.float64, device=self.device) if out is None else out
         _check(lib().lam_apply(self._h, ws.data_ptr(), self.ws_bytes, C.data_ptr(), theta.data_ptr(), u.data_ptr(),
-                               u.numel(), y.data_ptr(), _stream()), "lam_apply")
+                               None if fx is None else fx.data_ptr(), u.numel(), y.data_ptr(), _stream()),
+               "lam_apply")
         return y
+
+    def cg(self, C, theta, b, fixed=None, x0=None, tol=1e-10, max_iter=10000):
+        """Conjugate gradients for K x = b with the Dirichlet rows `fixed`
+        eliminated (lam_cg); returns (x, iterations, relative residual)."""
+        ws = self._ws()
+        C, theta = self._inputs(C, theta)
+        b = b.to(dtype=torch.float64).contiguous()
+        x = torch.zeros(self.n_rows, dtype=torch.float64, device=self.device) if x0 is None else \
+            x0.to(dtype=torch.float64).clone()
+        fx = None if fixed is None else fixed.to(device=self.device, dtype=torch.uint8).contiguous()
+        nw = int(lib().lam_cg_work_bytes(self._h))
+        work = torch.empty((nw + 7) // 8, dtype=torch.float64, device=self.device)
+        iters, res = ctypes.c_int32(), ctypes.c_double()
+        _check(lib().lam_cg(self._h, ws.data_ptr(), self.ws_bytes, C.data_ptr(), theta.data_ptr(),
+                            None if fx is None else fx.data_ptr(), b.data_ptr(), x.data_ptr(), x.numel(),
+                            work.data_ptr(), work.numel() * 8, float(tol), int(max_iter), ctypes.byref(iters),
+                            ctypes.byref(res), _stream()), "lam_cg")
+        return x, iters.value, res.value
 
     def adjoint_rank1(self, C, theta, u):
         """Gradient of L = u^T K u (lam_adjoint_rank1): G = u u^T is never formed."""

@@ -100,3 +100,50 @@ def test_apply_full_plate(oracle, L):
     rel2 = float((y - y2).norm() / y2.norm())
     print("vs assembled K on the GPU rel %.3e" % rel2, flush=True)
     assert rel2 <= TOL
+
+
+def _clamped_rows(lam, n_rows):
+    """Rows of the functions on the first in-plane edge (i1 = 0): all
+    thickness functions and components there are fixed."""
+    n1 = len(lam.k1) - lam.p1 - 1
+    n2 = len(lam.k2) - lam.p2 - 1
+    rows = np.arange(n_rows)
+    return (((rows // 3) % (n1 * n2)) % n1 == 0)
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_apply_dirichlet_and_cg(oracle, L, case):
+    """Eliminated operator P K P u + (I - P) u against the oracle's K, and CG
+    for the clamped laminate to a recurrence residual of 1e-12: the normwise
+    backward error of x against the oracle's K_ff, ||K_ff x_f - b_f|| /
+    (||K_ff|| ||x_f|| + ||b_f||) with the Frobenius norm, is below 1e-12 (the
+    true residual itself can exceed the recurrence's by cond(K_ff) times the
+    rounding of the products), and the fixed entries of x are zero."""
+    rng = np.random.default_rng(7500 + case)
+    lam = W.config_q1_8x8() if case == 0 else W.random_small(rng, max_ply=5, n_mat=2)
+    mode = ("bucket", "ply")[case % 2]
+    rp, ci, ref = oracle.assemble(lam)
+    n = len(rp) - 1
+    K = oracle.to_scipy(rp, ci, ref, n)
+    fixed = _clamped_rows(lam, n)
+    free = ~fixed
+    plan = L.Plan(lam, set_mode=mode)
+    C, th = _mats(lam)
+    fx = torch.tensor(fixed, device="cuda")
+    u = rng.standard_normal(n)
+    y = plan.apply(C, th, torch.tensor(u, device="cuda"), fixed=fx).cpu().numpy()
+    yr = np.where(free, K @ np.where(free, u, 0.0), u)
+    e_apply = float(np.linalg.norm(y - yr) / np.linalg.norm(yr))
+    b = rng.standard_normal(n)
+    x, iters, res = plan.cg(C, th, torch.tensor(b, device="cuda"), fixed=fx, tol=1e-12, max_iter=50 * n)
+    x = x.cpu().numpy()
+    Kff = K[free][:, free]
+    r = Kff @ x[free] - b[free]
+    e_cg = float(np.linalg.norm(r) / (np.sqrt(Kff.multiply(Kff).sum()) * np.linalg.norm(x[free]) +
+                                      np.linalg.norm(b[free])))
+    print("case %d n %d: apply rel %.2e, cg %d iterations, residual %.2e (oracle K: backward error %.2e, "
+          "relative residual %.2e)" % (case, n, e_apply, iters, res, e_cg,
+                                        np.linalg.norm(r) / np.linalg.norm(b[free])), flush=True)
+    assert e_apply <= TOL
+    assert res <= 1e-12 and e_cg <= 1e-12
+    assert np.abs(x[fixed]).max() == 0.0
