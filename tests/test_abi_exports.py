@@ -124,3 +124,55 @@ def test_tuning_validation_and_cache_lookup():
     for lam in [W.config_p2_64x64_32ply(), W.config_p3_128x128_128ply()] + W.batch_laminates(16):
         t = autotune.lookup(lam, "bucket", cache)
         assert t is not None and set(t) <= {"tile_k", "set_slots", "target_blocks", "lds_kib"}
+
+
+def test_product_cg_rank1_argument_errors():
+    """lam_apply, lam_cg and lam_adjoint_rank1 reject bad arguments on the host,
+    before any device work (a host buffer stands in for the workspace)."""
+    import numpy as np
+    from paper_1905_05417_amd import lamasm, workloads as W
+    try:
+        lib = lamasm.lib()
+    except (RuntimeError, OSError) as e:
+        pytest.skip("library not built: %s" % e)
+
+    def plan(mode):
+        d, keep = lamasm._make_desc(W.config_q1_8x8(), mode)
+        h = ctypes.c_void_p()
+        assert lib.lam_plan_create(ctypes.byref(d), ctypes.byref(h)) == 0
+        nr, nz, wb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        assert lib.lam_plan_info(h, ctypes.byref(nr), ctypes.byref(nz), ctypes.byref(wb), None, None, None) == 0
+        return h, nr.value, wb.value
+
+    h, n, wb = plan("bucket")
+    raw = np.zeros(wb + 512, dtype=np.uint8)
+    ws = raw.ctypes.data + (-raw.ctypes.data) % 256
+    buf = np.zeros(max(n, 64), dtype=np.float64)
+    p = buf.ctypes.data
+    it, res = ctypes.c_int32(), ctypes.c_double()
+    assert lib.lam_cg_work_bytes(h) == 8 * (3 * n + 512 + 4)
+    # wrong row count
+    assert lib.lam_apply(h, ws, wb, p, p, p, None, n + 1, p, None) == -5
+    assert lib.lam_adjoint_rank1(h, ws, wb, p, p, p, n - 1, p, p, None) == -5
+    assert lib.lam_cg(h, ws, wb, p, p, None, p, p, n + 1, p, 1 << 30, 1e-8, 10, ctypes.byref(it), ctypes.byref(res),
+                      None) == -5
+    # missing pointers, short work buffer, bad tolerance or iteration count
+    assert lib.lam_apply(h, ws, wb, p, p, None, None, n, p, None) == -1
+    assert lib.lam_cg(h, ws, wb, p, p, None, p, p, n, p, 16, 1e-8, 10, ctypes.byref(it), ctypes.byref(res),
+                      None) == -5
+    assert lib.lam_cg(h, ws, wb, p, p, None, p, p, n, p, 1 << 30, -1.0, 10, ctypes.byref(it), ctypes.byref(res),
+                      None) == -1
+    assert lib.lam_cg(h, ws, wb, p, p, None, p, p, n, p, 1 << 30, 1e-8, -1, ctypes.byref(it), ctypes.byref(res),
+                      None) == -1
+    # short or misaligned workspace
+    assert lib.lam_apply(h, ws, wb - 1, p, p, p, None, n, p, None) == -5
+    assert lib.lam_apply(h, ws + 8, wb, p, p, p, None, n, p, None) == -1
+    lib.lam_plan_destroy(h)
+    # harmonic plans keep more than two slots per chunk: the product is unsupported
+    h, n, wb = plan("harmonic9")
+    raw = np.zeros(wb + 512, dtype=np.uint8)
+    ws = raw.ctypes.data + (-raw.ctypes.data) % 256
+    buf = np.zeros(n, dtype=np.float64)
+    p = buf.ctypes.data
+    assert lib.lam_apply(h, ws, wb, p, p, p, None, n, p, None) == -7
+    lib.lam_plan_destroy(h)
