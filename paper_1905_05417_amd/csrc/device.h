@@ -443,13 +443,19 @@ __device__ __forceinline__ void item_kron_reg(const Dev &d, const double *__rest
   const int64_t astride = 3 * (int64_t)Ls;
   __syncthreads();
   if (act) {
+    double pr[NSC][4][3];
+    int slot_set[NSC];  // group-local set of each slot's P
+#pragma unroll
+    for (int u = 0; u < NSC; ++u) slot_set[u] = -1;
     for (int ch = ch0; ch < ch1; ++ch) {
       const int it0 = d.chunk_ptr[ch], it1 = d.chunk_ptr[ch + 1];
       const int c0 = d.chunk_sptr[ch], nsc = d.chunk_sptr[ch + 1] - c0;
-      double pr[NSC][4][3];
 #pragma unroll
       for (int u = 0; u < NSC; ++u) {
-        const double *eu = le + 81 * (u < nsc ? d.chunk_lset[c0 + u] : ns);  // unused slots: zeros
+        const int ls = u < nsc ? d.chunk_lset[c0 + u] : ns;  // unused slots: the zero block
+        if (ls == slot_set[u]) continue;  // the slot keeps its set (and P) from the previous chunk
+        slot_set[u] = ls;
+        const double *eu = le + 81 * ls;
 #pragma unroll
         for (int ab = 0; ab < 4; ++ab)
 #pragma unroll

@@ -491,12 +491,22 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
     int start = 0;
     int64_t qbytes = 0;
     const bool by_sets = reg_mode || lds_sets;
+    std::vector<int> prev;  // the previous chunk's sets, in slot order
     auto flush = [&](int end) {
+      // slot order: a set the previous chunk also had keeps its slot where it
+      // fits, so that the scatter recomputes P only for the slots that change
       std::sort(cur.begin(), cur.end());
+      std::vector<int> ord(cur.size(), -1);
+      for (size_t w = 0; w < prev.size() && w < ord.size(); ++w)
+        if (std::binary_search(cur.begin(), cur.end(), prev[w])) ord[w] = prev[w];
+      for (int sset : cur)
+        if (std::find(ord.begin(), ord.end(), sset) == ord.end()) *std::find(ord.begin(), ord.end(), -1) = sset;
+      cur = ord;
+      prev = ord;
       for (int it = start; it < end; ++it) {
         zchunk[it] = (int)chunk_ptr.size() - 1;
         for (int j = zaptr[it]; j < zaptr[it + 1]; ++j)
-          zaslot[j] = by_sets ? (int)(std::lower_bound(cur.begin(), cur.end(), zaset[j]) - cur.begin()) : 0;
+          zaslot[j] = by_sets ? (int)(std::find(cur.begin(), cur.end(), zaset[j]) - cur.begin()) : 0;
       }
       chunk_set.insert(chunk_set.end(), cur.begin(), cur.end());
       chunk_sptr.push_back((int)chunk_set.size());
