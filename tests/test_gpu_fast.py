@@ -112,9 +112,9 @@ def test_deterministic(oracle, L):
     assert torch.equal(a, b)
 
 
-def _sampled_rows(oracle, L, lam, mode, n_rand=1500, seed=5):
-    plan = L.Plan(lam, set_mode=mode)
-    print("case", lam.name, mode, "nnz", plan.nnz, flush=True)
+def _sampled_rows(oracle, L, lam, mode, n_rand=1500, seed=5, tuning=None):
+    plan = L.Plan(lam, set_mode=mode, tuning=tuning)
+    print("case", lam.name, mode, tuning, "nnz", plan.nnz, flush=True)
     rowptr, colind = plan.pattern()
     C, th = _mats(lam)
     vals = plan.assemble(C, th)
@@ -150,3 +150,19 @@ def test_full_size_p2_64x64_32ply_sampled(oracle, L):
 
 def test_full_size_adjoint_plate_sampled(oracle, L):
     _sampled_rows(oracle, L, W.config_adjoint_p2_96x96_64ply(), "harmonic5", n_rand=800)
+
+
+def test_full_size_adjoint_plate_sampled_one_set_per_ply(oracle, L):
+    """64 plies with seeded random angles, one set per ply: every chunk holds
+    one ply, groups of chunks share the block (the grouped scatter at full size)."""
+    from paper_1905_05417_amd import autotune
+    lam = W.config_adjoint_p2_96x96_64ply()
+    _sampled_rows(oracle, L, lam, "ply", n_rand=800, tuning=autotune.lookup(lam, "bucket"))
+
+
+def test_full_size_p3_128x128_128ply_sampled(oracle, L):
+    """The 128-ply degree-3 plate (7.6e9 nonzeros, 60 GB of values) with the
+    tuned scatter of the benchmark: sampled rows against the oracle."""
+    from paper_1905_05417_amd import autotune
+    lam = W.config_p3_128x128_128ply()
+    _sampled_rows(oracle, L, lam, "bucket", n_rand=400, tuning=autotune.lookup(lam, "bucket"))
