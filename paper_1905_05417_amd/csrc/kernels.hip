@@ -2,16 +2,20 @@
 // entry points of the C ABI.
 //
 // Path of lam_assemble (all kernels on the caller's stream, FP64):
-//   k_rotate   per set: rotated 6x6 D_s (bucket) or its angular harmonic
-//              (harmonic mode), and the 81 coefficients
+//   k_rotate   per set: rotated 6x6 D_s (bucket, per ply) or its angular
+//              harmonic (harmonic mode), and the 81 coefficients
 //              E_s[k][l][r][t] = [B(e_k)^T D_s B(e_l)]_{rt}   (eq. B_1, eq. D)
-//   k_p2d      per in-plane nonzero: 2D Gauss quadrature of the geometric
-//              moments of grad V and W, contracted with every set's E_s:
-//              P_{s,ab}^{is js}                                     (eq. P)
-//   k_q1d      per thickness nonzero and active set: the 1D integrals Q_l
-//              summed over the set's plies with their weights      (eq. Q)
-//   k_kron     every nonzero of K written once, in CSR order:
+//   k_prep     per in-plane nonzero: the set-independent moments of grad V
+//              and W, each a product of two 1D Gauss sums (eq. P without
+//              the material); per thickness nonzero and set slot: the 1D
+//              integrals Q_l summed over the set's plies          (eq. Q)
+//   k_kron_reg every nonzero of K written once, in CSR order, with
+//              P_s = moments x E_s formed in registers:
 //              sum_sets sum_ab Qbar ⊗ P                          (eq. Km_2)
+// (LDS mode, more than eight sets on a thickness row: k_p2d stores P of
+// every set, k_q1d, k_kron_lds.)  Also here: the standard 3D assembly, the
+// adjoint and its rank-one form, the matrix-free product and CG, and the
+// pattern kernels.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
