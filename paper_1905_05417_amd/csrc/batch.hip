@@ -190,8 +190,9 @@ extern "C" LAM_API lam_status lam_batch_create_tuned(int32_t n, const lam_lamina
       return st;
     }
     B->plans.push_back(p);
-    // the scatter kernel holds exactly two set slots per thread
-    if (p->kron_nsc != 2 || 3 * p->tile_k > BATCH_THREADS) {
+    // the scatter kernel holds exactly two set slots per thread; harmonic
+    // sets evaluated per ply (their per-ply tensors) are not batched
+    if (p->kron_nsc != 2 || 3 * p->tile_k > BATCH_THREADS || p->harm_ply) {
       lam_batch_destroy(B);
       return LAM_EUNSUP;
     }

@@ -38,6 +38,8 @@ struct Dev {
   const int *a1f, *a1c, *a2f, *a2c, *zs_first, *zs_cptr, *zs_cell;
   int ne1, ne2, nzs;
   double *Eply;
+  const double *Escat;  // bracket coefficients of the scatter's sets (Ec: batches hold no per-ply harmonic plans)
+  int harm_ply;
   const int *rowply, *rowfin;
   double *Qp, *adj_part, *adj_y, *adj_dD;
   // scratch
@@ -96,12 +98,14 @@ inline Dev make_dev_split(const lam_plan *p, void *cbase, void *sbase) {
   d.zs_first = at<int>(cbase, L.zs_first); d.zs_cptr = at<int>(cbase, L.zs_cptr); d.zs_cell = at<int>(cbase, L.zs_cell);
   d.ne1 = p->ne1; d.ne2 = p->ne2; d.nzs = p->nzs;
   d.Eply = at<double>(sb, L.Eply);
+  d.harm_ply = p->harm_ply;
   d.rowply = at<int>(cbase, L.rowply); d.rowfin = at<int>(cbase, L.rowfin);
   d.Qp = at<double>(sb, L.Qp); d.adj_part = at<double>(sb, L.adj_part);
   d.adj_y = at<double>(sb, L.adj_y); d.adj_dD = at<double>(sb, L.adj_dD);
   d.kron_nsc = p->kron_nsc;
   d.kron_lds_p = p->kron_lds_p;
   d.D = at<double>(sb, L.D); d.Ec = at<double>(sb, L.Ec); d.P = at<double>(sb, L.P);
+  d.Escat = d.Ec;
   d.Qc = at<double>(sb, L.Qc); d.M = at<double>(sb, L.M);
   return d;
 }

@@ -85,6 +85,7 @@ struct lam_plan {
   int64_t kron_lds = 0;             // LDS bytes of the scatter kernel
   int kron_nsc = 0;                 // register mode: set slots per thread (0: LDS mode)
   int kron_threads = 256;           // scatter block size
+  int harm_ply = 0;                 // harmonic sets evaluated per ply (scatter sets are the plies)
   int64_t kron_lds_q = 0, kron_lds_p = 0;  // LDS bytes of the Q and P parts (output buffer follows)
   double jit[9] = {0};  // DF^{-T}, row-major
   double detj = 0.0;    // |det DF|

@@ -52,6 +52,8 @@ struct Dev {
   const int *a1f, *a1c, *a2f, *a2c, *zs_first, *zs_cptr, *zs_cell;
   int ne1, ne2, nzs;
   double *Eply;
+  const double *Escat;  // bracket coefficients of the scatter's sets: Ec, or Eply for harmonic plans
+  int harm_ply;
   const int *rowply, *rowfin;
   double *Qp, *adj_part, *adj_y, *adj_dD;
   // scratch
@@ -106,12 +108,14 @@ Dev make_dev(const lam_plan *p, void *ws) {
   d.zs_first = at<int>(ws, L.zs_first); d.zs_cptr = at<int>(ws, L.zs_cptr); d.zs_cell = at<int>(ws, L.zs_cell);
   d.ne1 = p->ne1; d.ne2 = p->ne2; d.nzs = p->nzs;
   d.Eply = at<double>(ws, L.Eply);
+  d.harm_ply = p->harm_ply;
   d.rowply = at<int>(ws, L.rowply); d.rowfin = at<int>(ws, L.rowfin);
   d.Qp = at<double>(ws, L.Qp); d.adj_part = at<double>(ws, L.adj_part);
   d.adj_y = at<double>(ws, L.adj_y); d.adj_dD = at<double>(ws, L.adj_dD);
   d.kron_nsc = p->kron_nsc;
   d.kron_lds_p = p->kron_lds_p;
   d.D = at<double>(ws, L.D); d.Ec = at<double>(ws, L.Ec); d.P = at<double>(ws, L.P);
+  d.Escat = p->harm_ply ? d.Eply : d.Ec;
   d.Qc = at<double>(ws, L.Qc); d.M = at<double>(ws, L.M);
   return d;
 }
@@ -244,6 +248,26 @@ __global__ void k_rotate_plies(Dev d, const double *__restrict__ C, const double
   bracket_coefficients(D, d.Eply + 81 * l);
 }
 
+// Harmonic plans: each ply's tensor is its material's harmonic components
+// D_h (from k_rotate) summed with the ply's weights, D_l = sum_h f_h(theta_l) D_h
+// (Remark on orientations), and its bracket coefficients go to Eply, where the
+// scatter reads them (its sets are the plies).
+__global__ void k_harm_ply(Dev d, const double *__restrict__ theta) {
+  int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= d.n_ply) return;
+  const int s0 = d.ply_set[l];  // the material's first harmonic set
+  double D[6][6];
+  for (int I = 0; I < 6; ++I)
+    for (int J = 0; J < 6; ++J) D[I][J] = 0.0;
+  for (int h = 0; h < d.n_harm; ++h) {
+    const double w = harmonic_weight(d.n_harm, d.set_aux[s0 + h], theta[l]);
+    const double *Dh = d.D + 36 * (s0 + h);
+    for (int I = 0; I < 6; ++I)
+      for (int J = 0; J < 6; ++J) D[I][J] += w * Dh[6 * I + J];
+  }
+  bracket_coefficients(D, d.Eply + 81 * l);
+}
+
 // 1D moments of functions i and j of one in-plane direction over the elements
 // of their common support (range: first element, count), by Gauss quadrature:
 // out = {int N_i N_j, int N_i' N_j, int N_i N_j', int N_i' N_j'} (weights include
@@ -372,7 +396,9 @@ __device__ __forceinline__ void q1d_one(const Dev &d, const double *__restrict__
     for (int ci = d.zcptr[zk]; ci < d.zcptr[zk + 1]; ++ci) {
       const int c = d.zcell[ci], l = d.zply[c];
       double wgt;
-      if (d.set_mode == LAM_SETS_BUCKET) {
+      if (d.harm_ply) {
+        wgt = l == s ? 1.0 : 0.0;  // the scatter's sets are the plies
+      } else if (d.set_mode == LAM_SETS_BUCKET) {
         wgt = d.ply_set[l] == s ? 1.0 : 0.0;
       } else {
         wgt = d.ply_mat[l] == d.set_mat[s] ? harmonic_weight(d.n_harm, d.set_aux[s], theta[l]) : 0.0;
@@ -589,7 +615,7 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron_reg(Dev d, const double *
     const int s0 = d.group_sptr[g], ns = d.group_sptr[g + 1] - s0;
     for (int e = sig; e < 81 * (ns + 1); e += blockDim.x) {
       const int u = e / 81;
-      le[e] = u < ns ? d.Ec[81 * (int64_t)d.group_set[s0 + u] + (e - 81 * u)] : 0.0;
+      le[e] = u < ns ? d.Escat[81 * (int64_t)d.group_set[s0 + u] + (e - 81 * u)] : 0.0;
     }
     for (int e = sig; e < nq; e += blockDim.x) lq[e] = qd[4 * (int64_t)NSC * zk0 + e];
     __syncthreads();
@@ -660,7 +686,7 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron_reg(Dev d, const double *
     const int c0 = d.chunk_sptr[ch], nsc = d.chunk_sptr[ch + 1] - c0;
     for (int e = sig; e < NSC * 81; e += blockDim.x) {
       const int u = e / 81;
-      le[e] = u < nsc ? d.Ec[81 * (int64_t)d.chunk_set[c0 + u] + (e - 81 * u)] : 0.0;
+      le[e] = u < nsc ? d.Escat[81 * (int64_t)d.chunk_set[c0 + u] + (e - 81 * u)] : 0.0;
     }
     for (int e = sig; e < nq; e += blockDim.x) lq[e] = qd[4 * (int64_t)NSC * zk0 + e];
     __syncthreads();
@@ -752,7 +778,7 @@ __global__ void __launch_bounds__(KRON_THREADS) k_apply(Dev d, const double *__r
   double *lc = le + d.kron_lds_p / 8;  // [APPLY_ROWS][3][nth]
   for (int e = sig; e < 81 * (ns + 1); e += nth) {
     const int w = e / 81;
-    le[e] = w < ns ? d.Ec[81 * (int64_t)d.group_set[s0 + w] + (e - 81 * w)] : 0.0;
+    le[e] = w < ns ? d.Escat[81 * (int64_t)d.group_set[s0 + w] + (e - 81 * w)] : 0.0;
   }
   for (int e = sig; e < nq; e += nth) lq[e] = qd[4 * (int64_t)NSC * zk0 + e];
   __syncthreads();
@@ -1265,6 +1291,7 @@ extern "C" LAM_API lam_status lam_assemble(const lam_plan *p, void *ws, int64_t 
   Dev d = make_dev(p, ws);
   int64_t nq = p->nnzz * (p->kron_nsc > 0 ? p->kron_nsc : p->maxact);
   hipLaunchKernelGGL(k_rotate, dim3((p->n_sets + 63) / 64), dim3(64), 0, s, d, C, theta);
+  if (p->harm_ply) hipLaunchKernelGGL(k_harm_ply, dim3((p->n_ply + 63) / 64), dim3(64), 0, s, d, theta);
   if (p->kron_nsc > 0) {
     // register-mode scatter contracts P itself from the moments: one launch
     // for the moments and the 1D coefficients
@@ -1289,6 +1316,7 @@ void launch_prep(const lam_plan *p, const Dev &d, const double *C, const double 
   const int64_t nq = p->nnzz * p->kron_nsc;
   const int nb_m = (int)((p->nnz2 + 255) / 256), nb_q = (int)((nq + 255) / 256);
   hipLaunchKernelGGL(k_rotate, dim3((p->n_sets + 63) / 64), dim3(64), 0, s, d, C, theta);
+  if (p->harm_ply) hipLaunchKernelGGL(k_harm_ply, dim3((p->n_ply + 63) / 64), dim3(64), 0, s, d, theta);
   hipLaunchKernelGGL(k_prep, dim3((unsigned)(nb_m + nb_q)), dim3(256), 0, s, d, theta, nb_m);
 }
 

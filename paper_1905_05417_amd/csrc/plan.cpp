@@ -392,6 +392,21 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
     for (int l = 0; l < d->n_ply; ++l) ply_set[l] = first_set[d->ply_mat[l]];  // first harmonic of its material
   }
   P->n_sets = (int)set_mat.size();
+  // Harmonic sets are evaluated per ply when at most two plies touch any
+  // thickness row (layerwise spaces): the scatter's sets are then the plies,
+  // each ply's tensor the sum of its material's harmonics with the ply's
+  // weights, which keeps two set slots instead of n_harm per material.
+  if (P->set_mode != LAM_SETS_BUCKET) {
+    int most = 0;
+    for (int it = 0; it < P->nt; ++it) {
+      std::vector<int> pl;
+      for (int c = 0; c < P->nzc; ++c)
+        if (it >= zfirst[c] && it <= zfirst[c] + d->q) pl.push_back(zply[c]);
+      std::sort(pl.begin(), pl.end());
+      most = std::max(most, (int)(std::unique(pl.begin(), pl.end()) - pl.begin()));
+    }
+    P->harm_ply = most <= 2 ? 1 : 0;
+  }
   // sets active on each thickness row: those of plies with a cell in the row's support
   std::vector<int> zaptr(P->nt + 1, 0), zaset;
   int maxact = 0;
@@ -402,6 +417,8 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
       int l = zply[c];
       if (P->set_mode == LAM_SETS_BUCKET) {
         act.push_back(ply_set[l]);
+      } else if (P->harm_ply) {
+        act.push_back(l);
       } else {
         for (int h = 0; h < P->n_harm; ++h) act.push_back(ply_set[l] + h);
       }

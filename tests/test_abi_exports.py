@@ -168,8 +168,14 @@ def test_product_cg_rank1_argument_errors():
     assert lib.lam_apply(h, ws, wb - 1, p, p, p, None, n, p, None) == -5
     assert lib.lam_apply(h, ws + 8, wb, p, p, p, None, n, p, None) == -1
     lib.lam_plan_destroy(h)
-    # harmonic plans keep more than two slots per chunk: the product is unsupported
-    h, n, wb = plan("harmonic9")
+    # four set slots per chunk (one set per ply, four plies, a tuning): the product is unsupported
+    d, keep = lamasm._make_desc(W.config_q1_8x8(), "ply")
+    h = ctypes.c_void_p()
+    assert lib.lam_plan_create_tuned(ctypes.byref(d), ctypes.byref(lamasm._make_tuning({"set_slots": 4})),
+                                     ctypes.byref(h)) == 0
+    nr, wbv = ctypes.c_int64(), ctypes.c_int64()
+    assert lib.lam_plan_info(h, ctypes.byref(nr), None, ctypes.byref(wbv), None, None, None) == 0
+    n, wb = nr.value, wbv.value
     raw = np.zeros(wb + 512, dtype=np.uint8)
     ws = raw.ctypes.data + (-raw.ctypes.data) % 256
     buf = np.zeros(n, dtype=np.float64)
