@@ -743,7 +743,8 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron_reg(Dev d, const double *
 // then forms its share c_r = sum_u sum_ab P_u[ab][r] V_u[ab] of
 // y[3 (it n_s + is) + r].  The shares of APPLY_ROWS thickness rows go to LDS
 // behind one barrier and are summed per (row, in-plane row, r) by one thread
-// each; every entry of y belongs to exactly one block, so no atomics.
+// each, in three chains (one per component t) so the LDS reads overlap; every
+// entry of y belongs to exactly one block, so no atomics.
 // fixed (nullable, one byte per row): Dirichlet elimination, y = P K P u +
 // (I - P) u with P the projection on the free rows (fixed entries of u read
 // as 0, fixed rows of y copy u).
@@ -832,10 +833,15 @@ __global__ void __launch_bounds__(KRON_THREADS) k_apply(Dev d, const double *__r
     __syncthreads();
     for (int o = sig; o < 3 * nrow * nb; o += nth) {
       const int j = o / (3 * nrow), rem = o - 3 * nrow * j, i = rem / 3, r = rem - 3 * i, is = is0 + i;
-      const int a0 = 3 * (d.srow[is] - k0), a1 = 3 * (d.srow[is + 1] - k0);
+      const int m0 = d.srow[is] - k0, m1 = d.srow[is + 1] - k0;
       const double *src = lc + (3 * j + r) * nth;
-      double acc = 0.0;
-      for (int a = a0; a < a1; ++a) acc += src[a];
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+      for (int m = m0; m < m1; ++m) {
+        a0 += src[3 * m];
+        a1 += src[3 * m + 1];
+        a2 += src[3 * m + 2];
+      }
+      const double acc = (a0 + a1) + a2;
       const int64_t row = 3 * ((int64_t)(b0 + j) * d.ns + is) + r;
       y[row] = fixed && fixed[row] ? u[row] : acc;
     }
