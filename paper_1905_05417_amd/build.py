@@ -17,6 +17,8 @@ HIPCC_FLAGS = [
     # no packed-FP32 instructions in generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    # a local that hides an outer index (e.g. a row base) is a build error
+    "-Werror=shadow",
 ]
 
 
