@@ -183,9 +183,10 @@ LAM_API lam_status lam_apply(const lam_plan *plan, void *ws, int64_t ws_bytes, c
  * max_iter iterations.  Every product is lam_apply's; vector updates and dot
  * products are kernels of their own with device-side scalars.  work: device,
  * at least lam_cg_work_bytes(plan) bytes, 8-byte aligned.  Unlike the other
- * entry points it waits on the stream after every iteration (to test the
- * residual); *iters and *rel_res (host) receive the iteration count and the
- * final relative residual.  LAM_ESIZE for a short work buffer or a wrong
+ * entry points it waits on the stream, after every 8 iterations (to test the
+ * residual), so up to 7 iterations may run past the tolerance; *iters and
+ * *rel_res (host) receive the iteration count and the final relative
+ * residual.  LAM_ESIZE for a short work buffer or a wrong
  * n_rows; LAM_EUNSUP as for lam_apply. */
 LAM_API int64_t lam_cg_work_bytes(const lam_plan *plan);
 LAM_API lam_status lam_cg(const lam_plan *plan, void *ws, int64_t ws_bytes, const double *C, const double *theta,

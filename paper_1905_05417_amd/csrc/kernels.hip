@@ -1362,6 +1362,9 @@ extern "C" LAM_API lam_status lam_apply(const lam_plan *p, void *ws, int64_t ws_
 // sums (deterministic).  work (doubles): r, p, q = A p (n each), CG_PARTS
 // partial sums, 4 scalars {r.r, p.q, new r.r, P b . P b}.
 constexpr int CG_PARTS = 512;
+// iterations between two host reads of the residual (each read waits for the
+// stream); up to CG_CHECK - 1 iterations may run past the tolerance
+constexpr int CG_CHECK = 8;
 
 __global__ void __launch_bounds__(256) k_dot_partial(const double *__restrict__ a, const double *__restrict__ b,
                                                      const uint8_t *__restrict__ fixed, int64_t n,
@@ -1400,22 +1403,23 @@ __global__ void k_cg_init(int64_t n, const double *__restrict__ b, const double 
   p[i] = v;
 }
 
-// alpha = (r.r) / (p.q); x += alpha p; r -= alpha q
+// alpha = (r.r) / (p.q); x += alpha p; r -= alpha q.  alpha = 0 once p.q is
+// zero (p = 0: an iteration after the exact solution, see CG_CHECK)
 __global__ void k_cg_step(int64_t n, const double *__restrict__ scal, const double *__restrict__ p,
                           const double *__restrict__ q, double *__restrict__ x, double *__restrict__ r) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double alpha = scal[0] / scal[1];
+  const double alpha = scal[1] != 0.0 ? scal[0] / scal[1] : 0.0;
   x[i] += alpha * p[i];
   r[i] -= alpha * q[i];
 }
 
-// beta = (new r.r) / (r.r); p = r + beta p
+// beta = (new r.r) / (r.r); p = r + beta p (beta = 0 once r.r is zero)
 __global__ void k_cg_dir(int64_t n, const double *__restrict__ scal, const double *__restrict__ r,
                          double *__restrict__ p) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  p[i] = r[i] + (scal[2] / scal[0]) * p[i];
+  p[i] = r[i] + (scal[0] != 0.0 ? scal[2] / scal[0] : 0.0) * p[i];
 }
 
 __global__ void k_scalar_copy(double *__restrict__ scal, int to, int from) {
@@ -1463,16 +1467,19 @@ extern "C" LAM_API lam_status lam_cg(const lam_plan *p, void *ws, int64_t ws_byt
   double rr = host[0];
   int it = 0;
   while (it < max_iter && !(bb > 0.0 ? rr <= tol * tol * bb : rr == 0.0)) {
-    launch_apply(p, d, pv, fixed, q, stream);
-    launch_dot(pv, q, nullptr, n, part, scal + 1, s);
-    hipLaunchKernelGGL(k_cg_step, vg, vb, 0, s, n, scal, pv, q, x, r);
-    launch_dot(r, r, nullptr, n, part, scal + 2, s);
-    hipLaunchKernelGGL(k_cg_dir, vg, vb, 0, s, n, scal, r, pv);
-    hipLaunchKernelGGL(k_scalar_copy, dim3(1), dim3(64), 0, s, scal, 0, 2);
+    const int batch = max_iter - it < CG_CHECK ? max_iter - it : CG_CHECK;
+    for (int k = 0; k < batch; ++k) {
+      launch_apply(p, d, pv, fixed, q, stream);
+      launch_dot(pv, q, nullptr, n, part, scal + 1, s);
+      hipLaunchKernelGGL(k_cg_step, vg, vb, 0, s, n, scal, pv, q, x, r);
+      launch_dot(r, r, nullptr, n, part, scal + 2, s);
+      hipLaunchKernelGGL(k_cg_dir, vg, vb, 0, s, n, scal, r, pv);
+      hipLaunchKernelGGL(k_scalar_copy, dim3(1), dim3(64), 0, s, scal, 0, 2);
+    }
     if (hipMemcpyAsync(&rr, scal + 2, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return LAM_EHIP;
-    ++it;
+    it += batch;
   }
   *iters = it;
   *rel_res = bb > 0.0 ? sqrt(rr / bb) : sqrt(rr);
