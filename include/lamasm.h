@@ -68,11 +68,13 @@ typedef int32_t lam_status;
  *  BUCKET:     one set per distinct (material, angle) pair, the grouping read
  *              from desc.ply_theta at plan time (Sec. 3, reuse per distinct
  *              orientation).  The angles passed at assembly must agree within
- *              each set; the set's angle is that of its first ply.
+ *              each set; the set's angle is that of its first ply (a
+ *              disagreement raises LAM_CHECK_BUCKET_ANGLES, see lam_check).
  *  HARMONIC5:  one set per (material, harmonic), harmonics {1, cos 2t,
  *              sin 2t, cos 4t, sin 4t}: exact for any angles when each
  *              material has no coupling between {11,22,33,12} and {13,23}
- *              (orthotropic or monoclinic about the ply plane), Remark 3.
+ *              (orthotropic or monoclinic about the ply plane), Remark 3;
+ *              a coupled material raises LAM_CHECK_HARMONIC5_COUPLING.
  *  HARMONIC9:  harmonics up to order 4 including odd ones: exact for any 6x6.
  *  PLY:        one set per ply: exact for any angles passed at assembly
  *              (no plan-time angles needed).  The scatter forms each set's 2D
@@ -136,6 +138,25 @@ LAM_API lam_status lam_plan_info(const lam_plan *plan, int64_t *n_rows, int64_t 
  * (ws_bytes from lam_plan_info, 256-byte aligned).  Must precede every other
  * device call on that workspace; asynchronous on `stream`. */
 LAM_API lam_status lam_plan_upload(const lam_plan *plan, void *ws, int64_t ws_bytes, void *stream);
+
+/* Reads and clears the workspace's status flags (synchronizes the stream;
+ * not for HIP graph capture).  The fast assembly checks its inputs against
+ * the plan on the device, since C and theta live there, and raises a flag
+ * instead of failing; a flag stays set until this call.  *flags (host)
+ * receives the OR of:
+ *  LAM_CHECK_BUCKET_ANGLES: a BUCKET plan was given a theta in which the
+ *    plies of one set differ; every ply of the set was rotated by the angle
+ *    of the set's first ply, so the values are not K(theta) (Sec. 3: one 2D
+ *    operator per distinct orientation).  Use LAM_SETS_PLY or a harmonic
+ *    mode for angles that change per ply.
+ *  LAM_CHECK_HARMONIC5_COUPLING: a HARMONIC5 plan was given a material with
+ *    an entry coupling {11,22,33,12} with {13,23} above 1e-13 of its largest
+ *    entry; its rotation has odd harmonics that the five terms of the Remark
+ *    on orientations omit.  Use LAM_SETS_HARMONIC9.
+ * Returns LAM_OK (whatever the flags) or a size / HIP error. */
+#define LAM_CHECK_BUCKET_ANGLES 1
+#define LAM_CHECK_HARMONIC5_COUPLING 2
+LAM_API lam_status lam_check(const lam_plan *plan, void *ws, int64_t ws_bytes, int32_t *flags, void *stream);
 
 /* Writes the CSR pattern: rowptr[n_rows+1] (int64) and colind[nnz] (int32). */
 LAM_API lam_status lam_pattern(const lam_plan *plan, const void *ws, int64_t ws_bytes, int64_t *rowptr,

@@ -42,6 +42,7 @@ struct Dev {
   int harm_ply;
   const int *rowply, *rowfin;
   double *Qp, *adj_part, *adj_y, *adj_dD;
+  int *status;  // lam::N_STATUS flags, set by kernels, cleared by lam_check / lam_batch_check
   // scratch
   double *D, *Ec, *P, *Qc, *M;
 };
@@ -52,8 +53,10 @@ inline T *at(void *ws, const Region &r) {
 }
 
 // Device view of a plan whose constant tables live at cbase and whose scratch
-// regions (offsets >= const_bytes) live at sbase (the single-laminate path
-// passes the same workspace for both).
+// regions (offsets >= const_bytes) start at sbase: region r lives at
+// sbase + (r.off - const_bytes).  In one workspace holding both, sbase is
+// ws + const_bytes (make_dev), never ws itself: that would put D at ws and
+// the other scratch regions over the constant tables.
 inline Dev make_dev_split(const lam_plan *p, void *cbase, void *sbase) {
   char *sb = static_cast<char *>(sbase) - p->L.const_bytes;
   Dev d;
@@ -104,13 +107,16 @@ inline Dev make_dev_split(const lam_plan *p, void *cbase, void *sbase) {
   d.adj_y = at<double>(sb, L.adj_y); d.adj_dD = at<double>(sb, L.adj_dD);
   d.kron_nsc = p->kron_nsc;
   d.kron_lds_p = p->kron_lds_p;
+  d.status = at<int>(cbase, L.status);
   d.D = at<double>(sb, L.D); d.Ec = at<double>(sb, L.Ec); d.P = at<double>(sb, L.P);
   d.Escat = d.Ec;
   d.Qc = at<double>(sb, L.Qc); d.M = at<double>(sb, L.M);
   return d;
 }
 
-inline Dev make_dev(const lam_plan *p, void *ws) { return make_dev_split(p, ws, ws); }
+inline Dev make_dev(const lam_plan *p, void *ws) {
+  return make_dev_split(p, ws, static_cast<char *>(ws) + p->L.const_bytes);
+}
 
 // ---------------------------------------------------------------------------
 // Material rotation (eq. D).  With R[i][k] = e_i . a_k (material axes

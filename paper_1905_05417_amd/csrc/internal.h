@@ -12,6 +12,9 @@ namespace lam {
 constexpr int MAXP = 4;      // largest supported degree (in-plane and thickness)
 constexpr int MAXG = 8;      // largest Gauss rule per direction
 constexpr int NHARM_MAX = 9; // harmonics of D(theta) for a general 6x6
+// status words of a workspace: [0] a bucket set's plies were given different
+// angles, [1] a harmonic5 set's material couples {11,22,33,12} with {13,23}
+constexpr int N_STATUS = 2;
 
 // A byte range of the device workspace.
 struct Region {
@@ -50,8 +53,12 @@ struct Layout {
   // each), the distinct sets of each group (group_sptr, group_set) and each
   // chunk slot's index in its group's list (chunk_lset, parallel to chunk_set)
   Region tiles, chunk_ptr, chunk_sptr, chunk_set, zaslot, zchunk, group_ptr, group_sptr, group_set, chunk_lset;
+  // status words, zero after the upload, set (never cleared) by kernels that
+  // find inputs the plan cannot honour; read and cleared by lam_check
+  Region status;
   int64_t const_bytes = 0;  // end of the constant part
-  // scratch: the fast assembly uses [const_bytes, fwd_end); the standard
+  // scratch: the fast assembly uses [const_bytes, fwd_end) (P only in LDS
+  // mode, Eply only for harmonic plans evaluated per ply); the standard
   // assembly and the adjoint use the regions after it
   Region D, Ec, P, Qc, M, Eply, Qp, adj_part, adj_y, adj_dD;
   int64_t fwd_end = 0;

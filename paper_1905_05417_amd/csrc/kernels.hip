@@ -56,6 +56,7 @@ struct Dev {
   int harm_ply;
   const int *rowply, *rowfin;
   double *Qp, *adj_part, *adj_y, *adj_dD;
+  int *status;  // lam::N_STATUS flags, set by kernels, cleared by lam_check
   // scratch
   double *D, *Ec, *P, *Qc, *M;
 };
@@ -114,6 +115,7 @@ Dev make_dev(const lam_plan *p, void *ws) {
   d.adj_y = at<double>(ws, L.adj_y); d.adj_dD = at<double>(ws, L.adj_dD);
   d.kron_nsc = p->kron_nsc;
   d.kron_lds_p = p->kron_lds_p;
+  d.status = at<int>(ws, L.status);
   d.D = at<double>(ws, L.D); d.Ec = at<double>(ws, L.Ec); d.P = at<double>(ws, L.P);
   d.Escat = p->harm_ply ? d.Eply : d.Ec;
   d.Qc = at<double>(ws, L.Qc); d.M = at<double>(ws, L.M);
@@ -208,10 +210,34 @@ __device__ void bracket_coefficients(const double D[6][6], double *E) {
 // degree <= 4 once NH >= 9).
 constexpr int NH = 12;
 
+// Inputs a plan cannot honour raise a status word (plain stores of 1, never
+// cleared here; lam_check reads and clears them):
+//  - bucket sets: a ply given another angle than its set's first ply (the set
+//    is rotated by that one angle, so K would not be K(theta));
+//  - harmonic5 sets: a material with a nonzero {11,22,33,12}-{13,23} entry
+//    (relative to its largest entry, above 1e-13), whose rotation has odd
+//    harmonics that five terms do not hold (Remark on orientations).
+__device__ __forceinline__ void check_set(const Dev &d, const double *__restrict__ Cm,
+                                          const double *__restrict__ theta, int s) {
+  if (d.set_mode == LAM_SETS_BUCKET) {
+    const double th = theta[d.set_aux[s]];
+    bool bad = false;
+    for (int l = 0; l < d.n_ply; ++l) bad |= d.ply_set[l] == s && !(theta[l] == th);
+    if (bad) d.status[0] = 1;
+  } else if (d.n_harm == 5 && d.set_aux[s] == 0) {
+    double big = 0.0, cpl = 0.0;
+    for (int e = 0; e < 36; ++e) big = fmax(big, fabs(Cm[e]));
+    for (int I = 0; I < 4; ++I)
+      for (int J = 4; J < 6; ++J) cpl = fmax(cpl, fmax(fabs(Cm[6 * I + J]), fabs(Cm[6 * J + I])));
+    if (!(cpl <= 1e-13 * big)) d.status[1] = 1;
+  }
+}
+
 __device__ __forceinline__ void rotate_one(const Dev &d, const double *__restrict__ C, const double *__restrict__ theta,
                                            int s) {
   if (s >= d.n_sets) return;
   const double *Cm = C + 36 * d.set_mat[s];
+  check_set(d, Cm, theta, s);
   double D[6][6];
   if (d.set_mode == LAM_SETS_BUCKET) {
     double th = theta[d.set_aux[s]];
@@ -1272,6 +1298,22 @@ extern "C" LAM_API lam_status lam_plan_upload(const lam_plan *p, void *ws, int64
   hipError_t e = hipMemcpyAsync(ws, p->image.data(), p->L.const_bytes, hipMemcpyHostToDevice,
                                 static_cast<hipStream_t>(stream));
   return e == hipSuccess ? LAM_OK : LAM_EHIP;
+}
+
+extern "C" LAM_API lam_status lam_check(const lam_plan *p, void *ws, int64_t ws_bytes, int32_t *flags, void *stream) {
+  lam_status st = check_ws(p, ws, ws_bytes);
+  if (st != LAM_OK) return st;
+  if (!flags) return LAM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int32_t *dev = at<int32_t>(ws, p->L.status);
+  int32_t host[lam::N_STATUS];
+  static const int32_t zeros[lam::N_STATUS] = {};
+  if (hipMemcpyAsync(host, dev, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(dev, zeros, sizeof(zeros), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return LAM_EHIP;
+  *flags = (host[0] ? LAM_CHECK_BUCKET_ANGLES : 0) | (host[1] ? LAM_CHECK_HARMONIC5_COUPLING : 0);
+  return LAM_OK;
 }
 
 extern "C" LAM_API lam_status lam_pattern(const lam_plan *p, const void *ws, int64_t ws_bytes, int64_t *rowptr,

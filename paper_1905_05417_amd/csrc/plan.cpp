@@ -743,14 +743,17 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
   L.chunk_sptr = B.take(sizeof(int) * chunk_sptr.size());
   L.chunk_set = B.take(sizeof(int) * chunk_set.size());
   L.zaslot = B.take(sizeof(int) * zaslot.size());
+  L.status = B.take(sizeof(int) * lam::N_STATUS);
   L.const_bytes = B.cur;
   L.D = B.take(sizeof(double) * 36 * P->n_sets);
   L.Ec = B.take(sizeof(double) * 81 * P->n_sets);
-  L.P = B.take(sizeof(double) * 36 * (int64_t)P->n_sets * P->nnz2);
+  // P of every set is stored only by the LDS-mode scatter; the register mode
+  // contracts it from the moments M
+  L.P = B.take(P->kron_nsc > 0 ? 0 : sizeof(double) * 36 * (int64_t)P->n_sets * P->nnz2);
   L.Qc = B.take(sizeof(double) * 4 * (int64_t)std::max(P->maxact, P->kron_nsc) * P->nnzz);
   L.M = B.take(sizeof(double) * 36 * P->nnz2);
-  L.fwd_end = B.cur;  // scratch of the fast assembly ends here
   L.Eply = B.take(sizeof(double) * 81 * P->n_ply);
+  L.fwd_end = B.cur;  // scratch of the fast assembly ends here
   // adjoint scratch: per-ply 1D operators by slot (padded per thickness row), per (ply, tile) partial sums,
   // per-ply totals and dL/dD_l
   L.Qp = B.take(sizeof(double) * 8 * std::max<int64_t>(P->nnzz, (int64_t)P->nt * (2 * P->q + 1)));

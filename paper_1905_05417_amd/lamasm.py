@@ -60,7 +60,8 @@ def _make_tuning(t):
 
 _lib = None
 
-EXPORTED = ("lam_plan_create", "lam_plan_create_tuned", "lam_plan_destroy", "lam_plan_info", "lam_plan_upload", "lam_pattern",
+EXPORTED = ("lam_plan_create", "lam_plan_create_tuned", "lam_plan_destroy", "lam_plan_info", "lam_plan_upload", "lam_check",
+            "lam_pattern",
             "lam_assemble", "lam_assemble_standard", "lam_apply", "lam_cg", "lam_cg_work_bytes", "lam_adjoint", "lam_adjoint_rank1",
             "lam_batch_create", "lam_batch_create_tuned", "lam_batch_destroy", "lam_batch_info", "lam_batch_laminate", "lam_batch_upload",
             "lam_batch_pattern", "lam_batch_assemble", "lam_batch_check",
@@ -83,6 +84,7 @@ def lib():
         L.lam_plan_destroy.restype = None
         L.lam_plan_info.argtypes = [vp, i64p, i64p, i64p, _i32p, _i32p, _i32p]
         L.lam_plan_upload.argtypes = [vp, vp, i64, vp]
+        L.lam_check.argtypes = [vp, vp, i64, _i32p, vp]
         L.lam_pattern.argtypes = [vp, vp, i64, vp, vp, vp]
         L.lam_assemble.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
         L.lam_assemble_standard.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
@@ -126,10 +128,18 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+CHECK_FLAGS = {1: "the plies of a bucket set were given different angles (each set is rotated by its first "
+                  "ply's angle, so the values are not K(theta)); use set_mode 'ply' or a harmonic mode",
+               2: "a harmonic5 plan was given a material that couples {11,22,33,12} with {13,23} (odd angular "
+                  "harmonics are omitted, so the values are not K(theta)); use set_mode 'harmonic9'"}
+
+
 def default_set_mode(lam) -> str:
-    """Bucket sets (one per distinct (material, angle) pair of the plan-time
-    angles); the scatter's cost does not grow with the number of sets."""
-    return "bucket"
+    """One set per ply: exact for any angles passed at assembly (nothing is
+    fixed at plan time), and the scatter's cost hardly grows with the number
+    of sets.  Bucket sets ('bucket', one per distinct plan-time (material,
+    angle) pair) serve fixed layups."""
+    return "ply"
 
 
 def _make_desc(lam, set_mode):
@@ -202,6 +212,16 @@ class Plan:
         if C.numel() != 36 * self.n_mat or theta.numel() != self.n_ply:
             raise ValueError("C must hold n_mat*36 values and theta n_ply values")
         return C, theta
+
+    def check(self):
+        """Reads and clears the workspace's status flags (lam_check; waits for
+        the stream) and raises if an assembly since the last check was given
+        inputs the plan's sets cannot honour."""
+        ws = self._ws()
+        f = ctypes.c_int32()
+        _check(lib().lam_check(self._h, ws.data_ptr(), self.ws_bytes, ctypes.byref(f), _stream()), "lam_check")
+        if f.value:
+            raise ValueError("lam_check: " + "; ".join(m for b, m in CHECK_FLAGS.items() if f.value & b))
 
     def pattern(self):
         ws = self._ws()
@@ -402,9 +422,15 @@ class BatchPlan:
 class _Assemble(torch.autograd.Function):
     @staticmethod
     def forward(ctx, C, theta, plan):
+        if plan.set_mode == "bucket":
+            raise ValueError("assemble(): a bucket plan groups plies by their plan-time angles, so it cannot follow "
+                             "per-ply angle changes; differentiate through a 'ply' or harmonic plan")
         ctx.plan = plan
         ctx.save_for_backward(C, theta)
-        return plan.assemble(C.detach(), theta.detach())
+        vals = plan.assemble(C.detach(), theta.detach())
+        if plan.set_mode == "harmonic5":
+            plan.check()  # the five-term split needs materials without {11,22,33,12}-{13,23} coupling
+        return vals
 
     @staticmethod
     def backward(ctx, grad_vals):
@@ -414,5 +440,9 @@ class _Assemble(torch.autograd.Function):
 
 
 def assemble(plan: Plan, C: torch.Tensor, theta: torch.Tensor) -> torch.Tensor:
-    """CSR values of K(C, theta); differentiable in C (n_mat,6,6) and theta (n_ply,)."""
+    """CSR values of K(C, theta); differentiable in C (n_mat,6,6) and theta (n_ply,).
+
+    The backward is lam_adjoint.  Bucket plans are refused (their sets fix the
+    ply angles' grouping at plan time); harmonic5 plans are checked on the
+    device for materials the five-term split cannot represent."""
     return _Assemble.apply(C, theta, plan)
