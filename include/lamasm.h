@@ -63,6 +63,7 @@ typedef int32_t lam_status;
 #define LAM_ESIZE (-5)   /* workspace or output length does not match the plan */
 #define LAM_EHIP (-6)    /* HIP runtime error (launch or an earlier asynchronous fault) */
 #define LAM_EUNSUP (-7)  /* supported by the method but not by this build (limits below) */
+#define LAM_ESCRATCH (-8) /* the plan needs more scratch than lam_assemble_static's static buffer */
 
 /* How plies are grouped into the sets that share one 2D operator P.
  *  BUCKET:     one set per distinct (material, angle) pair, the grouping read
@@ -167,6 +168,26 @@ LAM_API lam_status lam_pattern(const lam_plan *plan, const void *ws, int64_t ws_
  * Every value of vals is overwritten. */
 LAM_API lam_status lam_assemble(const lam_plan *plan, void *ws, int64_t ws_bytes, const double *C,
                                 const double *theta, double *vals, int64_t nnz, void *stream);
+
+/* lam_assemble for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same values, bit for bit, but the assembly's
+ * scratch (set tensors, bracket coefficients, in-plane moments, thickness
+ * coefficients: bytes [const part, fast-scratch end) of the workspace layout)
+ * lives in a static device array of LAM_STATIC_SCRATCH_MIB MiB that the
+ * library holds on every GPU it runs on until the process ends.  ws needs only
+ * the plan's constant tables: any ws_bytes from the constant part's size up
+ * (lam_plan_info's ws_bytes always suffices; lam_plan_upload fills it) and
+ * nothing in it is written except the status words of lam_check.  Calls that
+ * allocate nothing: no hipMalloc, no hipFree, no allocating library routine.
+ * Every call on one GPU shares that GPU's static array, so calls that overlap
+ * on one GPU (concurrent streams, threads) race and must be serialized by the
+ * caller.  LAM_ESCRATCH if the plan's scratch exceeds the array (about
+ * 288 B per in-plane nonzero: up to ~460,000 in-plane nonzeros, e.g. degree 2
+ * on 128x128 elements), LAM_EHIP if the array's address cannot be obtained. */
+#define LAM_STATIC_SCRATCH_MIB 128
+LAM_API lam_status lam_assemble_static(const lam_plan *plan, void *ws, int64_t ws_bytes, const double *C,
+                                       const double *theta, double *vals, int64_t nnz, void *stream);
 
 /* Standard 3D assembly (Sec. 2.4): element by element over every
  * (in-plane element x ply x thickness knot span) cell with the tensor Gauss

@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <mutex>
 
 #include "internal.h"
 
@@ -66,7 +67,14 @@ T *at(void *ws, const Region &r) {
   return reinterpret_cast<T *>(static_cast<char *>(ws) + r.off);
 }
 
-Dev make_dev(const lam_plan *p, void *ws) {
+// Device view of a plan: constant tables (and status words) in the caller's
+// workspace ws; the fast assembly's scratch regions [const_bytes, fwd_end) at
+// sbase + (offset - const_bytes), by default right after the tables in ws.
+// With an outside sbase (the static scratch of lam_assemble_static) the
+// regions of the standard assembly and the adjoint are left null.
+Dev make_dev(const lam_plan *p, void *ws, void *sbase = nullptr) {
+  const bool own = sbase == nullptr;
+  char *sb = (own ? static_cast<char *>(ws) + p->L.const_bytes : static_cast<char *>(sbase)) - p->L.const_bytes;
   Dev d;
   d.p1 = p->p1; d.p2 = p->p2; d.q = p->q;
   d.n1 = p->n1; d.n2 = p->n2; d.nt = p->nt; d.ns = p->ns;
@@ -108,17 +116,19 @@ Dev make_dev(const lam_plan *p, void *ws) {
   d.a2f = at<int>(ws, L.a2f); d.a2c = at<int>(ws, L.a2c);
   d.zs_first = at<int>(ws, L.zs_first); d.zs_cptr = at<int>(ws, L.zs_cptr); d.zs_cell = at<int>(ws, L.zs_cell);
   d.ne1 = p->ne1; d.ne2 = p->ne2; d.nzs = p->nzs;
-  d.Eply = at<double>(ws, L.Eply);
+  d.Eply = at<double>(sb, L.Eply);
   d.harm_ply = p->harm_ply;
   d.rowply = at<int>(ws, L.rowply); d.rowfin = at<int>(ws, L.rowfin);
-  d.Qp = at<double>(ws, L.Qp); d.adj_part = at<double>(ws, L.adj_part);
-  d.adj_y = at<double>(ws, L.adj_y); d.adj_dD = at<double>(ws, L.adj_dD);
+  d.Qp = own ? at<double>(sb, L.Qp) : nullptr;
+  d.adj_part = own ? at<double>(sb, L.adj_part) : nullptr;
+  d.adj_y = own ? at<double>(sb, L.adj_y) : nullptr;
+  d.adj_dD = own ? at<double>(sb, L.adj_dD) : nullptr;
   d.kron_nsc = p->kron_nsc;
   d.kron_lds_p = p->kron_lds_p;
   d.status = at<int>(ws, L.status);
-  d.D = at<double>(ws, L.D); d.Ec = at<double>(ws, L.Ec); d.P = at<double>(ws, L.P);
+  d.D = at<double>(sb, L.D); d.Ec = at<double>(sb, L.Ec); d.P = at<double>(sb, L.P);
   d.Escat = p->harm_ply ? d.Eply : d.Ec;
-  d.Qc = at<double>(ws, L.Qc); d.M = at<double>(ws, L.M);
+  d.Qc = at<double>(sb, L.Qc); d.M = at<double>(sb, L.M);
   return d;
 }
 
@@ -1329,14 +1339,12 @@ extern "C" LAM_API lam_status lam_pattern(const lam_plan *p, const void *ws, int
   return hip_status();
 }
 
-extern "C" LAM_API lam_status lam_assemble(const lam_plan *p, void *ws, int64_t ws_bytes, const double *C,
-                                           const double *theta, double *vals, int64_t nnz, void *stream) {
-  lam_status st = check_ws(p, ws, ws_bytes);
-  if (st != LAM_OK) return st;
-  if (!C || !theta || !vals) return LAM_EINVAL;
-  if (nnz != p->nnz) return LAM_ESIZE;
+namespace {
+
+// The launches of the fast assembly (Sec. 3) on the device view d.
+void launch_assemble(const lam_plan *p, const Dev &d, const double *C, const double *theta, double *vals,
+                     void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
-  Dev d = make_dev(p, ws);
   int64_t nq = p->nnzz * (p->kron_nsc > 0 ? p->kron_nsc : p->maxact);
   hipLaunchKernelGGL(k_rotate, dim3((p->n_sets + 63) / 64), dim3(64), 0, s, d, C, theta);
   if (p->harm_ply) hipLaunchKernelGGL(k_harm_ply, dim3((p->n_ply + 63) / 64), dim3(64), 0, s, d, theta);
@@ -1353,6 +1361,57 @@ extern "C" LAM_API lam_status lam_assemble(const lam_plan *p, void *ws, int64_t 
   void *prof = lam::profile_begin(0, stream);
   launch_kron(p, d, vals, s);
   lam::profile_end(prof, stream);
+}
+
+}  // namespace
+
+// Static scratch of lam_assemble_static: one copy per GPU for the life of the
+// process, shared by every call on that GPU.  Host code never uses the
+// array's name as an address: each device's copy is looked up once with
+// hipGetSymbolAddress (with that device current) and kept in scratch_dev.
+constexpr int64_t STATIC_SCRATCH_BYTES = int64_t(LAM_STATIC_SCRATCH_MIB) << 20;
+static __device__ __align__(256) double scratch[STATIC_SCRATCH_BYTES / 8];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+void *scratch_dev[MAX_DEVICES];
+std::mutex scratch_mu;
+
+// The calling thread's current device's copy of scratch, or null on a HIP error.
+void *static_scratch() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    scratch_dev[dev] = ptr;
+  }
+  return scratch_dev[dev];
+}
+
+}  // namespace
+
+extern "C" LAM_API lam_status lam_assemble(const lam_plan *p, void *ws, int64_t ws_bytes, const double *C,
+                                           const double *theta, double *vals, int64_t nnz, void *stream) {
+  lam_status st = check_ws(p, ws, ws_bytes);
+  if (st != LAM_OK) return st;
+  if (!C || !theta || !vals) return LAM_EINVAL;
+  if (nnz != p->nnz) return LAM_ESIZE;
+  launch_assemble(p, make_dev(p, ws), C, theta, vals, stream);
+  return hip_status();
+}
+
+extern "C" LAM_API lam_status lam_assemble_static(const lam_plan *p, void *ws, int64_t ws_bytes, const double *C,
+                                                  const double *theta, double *vals, int64_t nnz, void *stream) {
+  if (!p || !ws || !C || !theta || !vals) return LAM_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return LAM_EINVAL;
+  if (ws_bytes < p->L.const_bytes || nnz != p->nnz) return LAM_ESIZE;
+  if (p->L.fwd_end - p->L.const_bytes > STATIC_SCRATCH_BYTES) return LAM_ESCRATCH;
+  void *sbase = static_scratch();
+  if (!sbase) return LAM_EHIP;
+  launch_assemble(p, make_dev(p, ws, sbase), C, theta, vals, stream);
   return hip_status();
 }
 

@@ -873,6 +873,7 @@ extern "C" LAM_API const char *lam_status_string(lam_status s) {
     case LAM_ESIZE: return "workspace or output size does not match the plan";
     case LAM_EHIP: return "HIP runtime error";
     case LAM_EUNSUP: return "outside the limits of this build";
+    case LAM_ESCRATCH: return "the plan's scratch exceeds the static scratch of lam_assemble_static";
     default: return "unknown status";
   }
 }

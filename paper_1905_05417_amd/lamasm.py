@@ -62,7 +62,7 @@ _lib = None
 
 EXPORTED = ("lam_plan_create", "lam_plan_create_tuned", "lam_plan_destroy", "lam_plan_info", "lam_plan_upload", "lam_check",
             "lam_pattern",
-            "lam_assemble", "lam_assemble_standard", "lam_apply", "lam_cg", "lam_cg_work_bytes", "lam_adjoint", "lam_adjoint_rank1",
+            "lam_assemble", "lam_assemble_static", "lam_assemble_standard", "lam_apply", "lam_cg", "lam_cg_work_bytes", "lam_adjoint", "lam_adjoint_rank1",
             "lam_batch_create", "lam_batch_create_tuned", "lam_batch_destroy", "lam_batch_info", "lam_batch_laminate", "lam_batch_upload",
             "lam_batch_pattern", "lam_batch_assemble", "lam_batch_check",
             "lam_profile_enable", "lam_profile_read", "lam_status_string", "lam_version")
@@ -87,6 +87,7 @@ def lib():
         L.lam_check.argtypes = [vp, vp, i64, _i32p, vp]
         L.lam_pattern.argtypes = [vp, vp, i64, vp, vp, vp]
         L.lam_assemble.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
+        L.lam_assemble_static.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
         L.lam_assemble_standard.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
         L.lam_adjoint.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
         L.lam_adjoint_rank1.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
@@ -238,6 +239,18 @@ class Plan:
         _check(lib().lam_assemble(self._h, ws.data_ptr(), self.ws_bytes, C.data_ptr(), theta.data_ptr(),
                                   vals.data_ptr(), vals.numel(), _stream()), "lam_assemble")
         return vals
+
+    def assemble_static(self, C, theta, out, ws=None):
+        """lam_assemble_static: the fast assembly with its scratch in the
+        library's static device array (no device allocation in the call; the
+        output must be given).  ws: a workspace holding this plan's uploaded
+        tables (default: the plan's own)."""
+        ws = self._ws() if ws is None else ws
+        C, theta = self._inputs(C, theta)
+        _check(lib().lam_assemble_static(self._h, ws.data_ptr(), ws.numel() * ws.element_size(), C.data_ptr(),
+                                         theta.data_ptr(), out.data_ptr(), out.numel(), _stream()),
+               "lam_assemble_static")
+        return out
 
     def assemble_standard(self, C, theta, out=None):
         ws = self._ws()
