@@ -1,19 +1,25 @@
 #!/usr/bin/env python
 """Benchmark of the fast 2D x 1D laminate stiffness assembly on one MI355X.
 
-One step = one lam_assemble call (material rotation, 2D operators P, 1D
-operators Q, Kronecker scatter into the CSR values) on the degree-2 IGA plate:
-64x64 in-plane elements, 32 plies [0/90]_16, degree 2 per ply (C0 at
-interfaces), thickness 0.02, 3x3x3 Gauss: 849,420 DOF, 242,809,488 nonzeros.
-Inputs (plan tables, C, theta) are resident in HBM before timing starts.
+One step = one lam_assemble call (material rotation, in-plane moments, folded
+thickness coefficients, Kronecker scatter into the CSR values) on the largest
+plate that fits one GPU: degree-3 C2 B-splines on 128x128 in-plane elements,
+128 plies [0/45/-45/90]_32 of carbon and glass alternating every 16 plies,
+degree 2 per ply (C0 at interfaces), thickness 0.02, 4x4x3 Gauss:
+13,231,131 DOF, 7,555,505,625 nonzeros (60.4 GB of FP64 values).  Inputs
+(plan tables, C, theta) are resident in HBM before timing starts; the steps
+cycle through three output allocations.
 
 Prints ONE JSON line.  `value` is assembled CSR nonzeros per second (FP64).
 `roofline` is for the dominant kernel (the Kronecker scatter), timed with HIP
 events recorded around its own launch on the assembly stream; its algorithmic
-traffic is the 8-byte write of every nonzero.  `cpu_baseline` times the CPU
-oracle (standard 3D Gauss assembly, layer by layer) on a slab of the same plate.
-`extra` carries the standard 3D GPU assembly on the same CSR and the other
-plate workloads when their entry points are built.
+traffic is the 8-byte write of every nonzero.  `roofline.achievable` holds the
+write, read and copy rates plain torch kernels reach on the same output
+buffers.  `cpu_baseline` times the CPU oracle (standard 3D Gauss assembly,
+layer by layer) on labelled slabs of the same plate, on all host threads and
+on one.  `extra` carries the standard 3D GPU assembly of the same plate and
+the other workloads (the 32-ply degree-2 plate with its matrix-free product
+and CG, the 64-ply adjoint plate, the 256-laminate batch).
 """
 from __future__ import annotations
 
@@ -169,12 +175,13 @@ def _adjoint_workload(torch, np, L, W, O, steps, warmup):
     torch.cuda.empty_cache()
     out = {}
     ms, ms_k = _time_steps(torch, lambda: out.update(g=plan.adjoint(C, th, G)), steps, warmup, L, "adjoint")
+    ms_med = _time_steps_median(torch, lambda: out.update(g=plan.adjoint(C, th, G)), max(steps, 9))
     gC, gT = out["g"]
     dD = O.grad_D_uu(lam, u.cpu().numpy())
     gC_ref, gT_ref = O.grad_material(lam, dD)
     err = max(float(np.abs(gC.cpu().numpy() - gC_ref).max() / np.abs(gC_ref).max()),
               float(np.abs(gT.cpu().numpy() - gT_ref).max() / np.abs(gT_ref).max()))
-    res.update({"nnz": plan.nnz, "adjoint_ms": ms, "adjoint_stream_kernel_ms": ms_k,
+    res.update({"nnz": plan.nnz, "adjoint_ms": ms, "adjoint_ms_median": ms_med, "adjoint_stream_kernel_ms": ms_k,
                 "adjoint_grad_read_GBps": 8.0 * plan.nnz / (ms_k * 1e-3) / 1e9,
                 "adjoint_hbm_frac": 8.0 * plan.nnz / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 "adjoint_rel_err_vs_oracle": err})
@@ -182,10 +189,11 @@ def _adjoint_workload(torch, np, L, W, O, steps, warmup):
     torch.cuda.empty_cache()
     # the same gradient with G = u u^T formed from u inside the stream (no G in memory)
     ms1, ms1_k = _time_steps(torch, lambda: out.update(g=plan.adjoint_rank1(C, th, u)), steps, warmup, L, "adjoint")
+    ms1_med = _time_steps_median(torch, lambda: out.update(g=plan.adjoint_rank1(C, th, u)), max(steps, 9))
     gC1, gT1 = out["g"]
     err1 = max(float(np.abs(gC1.cpu().numpy() - gC_ref).max() / np.abs(gC_ref).max()),
                float(np.abs(gT1.cpu().numpy() - gT_ref).max() / np.abs(gT_ref).max()))
-    res.update({"adjoint_rank1_ms": ms1, "adjoint_rank1_stream_kernel_ms": ms1_k,
+    res.update({"adjoint_rank1_ms": ms1, "adjoint_rank1_ms_median": ms1_med, "adjoint_rank1_stream_kernel_ms": ms1_k,
                 "adjoint_rank1_rel_err_vs_oracle": err1})
     del u, plan, rowptr
     torch.cuda.empty_cache()
@@ -193,7 +201,7 @@ def _adjoint_workload(torch, np, L, W, O, steps, warmup):
 
 
 def _apply_workload(torch, np, L, lam, plan, C, th, vals, rowptr, colind, steps, warmup):
-    """y = K u on the headline plate: matrix-free (lam_apply, K never formed)
+    """y = K u on the 32-ply degree-2 plate: matrix-free (lam_apply, K never formed)
     against multiplying the assembled K (torch's CSR matrix-vector product of
     the values lam_assemble wrote), and against assembling K and then multiplying."""
     u = torch.tensor(np.random.default_rng(11).standard_normal(plan.n_rows), device="cuda")
@@ -318,20 +326,143 @@ def _paper_sweep(torch, np, L, W, O, degrees, meshes, plies, layups, reps):
     return rows
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _c3_slab(W, ne1, ne2):
+    """A slab of the headline plate: ne1 x ne2 in-plane elements of the same
+    degree, every one of the 128 plies, the same materials, layup and Gauss
+    rules (the in-plane element size grows; the oracle's work per nonzero does not)."""
+    angles = [0, 45, -45, 90] * 32
+    ply_mat = [(l // 16) % 2 for l in range(128)]
+    lam = W.plate(3, ne1, 2, angles, [W.material(W.CARBON), W.material(W.GLASS)], ply_mat, ne2=ne2,
+                  name="p3_slab_%dx%d_128ply" % (ne1, ne2))
+    lam.ng = (4, 4, 3)
+    return lam
+
+
 def _cpu_baseline(oracle, W):
-    """Oracle on a slab of the headline plate: 16 x 64 in-plane elements, all
-    32 plies, same degrees and Gauss rules."""
+    """The oracle, untuned, on the host: all threads on a 4 x 48-element slab
+    of the headline plate (all 128 plies), one thread on a 1 x 24-element slab
+    (about 10 s each on a 16-thread EPYC host)."""
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
-    lam = W.plate(2, 16, 2, [0, 90] * 16, [W.material(W.CARBON)], [0] * 32, ne2=64, name="slab")
-    lam.ng = (3, 3, 3)
-    pat = oracle.pattern(lam)
-    t0 = time.perf_counter()
-    oracle.assemble(lam, nthreads=threads, pattern_=pat)
-    dt = time.perf_counter() - t0
-    nnz = len(pat[1])
-    return {"value": nnz / dt, "unit": "nnz/s", "cores": threads, "kind": "oracle",
-            "sample": "standard 3D assembly of a 16x64-element slab of the same plate (all 32 plies, "
-                      "%d nnz) in %.2f s; full plate projected at %.0f s" % (nnz, dt, dt * 4.0)}
+    out = {"unit": "nnz/s", "kind": "oracle", "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+           "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+    for key, (ne1, ne2, th) in (("all_threads", (4, 48, threads)), ("single_thread", (1, 24, 1))):
+        lam = _c3_slab(W, ne1, ne2)
+        pat = oracle.pattern(lam)
+        t0 = time.perf_counter()
+        oracle.assemble(lam, nthreads=th, pattern_=pat)
+        dt = time.perf_counter() - t0
+        nnz = len(pat[1])
+        out[key] = {"value": nnz / dt, "threads": th, "nnz": nnz, "seconds": round(dt, 2),
+                    "sample": "standard 3D assembly of a %dx%d-element slab of the 128x128 128-ply degree-3 plate "
+                              "(all plies, same degrees and Gauss rules)" % (ne1, ne2)}
+        print("cpu baseline %s: %.3e nnz/s in %.1f s" % (key, nnz / dt, dt), file=sys.stderr, flush=True)
+    out["value"] = out["all_threads"]["value"]
+    out["cores"] = out["all_threads"]["threads"]
+    out["sample"] = out["all_threads"]["sample"] + " on %d threads; single thread: %.3e nnz/s on a 1x24 slab" % (
+        out["cores"], out["single_thread"]["value"])
+    return out
+
+
+def _ceilings(torch, bufs, reps=6):
+    """Achievable HBM rates of plain torch kernels on the headline's own output
+    allocations (same sizes, same physical placement): write = fill_ of each
+    buffer in turn, read = sum of one buffer, copy = one buffer into another
+    (its read and write bytes both counted)."""
+    nbytes = 8 * bufs[0].numel()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, n):
+        fn(0)
+        torch.cuda.synchronize()
+        e0.record()
+        for i in range(n):
+            fn(i)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    ms_w = timed(lambda i: bufs[i % len(bufs)].fill_(0.0), reps)
+    sink = torch.empty((), dtype=torch.float64, device=bufs[0].device)
+    ms_r = timed(lambda i: torch.sum(bufs[i % len(bufs)], dim=0, out=sink), reps)
+    ms_c = timed(lambda i: bufs[(i + 1) % len(bufs)].copy_(bufs[i % len(bufs)]), reps)
+    small = bufs[0][: (1 << 28)]  # 2 GiB view
+    ms_ws = timed(lambda i: small.fill_(0.0), 20)
+    return {"write_fill_GBps": round(nbytes / (ms_w * 1e-3) / 1e9, 1),
+            "read_sum_GBps": round(nbytes / (ms_r * 1e-3) / 1e9, 1),
+            "copy_read_plus_write_GBps": round(2 * nbytes / (ms_c * 1e-3) / 1e9, 1),
+            "write_fill_2GiB_GBps": round(8 * small.numel() / (ms_ws * 1e-3) / 1e9, 1),
+            "bytes_per_buffer": nbytes, "buffers": len(bufs),
+            "how": "torch fill_/sum/copy_ on the headline's output allocations, HIP events, %d reps" % reps}
+
+
+def _time_steps_median(torch, fn, steps):
+    """Per-step HIP-event times (ms) of `steps` more calls, for the median."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    t = sorted(a.elapsed_time(b) for a, b in ev)
+    return t[len(t) // 2] if len(t) % 2 else 0.5 * (t[len(t) // 2 - 1] + t[len(t) // 2])
+
+
+def _c2_workload(torch, np, L, W, O, args):
+    """The 32-ply degree-2 plate: fast step with its scatter fraction, the
+    standard comparator, the matrix-free product and CG."""
+    from paper_1905_05417_amd import autotune
+    lam = W.config_p2_64x64_32ply()
+    tuning = autotune.lookup(lam, "bucket")
+    plan = L.Plan(lam, set_mode="bucket", tuning=tuning)
+    rowptr, colind = plan.pattern()
+    C = torch.tensor(np.asarray(lam.C), device="cuda")
+    th = torch.tensor(np.asarray(lam.theta), device="cuda")
+    bufs = [torch.empty(plan.nnz, dtype=torch.float64, device="cuda") for _ in range(OUT_BUFFERS)]
+    n_done = [0]
+
+    def step():
+        plan.assemble(C, th, out=bufs[n_done[0] % OUT_BUFFERS])
+        n_done[0] += 1
+
+    ms, ms_k = _time_steps(torch, step, args.steps, args.warmup, L, "assemble")
+    vals = bufs[(n_done[0] - 1) % OUT_BUFFERS]
+    res = {"workload": lam.name, "nnz": plan.nnz, "sets": plan.n_sets, "set_mode": "bucket",
+           "scatter_tuning": tuning or "automatic", "ms_per_step": ms, "nnz_per_s": plan.nnz / (ms * 1e-3),
+           "k_kron_ms": ms_k, "k_kron_GBps": 8.0 * plan.nnz / (ms_k * 1e-3) / 1e9,
+           "k_kron_hbm_frac": 8.0 * plan.nnz / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "traffic": _traffic(lam.name, "k_kron"),
+           "parity_sample_relF": _sample_parity(O, lam, plan, vals, rowptr)}
+    plan.check()
+    del bufs[:]
+    torch.cuda.empty_cache()
+    res["matrix_free_apply"] = _apply_workload(torch, np, L, lam, plan, C, th, vals, rowptr, colind,
+                                               max(10, args.steps), args.warmup)
+    try:
+        ms_std, ms_std_k = _time_steps(torch, lambda: plan.assemble_standard(C, th, out=vals),
+                                       max(3, args.steps // 4), 1, L, "standard")
+        flops = STD_FLOPS_PER_NNZ_P2Q2 * plan.nnz
+        res["standard"] = {"nnz_per_s": plan.nnz / (ms_std * 1e-3), "ms_per_step": ms_std,
+                           "speedup_fast_vs_standard": ms_std / ms, "element_kernel_ms": ms_std_k,
+                           "fp64_tflops_algorithmic": flops / (ms_std * 1e-3) / 1e12,
+                           "fp64_frac": flops / (ms_std * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
+    except L.LamError as e:
+        res["standard"] = {"skipped": str(e)}
+    del vals, rowptr, colind, plan
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -353,19 +484,21 @@ def main():
 
     from paper_1905_05417_amd import autotune
     tuning_cache = autotune.load_cache()
-    lam = W.config_p2_64x64_32ply()
+    lam = W.config_p3_128x128_128ply()
     tuning = autotune.lookup(lam, "bucket", tuning_cache)
     t0 = time.perf_counter()
     plan = L.Plan(lam, set_mode="bucket", tuning=tuning)
     rowptr, colind = plan.pattern()
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    del colind  # 30 GB; the pattern's equality with the oracle's is tested on smaller plates
+    torch.cuda.empty_cache()
     C = torch.tensor(np.asarray(lam.C), device="cuda")
     th = torch.tensor(np.asarray(lam.theta), device="cuda")
     # The timed steps cycle through OUT_BUFFERS separately allocated outputs:
     # the scatter's speed depends on the physical placement of its output (a
-    # spread of about 15% between allocations of one size, while a plain fill
-    # does not see it), so one allocation would make the figure a matter of luck.
+    # spread of about 15% between allocations of one size), so one allocation
+    # would make the figure a matter of luck.
     bufs = [torch.empty(plan.nnz, dtype=torch.float64, device="cuda") for _ in range(OUT_BUFFERS)]
     n_done = [0]
 
@@ -373,14 +506,21 @@ def main():
         plan.assemble(C, th, out=bufs[n_done[0] % OUT_BUFFERS])
         n_done[0] += 1
 
+    print("headline: %s, %d nnz, %d steps" % (lam.name, plan.nnz, args.steps), file=sys.stderr, flush=True)
     ms_step, ms_kron = _time_steps(torch, fast_step, args.steps, args.warmup, L, "assemble")
+    ms_median = _time_steps_median(torch, fast_step, max(args.steps, 5))
     vals = bufs[(n_done[0] - 1) % OUT_BUFFERS]
     value = plan.nnz / (ms_step * 1e-3)
     alg_bytes = 8.0 * plan.nnz
     achieved = alg_bytes / (ms_kron * 1e-3) / 1e9
+    from oracle import oracle as O
+    parity = _sample_parity(O, lam, plan, vals, rowptr, n_rows=200)
+    plan.check()  # the plan-time bucket grouping holds for the angles passed
+    ceil = _ceilings(torch, bufs)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(lam.name, "k_kron"),
-                "kernel": "k_kron", "kernel_ms": round(ms_kron, 5), "bytes_per_launch": alg_bytes}
+                "kernel": "k_kron_reg", "kernel_ms": round(ms_kron, 5), "bytes_per_launch": alg_bytes,
+                "achievable": dict(ceil, frac_of_write_fill=round(achieved / ceil["write_fill_GBps"], 4))}
 
     out = {
         "metric": "assembled CSR nnz/s (FP64, rel err <=1e-12) fast 2Dx1D vs standard 3D; adjoint ms",
@@ -388,40 +528,35 @@ def main():
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": lam.name, "nnz": plan.nnz, "dof": plan.n_rows, "plies": lam.n_ply,
-                   "degree_inplane": lam.p1, "degree_thickness": lam.q, "elements_inplane": "64x64",
-                   "sets": plan.n_sets, "set_mode": plan.set_mode, "scatter_tuning": tuning or "automatic",
-                   "output_buffers": OUT_BUFFERS,
+                   "degree_inplane": lam.p1, "degree_thickness": lam.q, "elements_inplane": "128x128",
+                   "materials": 2, "sets": plan.n_sets, "set_mode": plan.set_mode,
+                   "scatter_tuning": tuning or "automatic", "output_buffers": OUT_BUFFERS,
                    "parallelism": "single GPU"},
         "roofline": roofline,
+        "ms_per_step_median": ms_median,
         "setup_s": round(setup_s, 3),
+        "parity_sample_relF": parity,
     }
-
-    from oracle import oracle as O
-    out["parity_sample_relF"] = _sample_parity(O, lam, plan, vals, rowptr)
-    if out["parity_sample_relF"] > 1e-12:
+    if parity > 1e-12:
         out["value_invalid"] = "sampled parity above 1e-12"
 
     extra = {}
     if not args.no_extra:
-        extra["matrix_free_apply"] = _apply_workload(torch, np, L, lam, plan, C, th, vals, rowptr, colind,
-                                                     max(10, args.steps), args.warmup)
-    if not args.no_extra:
+        # the standard 3D comparator on the headline plate, into one of the buffers
         try:
-            ms_std, ms_std_k = _time_steps(torch, lambda: plan.assemble_standard(C, th, out=vals),
-                                           max(3, args.steps // 4), 1, L, "standard")
-            flops = STD_FLOPS_PER_NNZ_P2Q2 * plan.nnz
-            extra["standard_same_plate"] = {"nnz_per_s": plan.nnz / (ms_std * 1e-3), "ms_per_step": ms_std,
+            ms_std, ms_std_k = _time_steps(torch, lambda: plan.assemble_standard(C, th, out=vals), 2, 1, L,
+                                           "standard")
+            extra["standard_same_plate"] = {"ms_per_step": ms_std, "nnz_per_s": plan.nnz / (ms_std * 1e-3),
                                             "speedup_fast_vs_standard": ms_std / ms_step,
                                             "element_kernel_ms": ms_std_k,
-                                            "fp64_tflops_algorithmic": flops / (ms_std * 1e-3) / 1e12,
-                                            "fp64_frac": flops / (ms_std * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
+                                            "parity_sample_relF": _sample_parity(O, lam, plan, vals, rowptr,
+                                                                                 n_rows=50)}
         except L.LamError as e:
             extra["standard_same_plate"] = {"skipped": str(e)}
-    del vals, rowptr, colind
+    del vals, bufs, rowptr, plan
     torch.cuda.empty_cache()
     if not args.no_extra:
-        extra["p3_128x128_128ply"] = _fast_workload(torch, np, L, O, W.config_p3_128x128_128ply(), "bucket",
-                                                     max(5, args.steps // 2), args.warmup, standard_steps=2)
+        extra["p2_64x64_32ply"] = _c2_workload(torch, np, L, W, O, args)
     if not args.no_extra:
         extra["adjoint_p2_96x96_64ply"] = _adjoint_workload(torch, np, L, W, O, max(5, args.steps // 2), args.warmup)
     if not args.no_extra and not args.no_batch:
