@@ -684,7 +684,7 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron_reg(Dev d, const double *
         double *out = vals + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
         const int64_t rstride = 3 * (int64_t)Lz * Ls;
         const double *qz = lq + 4 * NSC * (zb - zk0);
-        switch (Lz) {  // thickness row widths q + 1 and 2q + 1 of q = 1..3, uniform over the block
+        switch (Lz) {  // widths 2..5 (q + 1 up to q = 4, 2q + 1 up to q = 2) fixed; 7 and 9 take the loop
           case 2: kron_row<NSC, 2>(qz, pr, out, rstride, astride); break;
           case 3: kron_row<NSC, 3>(qz, pr, out, rstride, astride); break;
           case 4: kron_row<NSC, 4>(qz, pr, out, rstride, astride); break;

@@ -217,13 +217,17 @@ def batch_laminates(n=256, seed=SEED_BATCH):
 
 
 def random_small(rng: np.random.Generator, p=None, q=None, paper_regime=False, anisotropic=True, sheared=True,
-                 n_mat=2, max_ply=4) -> Laminate:
+                 n_mat=2, max_ply=4, split_plies=None) -> Laminate:
     """A tiny laminate with nonuniform knots (one repeated interior knot),
-    a sheared affine map, fully anisotropic materials and random angles.
-    paper_regime: one thickness element spanning all plies."""
+    a sheared affine map, fully anisotropic materials and random angles;
+    in-plane degrees 1..3, thickness degree 1..4.  paper_regime: one
+    thickness element spanning all plies; otherwise one element per ply (C0
+    at interfaces), and with probability 1/2 (split_plies: always / never) one
+    ply gets an extra thickness knot of random multiplicity inside it, so it
+    holds two thickness elements (any through-thickness discretization)."""
     p1 = int(rng.integers(1, 4)) if p is None else p
     p2 = int(rng.integers(1, 4)) if p is None else p
-    q = int(rng.integers(1, 3)) if q is None else q
+    q = int(rng.integers(1, 5)) if q is None else q
 
     def knots(pp, ne):
         inner = np.sort(rng.uniform(0.05, 0.95, size=ne - 1))
@@ -249,6 +253,13 @@ def random_small(rng: np.random.Generator, p=None, q=None, paper_regime=False, a
         mats = [material(jittered(CARBON, rng)) for _ in range(n_mat)]
     ply_mat = rng.integers(0, n_mat, size=m).astype(np.int32)
     theta = rng.uniform(0, np.pi, size=m)
+    if not paper_regime:
+        split = rng.uniform() < 0.5 if split_plies is None else split_plies
+        l = int(rng.integers(0, m))
+        t = iface[l] + (iface[l + 1] - iface[l]) * rng.uniform(0.25, 0.75)
+        mult = int(rng.integers(1, q + 1))
+        if split:
+            k3 = np.sort(np.concatenate([k3, np.full(mult, t)]))
     return Laminate(p1=p1, k1=k1, p2=p2, k2=k2, q=q, k3=k3, jac=J, iface=iface, ply_mat=ply_mat,
                     theta=theta, C=np.stack(mats), name="random_small")
 
