@@ -21,9 +21,17 @@
  *     (11,22,33,12,13,23) with engineering shears.  The third column (u_3) is
  *     (0,0,d3,0,d1,d2): the printed equation repeats d3 in the last entry,
  *     which cannot be right because gamma_23 = du_2/dx_3 + du_3/dx_2;
- *   - physical gradients by the pull-back grad B = DF^{-T} grad_hat B (eq. gradient)
- *     for a constant map gradient DF (Assumption 2 with an affine extrusion,
- *     eq. extrusion);
+ *   - physical gradients by the pull-back grad B = DF^{-T} grad_hat B (eq. gradient),
+ *     either for a constant map gradient DF (an affine extrusion) or for the
+ *     extrusion of a curved mid-surface, F(xi) = S(xi1, xi2) + xi3 a
+ *     (Assumption 2, eq. extrusion), S given by control points on the
+ *     in-plane basis, with DF = [dS/dxi1 | dS/dxi2 | a] evaluated at every
+ *     Gauss point;
+ *   - in-plane basis: B-splines, or NURBS (Sec. 2.2) when weights are given,
+ *     R^i = w_i N^i / sum_k w_k N^k, used for the geometry and the
+ *     displacement alike;
+ *   - ply materials constant, or varying in the plane (Assumption 3): a
+ *     6x6 per material and in-plane control function, C_m(xi) = sum_i R^i(xi) C_{m,i};
  *   - the ply tensor D_l: the 6x6 given in material axes is expanded to the
  *     fourth-order tensor, rotated by theta about +e3 with four rotation
  *     matrices, and folded back to Voigt form (eq. D).
@@ -54,8 +62,15 @@ typedef struct {
   const int32_t *ply_mat; /* material of every ply, bottom to top */
   const double *ply_theta;/* ply angle in radians, counterclockwise about +e3 */
   int32_t n_mat;
-  const double *C;        /* n_mat 6x6 Voigt matrices in material axes, row-major */
+  const double *C;        /* n_mat 6x6 Voigt matrices in material axes, row-major
+                             (n_mat * n1*n2 of them when mat_field is set) */
   int32_t ng1, ng2, ngz;  /* Gauss points per element direction / per z cell */
+  /* Curved extruded shell (optional): when ctrl is not NULL, F(xi) = S(xi1,xi2) + xi3 a
+   * with S(xi1,xi2) = sum_i R^i(xi1,xi2) ctrl_i, and J is not used. */
+  const double *ctrl;     /* n1*n2 control points (x,y,z), in-plane function order i1 + n1*i2 */
+  const double *wts;      /* NULL (B-splines) or n1*n2 positive weights (NURBS) */
+  double a[3];            /* extrusion vector */
+  int32_t mat_field;      /* 1: C holds a 6x6 per material and in-plane function */
 } or_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -326,6 +341,108 @@ static void ctx_free(ctx *c) {
   free(c->gx1); free(c->gw1); free(c->gx2); free(c->gw2); free(c->gx3); free(c->gw3);
 }
 
+/* In-plane parametric point of Gauss point (g1, g2) of the element with knot
+ * intervals s1, s2, and the element's half lengths. */
+static void point_coords(const ctx *c, int s1, int s2, int g1, int g2, double *x1, double *x2, double *h1,
+                         double *h2) {
+  const or_problem *P = &c->P;
+  double a1 = P->k1[s1], b1 = P->k1[s1 + 1], a2 = P->k2[s2], b2 = P->k2[s2 + 1];
+  *h1 = 0.5 * (b1 - a1);
+  *h2 = 0.5 * (b2 - a2);
+  *x1 = 0.5 * (a1 + b1) + *h1 * c->gx1[g1];
+  *x2 = 0.5 * (a2 + b2) + *h2 * c->gx2[g2];
+}
+
+/* The (p1+1)(p2+1) in-plane functions nonzero on element (s1, s2) at (x1, x2):
+ * values R and derivatives dR1 = dR/dxi1, dR2 = dR/dxi2, local index
+ * b = b2*(p1+1) + b1 for the function (s1-p1+b1, s2-p2+b2).  B-spline
+ * products; with weights, the NURBS quotient R = w N / W, W = sum w N, and
+ * its derivative by the quotient rule. */
+static void inplane_basis(const ctx *c, int s1, int s2, double x1, double x2, double *R, double *dR1,
+                          double *dR2) {
+  const or_problem *P = &c->P;
+  int p1 = P->p1, p2 = P->p2;
+  double N1[16], d1[16], N2[16], d2[16];
+  bspline_on_span(p1, P->k1, s1, x1, N1, d1);
+  bspline_on_span(p2, P->k2, s2, x2, N2, d2);
+  for (int b2 = 0; b2 <= p2; ++b2)
+    for (int b1 = 0; b1 <= p1; ++b1) {
+      int b = b2 * (p1 + 1) + b1;
+      R[b] = N1[b1] * N2[b2];
+      dR1[b] = d1[b1] * N2[b2];
+      dR2[b] = N1[b1] * d2[b2];
+    }
+  if (!P->wts) return;
+  int nb = (p1 + 1) * (p2 + 1);
+  double W = 0.0, W1 = 0.0, W2 = 0.0, w[256];
+  for (int b2 = 0; b2 <= p2; ++b2)
+    for (int b1 = 0; b1 <= p1; ++b1) {
+      int b = b2 * (p1 + 1) + b1;
+      w[b] = P->wts[(s2 - p2 + b2) * c->n1 + (s1 - p1 + b1)];
+      W += w[b] * R[b];
+      W1 += w[b] * dR1[b];
+      W2 += w[b] * dR2[b];
+    }
+  for (int b = 0; b < nb; ++b) {
+    double r = w[b] * R[b] / W;
+    dR1[b] = (w[b] * dR1[b] - r * W1) / W;
+    dR2[b] = (w[b] * dR2[b] - r * W2) / W;
+    R[b] = r;
+  }
+}
+
+/* DF^{-1} (row-major) and det DF at an in-plane point of element (s1, s2):
+ * the constant map, or DF = [dS/dxi1 | dS/dxi2 | a] for the curved
+ * extrusion, dS/dxi_k = sum_b dR_k[b] ctrl(b).  Returns -1 if singular. */
+static int point_geometry(const ctx *c, int s1, int s2, const double *dR1, const double *dR2, double *Ji,
+                          double *det) {
+  const or_problem *P = &c->P;
+  if (!P->ctrl) {
+    memcpy(Ji, c->Ji, sizeof(double) * 9);
+    *det = c->detJ;
+    return 0;
+  }
+  int p1 = P->p1, p2 = P->p2;
+  double S1[3] = {0, 0, 0}, S2[3] = {0, 0, 0};
+  for (int b2 = 0; b2 <= p2; ++b2)
+    for (int b1 = 0; b1 <= p1; ++b1) {
+      int b = b2 * (p1 + 1) + b1;
+      const double *X = P->ctrl + 3 * (size_t)((s2 - p2 + b2) * c->n1 + (s1 - p1 + b1));
+      for (int k = 0; k < 3; ++k) {
+        S1[k] += dR1[b] * X[k];
+        S2[k] += dR2[b] * X[k];
+      }
+    }
+  double J[9];
+  for (int k = 0; k < 3; ++k) {
+    J[3 * k + 0] = S1[k];
+    J[3 * k + 1] = S2[k];
+    J[3 * k + 2] = P->a[k];
+  }
+  return inv3(J, Ji, det);
+}
+
+/* The rotated tensor of ply l at an in-plane point with basis values R on
+ * element (s1, s2): the constant one, or the rotation of
+ * C_m(xi) = sum_b R[b] C_{m, function b} for a material field. */
+static void point_material(const ctx *c, int l, int s1, int s2, const double *R, double *D) {
+  const or_problem *P = &c->P;
+  if (!P->mat_field) {
+    memcpy(D, c->Dply + 36 * (size_t)l, sizeof(double) * 36);
+    return;
+  }
+  int p1 = P->p1, p2 = P->p2;
+  double Cx[36] = {0};
+  for (int b2 = 0; b2 <= p2; ++b2)
+    for (int b1 = 0; b1 <= p1; ++b1) {
+      int b = b2 * (p1 + 1) + b1;
+      size_t is = (size_t)(s2 - p2 + b2) * c->n1 + (s1 - p1 + b1);
+      const double *Cc = P->C + 36 * ((size_t)P->ply_mat[l] * c->ns + is);
+      for (int e = 0; e < 36; ++e) Cx[e] += R[b] * Cc[e];
+    }
+  or_rotate_voigt(Cx, P->ply_theta[l], D);
+}
+
 /* Open knot vector on [0,1]: p+1 zeros, non-decreasing interior, p+1 ones. */
 static int check_knots(int p, int nk, const double *t) {
   if (p < 0 || p > 15 || nk < 2 * p + 2) return -1;
@@ -350,11 +467,20 @@ static int ctx_init(ctx *c, const or_problem *P) {
     if (!(P->iface[l + 1] > P->iface[l])) return -1;
     if (P->ply_mat[l] < 0 || P->ply_mat[l] >= P->n_mat) return -1;
   }
-  if (inv3(P->J, c->Ji, &c->detJ)) return -1;
+  if (!P->ctrl && inv3(P->J, c->Ji, &c->detJ)) return -1;
   c->n1 = n_funcs(P->p1, P->nk1);
   c->n2 = n_funcs(P->p2, P->nk2);
   c->nt = n_funcs(P->q, P->nk3);
   c->ns = c->n1 * c->n2;
+  if (P->ctrl) {
+    for (int e = 0; e < 3 * c->ns; ++e)
+      if (!isfinite(P->ctrl[e])) return -1;
+    for (int e = 0; e < 3; ++e)
+      if (!isfinite(P->a[e])) return -1;
+  }
+  if (P->wts)
+    for (int e = 0; e < c->ns; ++e)
+      if (!(P->wts[e] > 0.0) || !isfinite(P->wts[e])) return -1;
   c->sp1 = (int *)malloc(sizeof(int) * (size_t)P->nk1);
   c->sp2 = (int *)malloc(sizeof(int) * (size_t)P->nk2);
   c->sp3 = (int *)malloc(sizeof(int) * (size_t)P->nk3);
@@ -372,12 +498,11 @@ static int ctx_init(ctx *c, const or_problem *P) {
   overlap_1d(P->p2, P->nk2, P->k2, c->c2, c->a2);
   overlap_1d(P->q, P->nk3, P->k3, c->c3, c->a3);
   c->Dply = (double *)malloc(sizeof(double) * 36 * (size_t)P->n_ply);
-  for (int l = 0; l < P->n_ply; ++l) {
-    const double *Cm = P->C + 36 * (size_t)P->ply_mat[l];
-    for (int a = 0; a < 36; ++a)
-      if (!isfinite(Cm[a])) return -1;
-    or_rotate_voigt(Cm, P->ply_theta[l], c->Dply + 36 * (size_t)l);
-  }
+  const size_t per_mat = P->mat_field ? (size_t)c->ns : 1;
+  for (size_t e = 0; e < 36 * per_mat * (size_t)P->n_mat; ++e)
+    if (!isfinite(P->C[e])) return -1;
+  for (int l = 0; l < P->n_ply; ++l)  /* constant materials: each ply's rotated tensor */
+    or_rotate_voigt(P->C + 36 * per_mat * (size_t)P->ply_mat[l], P->ply_theta[l], c->Dply + 36 * (size_t)l);
   int g1 = P->ng1 > 0 ? P->ng1 : P->p1 + 1;
   int g2 = P->ng2 > 0 ? P->ng2 : P->p2 + 1;
   int g3 = P->ngz > 0 ? P->ngz : P->q + 1;
@@ -388,6 +513,16 @@ static int ctx_init(ctx *c, const or_problem *P) {
   if (or_gauss_legendre(g1, c->gx1, c->gw1) || or_gauss_legendre(g2, c->gx2, c->gw2) ||
       or_gauss_legendre(g3, c->gx3, c->gw3))
     return -1;
+  if (P->ctrl) /* a curved map must be invertible at every in-plane Gauss point */
+    for (int z2 = 0; z2 < c->ns2; ++z2)
+      for (int z1 = 0; z1 < c->ns1; ++z1)
+        for (int b = 0; b < g2; ++b)
+          for (int a = 0; a < g1; ++a) {
+            double R[256], dR1[256], dR2[256], Ji[9], det, x1, x2, h1, h2;
+            point_coords(c, c->sp1[z1], c->sp2[z2], a, b, &x1, &x2, &h1, &h2);
+            inplane_basis(c, c->sp1[z1], c->sp2[z2], x1, x2, R, dR1, dR2);
+            if (point_geometry(c, c->sp1[z1], c->sp2[z2], dR1, dR2, Ji, &det)) return -1;
+          }
   return 0;
 }
 
@@ -464,35 +599,35 @@ static int64_t find_col(const int32_t *col, int64_t lo, int64_t hi, int32_t key)
  * thickness interval [za, zb] inside knot interval s3.  The caller loops over
  * the cell's Gauss points; cell_point fills, for point (g1,g2,g3), the weight
  * and the physical gradients of the nloc = (p1+1)(p2+1)(q+1) local functions,
- * local index a = (at*(p2+1) + a2)*(p1+1) + a1. */
+ * local index a = (at*(p2+1) + a2)*(p1+1) + a1, and (R) the values of the
+ * (p1+1)(p2+1) in-plane functions. */
 typedef struct {
   int s1, s2, s3;
   double za, zb;
 } cell_t;
 
-static double cell_point(const ctx *c, const cell_t *cl, int g1, int g2, int g3, double (*grad)[3]) {
+static double cell_point(const ctx *c, const cell_t *cl, int g1, int g2, int g3, double (*grad)[3], double *R) {
   const or_problem *P = &c->P;
   int p1 = P->p1, p2 = P->p2, q = P->q;
-  double a1 = P->k1[cl->s1], b1 = P->k1[cl->s1 + 1];
-  double a2 = P->k2[cl->s2], b2 = P->k2[cl->s2 + 1];
-  double h1 = 0.5 * (b1 - a1), h2 = 0.5 * (b2 - a2), h3 = 0.5 * (cl->zb - cl->za);
-  double x1 = 0.5 * (a1 + b1) + h1 * c->gx1[g1];
-  double x2 = 0.5 * (a2 + b2) + h2 * c->gx2[g2];
+  double x1, x2, h1, h2;
+  point_coords(c, cl->s1, cl->s2, g1, g2, &x1, &x2, &h1, &h2);
+  double h3 = 0.5 * (cl->zb - cl->za);
   double x3 = 0.5 * (cl->za + cl->zb) + h3 * c->gx3[g3];
-  double N1[16], d1[16], N2[16], d2[16], T[16], dT[16];
-  bspline_on_span(p1, P->k1, cl->s1, x1, N1, d1);
-  bspline_on_span(p2, P->k2, cl->s2, x2, N2, d2);
+  double dR1[256], dR2[256], T[16], dT[16], Ji[9], det;
+  inplane_basis(c, cl->s1, cl->s2, x1, x2, R, dR1, dR2);
   bspline_on_span(q, P->k3, cl->s3, x3, T, dT);
+  if (point_geometry(c, cl->s1, cl->s2, dR1, dR2, Ji, &det)) return NAN;  /* excluded by ctx_init */
   int a = 0;
   for (int at = 0; at <= q; ++at)
     for (int b2 = 0; b2 <= p2; ++b2)
       for (int b1 = 0; b1 <= p1; ++b1, ++a) {
-        double gh[3] = {d1[b1] * N2[b2] * T[at], N1[b1] * d2[b2] * T[at], N1[b1] * N2[b2] * dT[at]};
+        int b = b2 * (p1 + 1) + b1;
+        double gh[3] = {dR1[b] * T[at], dR2[b] * T[at], R[b] * dT[at]};
         /* grad = DF^{-T} gh:  grad_k = sum_m Ji[m][k] gh[m] */
         for (int k = 0; k < 3; ++k)
-          grad[a][k] = c->Ji[0 * 3 + k] * gh[0] + c->Ji[1 * 3 + k] * gh[1] + c->Ji[2 * 3 + k] * gh[2];
+          grad[a][k] = Ji[0 * 3 + k] * gh[0] + Ji[1 * 3 + k] * gh[1] + Ji[2 * 3 + k] * gh[2];
       }
-  return c->gw1[g1] * c->gw2[g2] * c->gw3[g3] * h1 * h2 * h3 * fabs(c->detJ);
+  return c->gw1[g1] * c->gw2[g2] * c->gw3[g3] * h1 * h2 * h3 * fabs(det);
 }
 
 static int64_t local_to_global(const ctx *c, const cell_t *cl, int a) {
@@ -561,12 +696,13 @@ int or_assemble(const or_problem *P, const int64_t *rowptr, const int32_t *colin
           int ncell = column_cells(&c, s1, s2, cells, plies);
           for (int ic = 0; ic < ncell; ++ic) {
             const cell_t *cl = &cells[ic];
-            const double *D = c.Dply + 36 * (size_t)plies[ic];
             memset(Ke, 0, sizeof(double) * 9 * (size_t)nloc * nloc);
             for (int g3 = 0; g3 < c.P.ngz; ++g3)
               for (int g2 = 0; g2 < c.P.ng2; ++g2)
                 for (int g1 = 0; g1 < c.P.ng1; ++g1) {
-                  double w = cell_point(&c, cl, g1, g2, g3, grad);
+                  double R[256], D[36];
+                  double w = cell_point(&c, cl, g1, g2, g3, grad, R);
+                  point_material(&c, plies[ic], cl->s1, cl->s2, R, D);
                   for (int a = 0; a < nloc; ++a) bmat(grad[a], Bm[a]);
                   for (int a = 0; a < nloc; ++a)
                     for (int b = 0; b < nloc; ++b) {
@@ -652,14 +788,15 @@ int or_assemble_rows(const or_problem *P, int64_t nsel, const int64_t *rows, int
           for (int ic = 0; ic < ncell; ++ic) {
             const cell_t *cl = &cells[ic];
             if (cl->s3 < it || cl->s3 > it + P->q) continue;
-            const double *D = c.Dply + 36 * (size_t)plies[ic];
             int aloc = -1;
             for (int a = 0; a < nloc; ++a)
               if (local_to_global(&c, cl, a) == gi) aloc = a;
             for (int g3 = 0; g3 < c.P.ngz; ++g3)
               for (int g2 = 0; g2 < c.P.ng2; ++g2)
                 for (int g1 = 0; g1 < c.P.ng1; ++g1) {
-                  double w = cell_point(&c, cl, g1, g2, g3, grad);
+                  double R[256], D[36];
+                  double w = cell_point(&c, cl, g1, g2, g3, grad, R);
+                  point_material(&c, plies[ic], cl->s1, cl->s2, R, D);
                   for (int a = 0; a < nloc; ++a) bmat(grad[a], Bm[a]);
                   for (int b = 0; b < nloc; ++b) {
                     double blk[3][3];
@@ -689,7 +826,7 @@ int or_assemble_rows(const or_problem *P, int64_t nsel, const int64_t *rows, int
 int or_grad_D(const or_problem *P, const int64_t *rowptr, const int32_t *colind, const double *G,
               double *dLdD, int nthreads) {
   ctx c;
-  if (ctx_init(&c, P)) { ctx_free(&c); return -1; }
+  if (P->mat_field || ctx_init(&c, P)) { if (!P->mat_field) ctx_free(&c); return -1; }
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
@@ -732,7 +869,8 @@ int or_grad_D(const or_problem *P, const int64_t *rowptr, const int32_t *colind,
           for (int g3 = 0; g3 < c.P.ngz; ++g3)
             for (int g2 = 0; g2 < c.P.ng2; ++g2)
               for (int g1 = 0; g1 < c.P.ng1; ++g1) {
-                double w = cell_point(&c, cl, g1, g2, g3, grad);
+                double R[256];
+                double w = cell_point(&c, cl, g1, g2, g3, grad, R);
                 for (int a = 0; a < nloc; ++a) bmat(grad[a], Bm[a]);
                 /* V_a[J][r] = sum_{b,s} G[(a,r),(b,s)] B_b[J][s] */
                 for (int a = 0; a < nloc; ++a)
@@ -792,6 +930,40 @@ int or_grad_material(int32_t n_ply, const int32_t *ply_mat, const double *ply_th
   return 0;
 }
 
+/* The mapped position of an in-plane parametric point and its two tangents:
+ * S(xi1, xi2) = sum_i R^i ctrl_i and dS/dxi_k for a curved plan; for an
+ * affine one, x = DF (xi1, xi2, 0) and the first two columns of DF. */
+int or_surface_eval(const or_problem *P, double x1, double x2, double *x, double *t1, double *t2) {
+  ctx c;
+  if (ctx_init(&c, P)) { ctx_free(&c); return -1; }
+  if (!(x1 >= 0.0 && x1 <= 1.0 && x2 >= 0.0 && x2 <= 1.0)) { ctx_free(&c); return -1; }
+  for (int k = 0; k < 3; ++k) x[k] = t1[k] = t2[k] = 0.0;
+  if (!P->ctrl) {
+    for (int k = 0; k < 3; ++k) {
+      x[k] = P->J[3 * k] * x1 + P->J[3 * k + 1] * x2;
+      t1[k] = P->J[3 * k];
+      t2[k] = P->J[3 * k + 1];
+    }
+    ctx_free(&c);
+    return 0;
+  }
+  int s1 = find_span(P->p1, P->nk1, P->k1, x1), s2 = find_span(P->p2, P->nk2, P->k2, x2);
+  double R[256], dR1[256], dR2[256];
+  inplane_basis(&c, s1, s2, x1, x2, R, dR1, dR2);
+  for (int b2 = 0; b2 <= P->p2; ++b2)
+    for (int b1 = 0; b1 <= P->p1; ++b1) {
+      int b = b2 * (P->p1 + 1) + b1;
+      const double *X = P->ctrl + 3 * (size_t)((s2 - P->p2 + b2) * c.n1 + (s1 - P->p1 + b1));
+      for (int k = 0; k < 3; ++k) {
+        x[k] += R[b] * X[k];
+        t1[k] += dR1[b] * X[k];
+        t2[k] += dR2[b] * X[k];
+      }
+    }
+  ctx_free(&c);
+  return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Plain definitions of the split operators of Sec. 3.
  *
@@ -811,28 +983,24 @@ int or_P_pair(const or_problem *P, const double *D, int is, int js, double *Pout
     for (int z1 = 0; z1 < c.ns1; ++z1) {
       int s1 = c.sp1[z1];
       if (s1 < i1 || s1 > i1 + P->p1 || s1 < j1 || s1 > j1 + P->p1) continue;
-      double a1 = P->k1[s1], b1 = P->k1[s1 + 1], a2 = P->k2[s2], b2 = P->k2[s2 + 1];
-      double h1 = 0.5 * (b1 - a1), h2 = 0.5 * (b2 - a2);
       for (int g2 = 0; g2 < c.P.ng2; ++g2)
         for (int g1 = 0; g1 < c.P.ng1; ++g1) {
-          double x1 = 0.5 * (a1 + b1) + h1 * c.gx1[g1];
-          double x2 = 0.5 * (a2 + b2) + h2 * c.gx2[g2];
-          double w = c.gw1[g1] * c.gw2[g2] * h1 * h2 * fabs(c.detJ);
-          double N1[16], d1[16], N2[16], d2[16];
-          bspline_on_span(P->p1, P->k1, s1, x1, N1, d1);
-          bspline_on_span(P->p2, P->k2, s2, x2, N2, d2);
-          int ai1 = i1 - (s1 - P->p1), ai2 = i2 - (s2 - P->p2);
-          int aj1 = j1 - (s1 - P->p1), aj2 = j2 - (s2 - P->p2);
+          double x1, x2, h1, h2, R[256], dR1[256], dR2[256], Ji[9], det;
+          point_coords(&c, s1, s2, g1, g2, &x1, &x2, &h1, &h2);
+          inplane_basis(&c, s1, s2, x1, x2, R, dR1, dR2);
+          point_geometry(&c, s1, s2, dR1, dR2, Ji, &det);
+          double w = c.gw1[g1] * c.gw2[g2] * h1 * h2 * fabs(det);
+          int bi = (i2 - (s2 - P->p2)) * (P->p1 + 1) + i1 - (s1 - P->p1);
+          int bj = (j2 - (s2 - P->p2)) * (P->p1 + 1) + j1 - (s1 - P->p1);
           double hat[2][2][3]; /* [function i/j][alpha][component] */
-          double Si = N1[ai1] * N2[ai2], Sj = N1[aj1] * N2[aj2];
-          double gi[3] = {d1[ai1] * N2[ai2], N1[ai1] * d2[ai2], 0.0};
-          double gj[3] = {d1[aj1] * N2[aj2], N1[aj1] * d2[aj2], 0.0};
-          double wi[3] = {0.0, 0.0, Si}, wj[3] = {0.0, 0.0, Sj};
+          double gi[3] = {dR1[bi], dR2[bi], 0.0};
+          double gj[3] = {dR1[bj], dR2[bj], 0.0};
+          double wi[3] = {0.0, 0.0, R[bi]}, wj[3] = {0.0, 0.0, R[bj]};
           for (int k = 0; k < 3; ++k) {
-            hat[0][0][k] = c.Ji[0 * 3 + k] * gi[0] + c.Ji[1 * 3 + k] * gi[1] + c.Ji[2 * 3 + k] * gi[2];
-            hat[0][1][k] = c.Ji[0 * 3 + k] * wi[0] + c.Ji[1 * 3 + k] * wi[1] + c.Ji[2 * 3 + k] * wi[2];
-            hat[1][0][k] = c.Ji[0 * 3 + k] * gj[0] + c.Ji[1 * 3 + k] * gj[1] + c.Ji[2 * 3 + k] * gj[2];
-            hat[1][1][k] = c.Ji[0 * 3 + k] * wj[0] + c.Ji[1 * 3 + k] * wj[1] + c.Ji[2 * 3 + k] * wj[2];
+            hat[0][0][k] = Ji[0 * 3 + k] * gi[0] + Ji[1 * 3 + k] * gi[1] + Ji[2 * 3 + k] * gi[2];
+            hat[0][1][k] = Ji[0 * 3 + k] * wi[0] + Ji[1 * 3 + k] * wi[1] + Ji[2 * 3 + k] * wi[2];
+            hat[1][0][k] = Ji[0 * 3 + k] * gj[0] + Ji[1 * 3 + k] * gj[1] + Ji[2 * 3 + k] * gj[2];
+            hat[1][1][k] = Ji[0 * 3 + k] * wj[0] + Ji[1 * 3 + k] * wj[1] + Ji[2 * 3 + k] * wj[2];
           }
           for (int al = 0; al < 2; ++al)
             for (int be = 0; be < 2; ++be) {
@@ -884,7 +1052,7 @@ int or_Q_pair(const or_problem *P, int ply, int it, int jt, double *Qout) {
  * linear in D_l).  u holds 3 values per global function (DOF order). */
 int or_grad_uu(const or_problem *P, const double *u, double *dLdD, int nthreads) {
   ctx c;
-  if (ctx_init(&c, P)) { ctx_free(&c); return -1; }
+  if (P->mat_field || ctx_init(&c, P)) { if (!P->mat_field) ctx_free(&c); return -1; }
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
@@ -912,7 +1080,8 @@ int or_grad_uu(const or_problem *P, const double *u, double *dLdD, int nthreads)
           for (int g3 = 0; g3 < c.P.ngz; ++g3)
             for (int g2 = 0; g2 < c.P.ng2; ++g2)
               for (int g1 = 0; g1 < c.P.ng1; ++g1) {
-                double w = cell_point(&c, cl, g1, g2, g3, grad);
+                double R[256];
+                double w = cell_point(&c, cl, g1, g2, g3, grad, R);
                 double eps[6] = {0, 0, 0, 0, 0, 0};
                 for (int a = 0; a < nloc; ++a) {
                   double B[6][3];

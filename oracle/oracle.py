@@ -8,8 +8,14 @@ A laminate is passed as any object with the attributes
   jac                     3x3 constant map gradient DF
   iface                   n_ply+1 ply interfaces in the thickness parameter
   ply_mat, theta          material index and angle (radians) of every ply
-  C                       (n_mat, 6, 6) Voigt matrices in material axes
+  C                       (n_mat, 6, 6) Voigt matrices in material axes; with
+                          mat_field, (n_mat, n1*n2, 6, 6): one per in-plane function
   ng                      Gauss points (in-plane 1, in-plane 2, per z cell); 0 = degree+1
+and optionally (a curved extruded shell, F = S(xi1, xi2) + xi3 a_ext)
+  ctrl                    (n1*n2, 3) control points of S (in-plane function order)
+  weights                 (n1*n2,) NURBS weights, or None
+  a_ext                   (3,) extrusion vector
+  mat_field               True: C varies in the plane as above
 """
 from __future__ import annotations
 
@@ -52,6 +58,7 @@ class _Problem(ctypes.Structure):
         ("n_mat", ctypes.c_int32),
         ("C", _dp),
         ("ng1", ctypes.c_int32), ("ng2", ctypes.c_int32), ("ngz", ctypes.c_int32),
+        ("ctrl", _dp), ("wts", _dp), ("a", ctypes.c_double * 3), ("mat_field", ctypes.c_int32),
     ]
 
 
@@ -77,6 +84,7 @@ def lib():
         L.or_grad_material.argtypes = [ctypes.c_int32, _i32p, _dp, ctypes.c_int32, _dp, _dp, _dp, _dp]
         L.or_P_pair.argtypes = [ctypes.POINTER(_Problem), _dp, ctypes.c_int, ctypes.c_int, _dp]
         L.or_Q_pair.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
+        L.or_surface_eval.argtypes = [ctypes.POINTER(_Problem), ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -115,6 +123,12 @@ class _Bound:
         self.ply_mat = np.ascontiguousarray(lam.ply_mat, dtype=np.int32)
         self.theta = np.ascontiguousarray(lam.theta, dtype=np.float64)
         self.C = np.ascontiguousarray(np.asarray(lam.C, dtype=np.float64).reshape(-1, 36))
+        ctrl = getattr(lam, "ctrl", None)
+        wts = getattr(lam, "weights", None)
+        self.ctrl = None if ctrl is None else np.ascontiguousarray(np.asarray(ctrl, dtype=np.float64).reshape(-1))
+        self.wts = None if wts is None else np.ascontiguousarray(np.asarray(wts, dtype=np.float64).reshape(-1))
+        self.mat_field = int(bool(getattr(lam, "mat_field", False)))
+        n_mat = int(np.asarray(lam.C).shape[0])
         ng = tuple(getattr(lam, "ng", (0, 0, 0)))
         J = np.asarray(lam.jac, dtype=np.float64).reshape(9)
         s = _Problem()
@@ -127,9 +141,16 @@ class _Bound:
         s.iface = _p(self.iface)
         s.ply_mat = _p(self.ply_mat, _i32p)
         s.ply_theta = _p(self.theta)
-        s.n_mat = self.C.shape[0]
+        s.n_mat = n_mat
         s.C = _p(self.C)
         s.ng1, s.ng2, s.ngz = (int(g) for g in ng)
+        s.ctrl = None if self.ctrl is None else _p(self.ctrl)
+        s.wts = None if self.wts is None else _p(self.wts)
+        a = getattr(lam, "a_ext", None)
+        for k in range(3):
+            s.a[k] = 0.0 if a is None else float(a[k])
+        s.mat_field = self.mat_field
+        self.n_mat = n_mat
         self.s = s
 
     def ref(self):
@@ -238,6 +259,14 @@ def grad_material(lam, dLdD):
 def grad(lam, G, nthreads=0, pattern_=None):
     rowptr, colind = pattern(lam) if pattern_ is None else pattern_
     return grad_material(lam, grad_D(lam, rowptr, colind, G, nthreads))
+
+
+def surface_eval(lam, x1, x2):
+    """(S, dS/dxi1, dS/dxi2) of the laminate's in-plane map at (x1, x2)."""
+    b = _Bound(lam)
+    x, t1, t2 = np.zeros(3), np.zeros(3), np.zeros(3)
+    _check(lib().or_surface_eval(b.ref(), float(x1), float(x2), _p(x), _p(t1), _p(t2)), "surface_eval")
+    return x, t1, t2
 
 
 def P_pair(lam, D, i_s, j_s):

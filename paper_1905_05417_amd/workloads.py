@@ -8,7 +8,9 @@ constant map gradient of the extruded box, the ply stack and the materials.
 Workloads mirror the paper's setting (Sec. 4: flat plate, tensor-product
 B-splines in-plane, plies stacked [0/90]... or [0/45/-45/90]..., orthotropic
 plies rotated about the plate normal), at the sizes used by the tests and the
-benchmark.  Readings fixed here (the paper leaves them open):
+benchmark, and the shells of Sec. 2.3 (a curved B-spline or NURBS mid-surface
+extruded along a constant vector) with materials varying in the plane
+(Assumption 3).  Readings fixed here (the paper leaves them open):
   * thickness space: degree q per ply, one element per ply, C0 at interfaces
     (interior interface knots repeated q times);
   * total laminate thickness H (0.1 for the Q1 case, 0.02 otherwise), plies of
@@ -40,10 +42,15 @@ class Laminate:
     iface: np.ndarray          # (n_ply+1,)
     ply_mat: np.ndarray        # (n_ply,) int32
     theta: np.ndarray          # (n_ply,) radians
-    C: np.ndarray              # (n_mat,6,6) material axes
+    C: np.ndarray              # (n_mat,6,6) material axes; (n_mat, n1*n2, 6, 6) with mat_field
     ng: tuple = (0, 0, 0)
     name: str = ""
     meta: dict = field(default_factory=dict)
+    # curved extruded shell F(xi) = S(xi1, xi2) + xi3 a_ext (jac unused when ctrl is set)
+    ctrl: np.ndarray | None = None     # (n1*n2, 3) control points of S, in-plane function order
+    weights: np.ndarray | None = None  # (n1*n2,) NURBS weights, or None for B-splines
+    a_ext: np.ndarray | None = None    # (3,) extrusion vector
+    mat_field: bool = False            # C varies in the plane: one 6x6 per material and in-plane function
 
     @property
     def n1(self):
@@ -279,3 +286,159 @@ def control_points(lam: Laminate) -> np.ndarray:
     T, Y, X = np.meshgrid(g3, g2, g1, indexing="ij")
     xi = np.stack([X.ravel(), Y.ravel(), T.ravel()], axis=1)
     return xi @ np.asarray(lam.jac).T
+
+
+# --------------------------------------------------------------- shells ----
+def _blossom_coeffs(p: int, t: np.ndarray):
+    """Per basis function i of degree p on knots t: (mean of t[i+1..i+p],
+    mean of t_j t_k over pairs j < k of them), the B-spline coefficients of
+    xi and xi^2 (their blossoms), so that sum_i c_i N_i reproduces them exactly."""
+    n = len(t) - p - 1
+    m1, m2 = np.zeros(n), np.zeros(n)
+    for i in range(n):
+        u = t[i + 1:i + p + 1]
+        m1[i] = u.mean() if p > 0 else 0.5 * (t[i] + t[i + 1])
+        if p >= 2:
+            m2[i] = sum(u[j] * u[k] for j in range(p) for k in range(j + 1, p)) / (p * (p - 1) / 2)
+    return m1, m2
+
+
+def flat_shell(lam: Laminate) -> Laminate:
+    """The same laminate described as a shell: S(xi1, xi2) = DF (xi1, xi2, 0)
+    by control points at the Greville abscissae (B-splines reproduce linear
+    maps), extruded along DF e3."""
+    import copy
+    out = copy.copy(lam)
+    g1, g2 = greville(lam.p1, lam.k1), greville(lam.p2, lam.k2)
+    Y, X = np.meshgrid(g2, g1, indexing="ij")
+    xi = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], axis=1)
+    J = np.asarray(lam.jac, dtype=np.float64)
+    out.ctrl = xi @ J.T
+    out.a_ext = J[:, 2].copy()
+    out.weights = None
+    out.name = lam.name + "_as_shell"
+    return out
+
+
+def curved_shell(p, ne, q, angles_deg, mats, ply_mat, H=0.02, Lx=1.0, Ly=1.0, shear=0.3, bump=0.2, name="",
+                 ne2=None, p2=None) -> Laminate:
+    """A curved B-spline shell: S(xi) = (Lx xi1, Ly xi2 + shear xi1 (1 - xi1),
+    bump (xi1 xi2 + xi1 (1 - xi1))) extruded along (0, 0, H), its control
+    points the blossoms of these quadratics (exact for p >= 2).  Its map
+    gradient varies over the plane while det DF = Lx Ly H (the projection on
+    the xy-plane is a shear), so the shell's volume is Lx Ly H."""
+    p2 = p if p2 is None else p2
+    if min(p, p2) < 2:
+        raise ValueError("curved_shell reproduces quadratics: degree >= 2")
+    lam = plate(p, ne, q, angles_deg, mats, ply_mat, H=H, L=(Lx, Ly), name=name, ne2=ne2, p2=p2)
+    a1, q1 = _blossom_coeffs(lam.p1, lam.k1)
+    a2, _ = _blossom_coeffs(lam.p2, lam.k2)
+    A2, A1 = np.meshgrid(a2, a1, indexing="ij")
+    Q1 = np.meshgrid(a2, q1, indexing="ij")[1]
+    x = Lx * A1
+    y = Ly * A2 + shear * (A1 - Q1)
+    z = bump * (A1 * A2 + (A1 - Q1))
+    lam.ctrl = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    lam.a_ext = np.array([0.0, 0.0, H])
+    lam.weights = None
+    return lam
+
+
+def _insert_knot(p, t, P, w, u):
+    """Boehm's knot insertion in homogeneous coordinates: knot u once into the
+    degree-p curve with knots t, control points P (n, d) and weights w (n,)."""
+    n = len(t) - p - 1
+    k = np.searchsorted(t, u, side="right") - 1
+    Pw = np.concatenate([P * w[:, None], w[:, None]], axis=1)
+    Q = np.zeros((n + 1, Pw.shape[1]))
+    for i in range(n + 1):
+        if i <= k - p:
+            Q[i] = Pw[i]
+        elif i > k:
+            Q[i] = Pw[i - 1]
+        else:
+            a = (u - t[i]) / (t[i + p] - t[i])
+            Q[i] = a * Pw[i] + (1 - a) * Pw[i - 1]
+    t2 = np.insert(t, k + 1, u)
+    return t2, Q[:, :-1] / Q[:, -1:], Q[:, -1].copy()
+
+
+def nurbs_annulus_shell(ne1, ne2, q, angles_deg, mats, ply_mat, r0=0.6, r1=1.0, H=0.02, bump=0.15, name="",
+                        p2=1) -> Laminate:
+    """A quarter annulus (radii r0..r1, angle 0..pi/2) in the xy-plane as an
+    exact NURBS surface, degree 2 around (the standard quarter circle: weights
+    1, sqrt(2)/2, 1, refined by knot insertion) and degree p2 across, lifted
+    by z = bump * x * y at the control points and extruded along (0, 0, H)."""
+    p1 = 2
+    t1 = np.array([0, 0, 0, 1, 1, 1], dtype=np.float64)
+    arc = np.array([[1.0, 0.0], [1.0, 1.0], [0.0, 1.0]])
+    w1 = np.array([1.0, np.sqrt(0.5), 1.0])
+    for u in np.arange(1, ne1) / ne1:
+        t1, arc, w1 = _insert_knot(p1, t1, arc, w1, u)
+    k2 = open_uniform_knots(p2, ne2)
+    radii = r0 + (r1 - r0) * greville(p2, k2)
+    n1, n2 = len(w1), len(radii)
+    ctrl = np.zeros((n2, n1, 3))
+    for i2 in range(n2):
+        ctrl[i2, :, 0] = radii[i2] * arc[:, 0]
+        ctrl[i2, :, 1] = radii[i2] * arc[:, 1]
+    ctrl[:, :, 2] = bump * ctrl[:, :, 0] * ctrl[:, :, 1]
+    m = len(angles_deg)
+    iface = uniform_iface(m)
+    lam = Laminate(p1=p1, k1=t1, p2=p2, k2=k2, q=q, k3=layerwise_knots(q, iface), jac=box_jac(1.0, 1.0, H),
+                   iface=iface, ply_mat=np.asarray(ply_mat, dtype=np.int32), theta=deg(angles_deg),
+                   C=np.stack([np.asarray(c, dtype=np.float64) for c in mats]), name=name)
+    lam.ctrl = ctrl.reshape(-1, 3)
+    lam.weights = np.tile(w1, n2)
+    lam.a_ext = np.array([0.0, 0.0, H])
+    return lam
+
+
+def linear_material_field(lam: Laminate, C1: np.ndarray) -> Laminate:
+    """The laminate's materials varying linearly across the plane:
+    C_m(xi) = C_m + xi1 C1[m], given per in-plane function by the coefficient
+    at its Greville abscissa (B-splines reproduce linear functions)."""
+    import copy
+    out = copy.copy(lam)
+    g1 = greville(lam.p1, lam.k1)
+    gam = np.tile(g1, lam.n2)  # in-plane function order i1 + n1 * i2
+    C0 = np.asarray(lam.C, dtype=np.float64)
+    out.C = C0[:, None, :, :] + gam[None, :, None, None] * np.asarray(C1, dtype=np.float64)[:, None, :, :]
+    out.mat_field = True
+    out.name = lam.name + "_linear_field"
+    return out
+
+
+def smooth_material_field(lam: Laminate, rng: np.random.Generator, amp=0.3) -> Laminate:
+    """Seeded in-plane variation of every material: each in-plane function's
+    6x6 is the material's scaled by 1 + amp * (a smooth random function of
+    its Greville point), plus a small seeded symmetric perturbation."""
+    import copy
+    out = copy.copy(lam)
+    g1, g2 = greville(lam.p1, lam.k1), greville(lam.p2, lam.k2)
+    Y, X = np.meshgrid(g2, g1, indexing="ij")
+    C0 = np.asarray(lam.C, dtype=np.float64)
+    fields = []
+    for m in range(C0.shape[0]):
+        a, b, c = rng.uniform(0, 2 * np.pi, size=3)
+        f = 1.0 + amp * np.sin(2 * X + a) * np.cos(3 * Y + b) + 0.5 * amp * np.sin(X + Y + c)
+        E = rng.standard_normal((6, 6))
+        E = 0.02 * np.abs(C0[m]).max() * (E + E.T)
+        fields.append(f.ravel()[:, None, None] * C0[m][None] + np.sin(5 * X + c).ravel()[:, None, None] * E[None])
+    out.C = np.stack(fields)
+    out.mat_field = True
+    out.name = lam.name + "_field"
+    return out
+
+
+def shell_control_points(lam: Laminate) -> np.ndarray:
+    """Control points of the map x = F(xi) in global function order (i1
+    fastest, then i2, then i_t): ctrl_is + gamma_t a for a shell (B-splines in
+    the thickness reproduce xi3 by its Greville abscissae); for an affine
+    laminate, the control_points of DF xi."""
+    if lam.ctrl is None:
+        return control_points(lam)
+    g3 = greville(lam.q, lam.k3)
+    X = np.asarray(lam.ctrl, dtype=np.float64).reshape(-1, 3)
+    a = np.asarray(lam.a_ext, dtype=np.float64)
+    return (X[None, :, :] + g3[:, None, None] * a[None, None, :]).reshape(-1, 3)

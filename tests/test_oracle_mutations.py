@@ -20,14 +20,27 @@ MUTATIONS = {
     # clockwise instead of counterclockwise ply rotation
     "rotation_sign": ("double r[3][3] = {{c, -s, 0.0}, {s, c, 0.0}", "double r[3][3] = {{c, s, 0.0}, {-s, c, 0.0}"),
     # DF^{-1} instead of DF^{-T} in the pull-back
-    "pullback_transposed": ("grad[a][k] = c->Ji[0 * 3 + k] * gh[0] + c->Ji[1 * 3 + k] * gh[1] + c->Ji[2 * 3 + k] * gh[2];",
-                            "grad[a][k] = c->Ji[k * 3 + 0] * gh[0] + c->Ji[k * 3 + 1] * gh[1] + c->Ji[k * 3 + 2] * gh[2];"),
+    "pullback_transposed": ("grad[a][k] = Ji[0 * 3 + k] * gh[0] + Ji[1 * 3 + k] * gh[1] + Ji[2 * 3 + k] * gh[2];",
+                            "grad[a][k] = Ji[k * 3 + 0] * gh[0] + Ji[k * 3 + 1] * gh[1] + Ji[k * 3 + 2] * gh[2];"),
     # dropped Jacobian determinant
-    "dropped_jacobian": ("h1 * h2 * h3 * fabs(c->detJ);", "h1 * h2 * h3;"),
+    "dropped_jacobian": ("h1 * h2 * h3 * fabs(det);", "h1 * h2 * h3;"),
     # tensor shear convention: 13 and 23 swapped in the Voigt map
     "voigt_order": ("if (a == 0 && b == 2) return 4;\n  return 5;", "if (a == 0 && b == 2) return 5;\n  return 4;"),
     # whole instead of half interval length in the thickness Gauss map
     "z_map_length": ("h3 = 0.5 * (cl->zb - cl->za);", "h3 = (cl->zb - cl->za);"),
+}
+
+
+# mistakes in the curved-shell and material-field code, caught by the shell pins
+SHELL_MUTATIONS = {
+    # quotient rule of the NURBS derivative with the wrong sign
+    "nurbs_quotient_sign": ("dR1[b] = (w[b] * dR1[b] - r * W1) / W;", "dR1[b] = (w[b] * dR1[b] + r * W1) / W;"),
+    # the shell's map gradient assembled by rows instead of columns
+    "shell_map_gradient_transposed": ("J[3 * k + 0] = S1[k];\n    J[3 * k + 1] = S2[k];\n    J[3 * k + 2] = P->a[k];",
+                                      "J[k] = S1[k];\n    J[3 + k] = S2[k];\n    J[6 + k] = P->a[k];"),
+    # the material field averaged over the element instead of weighted by the basis
+    "material_field_unweighted": ("for (int e = 0; e < 36; ++e) Cx[e] += R[b] * Cc[e];",
+                                  "for (int e = 0; e < 36; ++e) Cx[e] += Cc[e] / ((p1 + 1) * (p2 + 1));"),
 }
 
 
@@ -85,3 +98,61 @@ def test_planted_mistake_is_caught(oracle, tmp_path, name):
     path = _build(tmp_path, name, old, new)
     with oracle.using_library(path):
         assert not _pins_pass(oracle), "mutation %s slipped through the pins" % name
+
+
+def _shell_pins_pass(o):
+    """Rigid modes on a NURBS shell, the patch energy on a curved B-spline
+    shell, the energy of a linear material field (test_oracle_shell.py)."""
+    rng = np.random.default_rng(98)
+    lam = W.nurbs_annulus_shell(3, 2, 2, [0, 45], [W.material(W.CARBON)], [0, 0])
+    rp, ci, v = o.assemble(lam)
+    K = o.to_scipy(rp, ci, v, lam.n_rows)
+    X = W.shell_control_points(lam)
+    nrm = np.linalg.norm(v)
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = 1
+        for r in (np.tile(e, (X.shape[0], 1)), np.cross(e[None, :], X)):
+            r = r.ravel() / np.linalg.norm(r)
+            if np.linalg.norm(K @ r) / nrm > 1e-13:
+                return False
+    lam = W.curved_shell(2, 3, 2, [35.0, 35.0], [W.random_anisotropic(rng)], [0, 0], ne2=2)
+    rp, ci, v = o.assemble(lam)
+    K = o.to_scipy(rp, ci, v, lam.n_rows)
+    A = rng.standard_normal((3, 3))
+    u = (W.shell_control_points(lam) @ A.T).ravel()
+    eps = np.array([A[0, 0], A[1, 1], A[2, 2], A[0, 1] + A[1, 0], A[0, 2] + A[2, 0], A[1, 2] + A[2, 1]])
+    E = math.fsum(u * (K @ u))
+    if abs(E - 0.02 * eps @ o.rotate(lam.C[0], lam.theta[0]) @ eps) > 1e-12 * abs(E):
+        return False
+    lam = W.plate(2, 3, 2, [0, 50], [W.material(W.CARBON)], [0, 0], ne2=2, H=0.1)
+    lam.k1 = np.array([0, 0, 0, 0.2, 0.7, 1, 1, 1], dtype=np.float64)  # nonuniform: the field's layout matters
+    C1 = 0.3 * W.random_anisotropic(rng)[None]
+    rp, ci, v = o.assemble(W.linear_material_field(lam, C1))
+    K = o.to_scipy(rp, ci, v, lam.n_rows)
+    u = (W.control_points(lam) @ A.T).ravel()
+    want = math.fsum(0.1 * 0.5 * eps @ o.rotate(lam.C[0] + 0.5 * C1[0], lam.theta[l]) @ eps for l in range(2))
+    if abs(math.fsum(u * (K @ u)) - want) > 1e-12 * abs(want):
+        return False
+    # u1 = x^2 / 2 (strain eps11 = x = xi1 on this unit box): energy
+    # sum_l V_l (D0_11 / 3 + D1_11 / 4) -- sensitive to where the field sits
+    t = lam.k1
+    m2 = np.array([t[i + 1] * t[i + 2] for i in range(lam.n1)])  # coefficients of xi^2 (degree 2 blossom)
+    u = np.zeros((lam.nt, lam.n2, lam.n1, 3))
+    u[..., 0] = 0.5 * m2[None, None, :]
+    u = u.ravel()
+    want = math.fsum(0.1 * 0.5 * (o.rotate(lam.C[0], lam.theta[l])[0, 0] / 3 + o.rotate(C1[0], lam.theta[l])[0, 0] / 4)
+                     for l in range(2))
+    return abs(math.fsum(u * (K @ u)) - want) <= 1e-12 * abs(want)
+
+
+def test_unmutated_oracle_passes_the_shell_pins(oracle):
+    assert _shell_pins_pass(oracle)
+
+
+@pytest.mark.parametrize("name", sorted(SHELL_MUTATIONS))
+def test_planted_shell_mistake_is_caught(oracle, tmp_path, name):
+    old, new = SHELL_MUTATIONS[name]
+    path = _build(tmp_path, name, old, new)
+    with oracle.using_library(path):
+        assert not _shell_pins_pass(oracle), "mutation %s slipped through the shell pins" % name
