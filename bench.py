@@ -19,7 +19,8 @@ buffers.  `cpu_baseline` times the CPU oracle (standard 3D Gauss assembly,
 layer by layer) on labelled slabs of the same plate, on all host threads and
 on one.  `extra` carries the standard 3D GPU assembly of the same plate and
 the other workloads (the 32-ply degree-2 plate with its matrix-free product
-and CG, the 64-ply adjoint plate, the 256-laminate batch).
+and CG, the 64-ply adjoint plate, curved B-spline and NURBS shells with and
+without in-plane material fields, the 256-laminate batch).
 """
 from __future__ import annotations
 
@@ -326,6 +327,47 @@ def _paper_sweep(torch, np, L, W, O, degrees, meshes, plies, layups, reps):
     return rows
 
 
+def _shell_workloads(torch, np, L, W, O, steps, warmup):
+    """Curved shells (Sec. 2.3, eq. extrusion) at the 64x64 32-ply size: a
+    curved B-spline mid-surface with constant ply materials (moments by 2D
+    Gauss sums with the per-point map gradient, then the register-mode
+    scatter), its standard assembly, and a NURBS quarter annulus whose two
+    materials vary over the plane (P of every set from the field, LDS-mode
+    scatter).  Sampled parity against the oracle for each."""
+    out = {}
+    cases = [("curved_bspline_p2_64x64_32ply",
+              W.curved_shell(2, 64, 2, [0, 90] * 16, [W.material(W.CARBON)], [0] * 32, name="curved_p2_64x64_32ply"),
+              True),
+             ("nurbs_annulus_field_p2_64x64_32ply",
+              W.smooth_material_field(W.nurbs_annulus_shell(64, 64, 2, [0, 45, -45, 90] * 8,
+                                                            [W.material(W.CARBON), W.material(W.GLASS)],
+                                                            [(l // 8) % 2 for l in range(32)], p2=2,
+                                                            name="annulus_p2_64x64_32ply"),
+                                      np.random.default_rng(8700)), False)]
+    for key, lam, std in cases:
+        lam.ng = (3, 3, 3)
+        plan = L.Plan(lam, set_mode="bucket")
+        rowptr, colind = plan.pattern()
+        del colind
+        C = torch.tensor(np.asarray(lam.C), device="cuda")
+        th = torch.tensor(np.asarray(lam.theta), device="cuda")
+        vals = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
+        ms, ms_k = _time_steps(torch, lambda: plan.assemble(C, th, out=vals), steps, warmup, L, "assemble")
+        rec = {"nnz": plan.nnz, "sets": plan.n_sets, "ms_per_step": ms, "nnz_per_s": plan.nnz / (ms * 1e-3),
+               "scatter_ms": ms_k, "scatter_hbm_frac": 8.0 * plan.nnz / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               "parity_sample_relF": _sample_parity(O, lam, plan, vals, rowptr, n_rows=100)}
+        plan.check()
+        if std:
+            ms_std, _ = _time_steps(torch, lambda: plan.assemble_standard(C, th, out=vals), 3, 1, L, "standard")
+            rec["standard"] = {"ms_per_step": ms_std, "speedup_fast_vs_standard": ms_std / ms,
+                               "parity_sample_relF": _sample_parity(O, lam, plan, vals, rowptr, n_rows=50)}
+        out[key] = rec
+        print("shell %s: %.3f ms" % (key, ms), file=sys.stderr, flush=True)
+        del vals, rowptr, plan
+        torch.cuda.empty_cache()
+    return out
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -559,6 +601,8 @@ def main():
         extra["p2_64x64_32ply"] = _c2_workload(torch, np, L, W, O, args)
     if not args.no_extra:
         extra["adjoint_p2_96x96_64ply"] = _adjoint_workload(torch, np, L, W, O, max(5, args.steps // 2), args.warmup)
+    if not args.no_extra:
+        extra["shells"] = _shell_workloads(torch, np, L, W, O, max(5, args.steps // 2), args.warmup)
     if not args.no_extra and not args.no_batch:
         extra["batch_256_uneven"] = _batch_workload(torch, np, L, W, O, args.batch_wave_gib, max(2, args.steps // 10))
     if args.paper_sweep:

@@ -19,7 +19,8 @@
  *    functions it (B-splines of degree q).  Global function i = it*ns + is,
  *    degree of freedom 3*i + r (r = displacement component x,y,z), eq. a_0.
  *  - Geometry (Assumption 2, eq. extrusion): x = DF xi with a constant 3x3 map
- *    gradient DF (an affine extrusion; a box plate is diag(Lx, Ly, H)).
+ *    gradient DF (an affine extrusion; a box plate is diag(Lx, Ly, H)), or a
+ *    curved mid-surface extruded along a vector (lam_plan_create_shell).
  *  - Plies (Sec. 2.3): ply l occupies xi3 in [iface[l], iface[l+1]],
  *    iface[0] = 0 < ... < iface[n_ply] = 1, ply 0 at the bottom.
  *  - Materials: 6x6 matrices in material axes, Voigt order
@@ -129,6 +130,34 @@ typedef struct {
 
 /* lam_plan_create with explicit scatter tuning (tuning may be NULL). */
 LAM_API lam_status lam_plan_create_tuned(const lam_laminate_desc *desc, const lam_tuning *tuning, lam_plan **out);
+
+/* Curved laminated shells (Sec. 2.3, Assumption 2, eq. extrusion;
+ * Assumption 3): the laminate's in-plane map is the extrusion of a
+ * mid-surface, F(xi) = S(xi1, xi2) + xi3 a, with S = sum_i R^i(xi1, xi2) ctrl_i
+ * over the in-plane basis of the descriptor (its knots and degrees).  Without
+ * weights R^i are the B-splines; with weights they are NURBS,
+ * R^i = w_i N^i / sum_k w_k N^k (Sec. 2.2), for the geometry and the
+ * displacement alike.  The map gradient DF = [dS/dxi1 | dS/dxi2 | a] varies
+ * over the plane but not through the thickness, which is what the split of
+ * Sec. 3 needs; desc.jac is not used.  Plies may also carry materials that
+ * vary over the plane: with mat_field set, C holds one 6x6 per material and
+ * in-plane function (n_mat * n1 * n2 matrices, material-major), and ply l uses
+ * C_{mat(l)}(xi) = sum_i R^i(xi) C_{mat(l), i} rotated by theta_l.
+ * Limits: material fields take BUCKET or PLY sets (LAM_EUNSUP otherwise), no
+ * adjoint, matrix-free product or standard assembly (LAM_EUNSUP); curved
+ * shells with constant materials support every entry point except the batch.
+ * lam_plan_create_shell returns LAM_EMAT for a non-finite control point,
+ * weight or extrusion vector, a weight <= 0 or a map gradient that is
+ * singular at an in-plane Gauss point. */
+typedef struct {
+  const double *ctrl;     /* n1*n2 control points (x, y, z), in-plane function order i1 + n1*i2 (host) */
+  const double *weights;  /* NULL (B-splines) or n1*n2 positive weights (NURBS) (host) */
+  double a[3];            /* extrusion vector */
+  int32_t mat_field;      /* 0: C holds n_mat 6x6; 1: n_mat*n1*n2 of them (one per in-plane function) */
+} lam_shell;
+
+LAM_API lam_status lam_plan_create_shell(const lam_laminate_desc *desc, const lam_shell *shell,
+                                         const lam_tuning *tuning, lam_plan **out);
 
 /* Sizes: rows of K (3*n), nonzeros, workspace bytes, number of sets, and the
  * number of plies and materials the device arrays must hold.  Any pointer may be NULL. */

@@ -53,6 +53,11 @@ struct Layout {
   // each), the distinct sets of each group (group_sptr, group_set) and each
   // chunk slot's index in its group's list (chunk_lset, parallel to chunk_set)
   Region tiles, chunk_ptr, chunk_sptr, chunk_set, zaslot, zchunk, group_ptr, group_sptr, group_set, chunk_lset;
+  // curved shells, per in-plane element e = e1 + ne1*e2 and Gauss point
+  // g = g1 + ng1*g2: gtab[e][g] = DF^{-T} (9, row-major) and the weight times
+  // |det DF| (Gauss weights and half lengths included); rtab[e][g][b][3] =
+  // (R, dR/dxi1, dR/dxi2) of local in-plane function b = b2*(p1+1) + b1
+  Region gtab, rtab;
   // status words, zero after the upload, set (never cleared) by kernels that
   // find inputs the plan cannot honour; read and cleared by lam_check
   Region status;
@@ -61,13 +66,17 @@ struct Layout {
   // mode, Eply only for harmonic plans evaluated per ply); the standard
   // assembly and the adjoint use the regions after it
   Region D, Ec, P, Qc, M, Eply, Qp, adj_part, adj_y, adj_dD;
+  // material fields (fast scratch): bracket coefficients per set and in-plane
+  // function, Ectl[s][is][81], and at every in-plane Gauss point, Epts[s][e][g][81]
+  Region Ectl, Epts;
   int64_t fwd_end = 0;
   int64_t total = 0;
 };
 
 // Host plan construction (plan.cpp); lam_plan_create uses no tuning and
 // min_nsc = 1.
-lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int min_nsc, lam_plan **out);
+lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int min_nsc, lam_plan **out,
+                       const lam_shell *shell = nullptr);
 
 // Kernel timing hooks (profile.cpp): a slot recorded around the dominant
 // kernel of entry point `which` (0 assemble, 1 standard, 2 adjoint).
@@ -93,6 +102,8 @@ struct lam_plan {
   int kron_nsc = 0;                 // register mode: set slots per thread (0: LDS mode)
   int kron_threads = 256;           // scatter block size
   int harm_ply = 0;                 // harmonic sets evaluated per ply (scatter sets are the plies)
+  int shell = 0;                    // curved extruded shell: per-point map gradients (gtab, rtab)
+  int mat_field = 0;                // materials vary over the plane (C per in-plane function)
   int64_t kron_lds_q = 0, kron_lds_p = 0;  // LDS bytes of the Q and P parts (output buffer follows)
   double jit[9] = {0};  // DF^{-T}, row-major
   double detj = 0.0;    // |det DF|

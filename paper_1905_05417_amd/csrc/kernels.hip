@@ -58,6 +58,11 @@ struct Dev {
   const int *rowply, *rowfin;
   double *Qp, *adj_part, *adj_y, *adj_dD;
   int *status;  // lam::N_STATUS flags, set by kernels, cleared by lam_check
+  // curved shells: per-point map gradients and in-plane basis (constant);
+  // material fields: set brackets per in-plane function and per point (scratch)
+  int shell, mat_field, ngp, nb;
+  const double *gtab, *rtab;
+  double *Ectl, *Epts;
   // scratch
   double *D, *Ec, *P, *Qc, *M;
 };
@@ -126,6 +131,14 @@ Dev make_dev(const lam_plan *p, void *ws, void *sbase = nullptr) {
   d.kron_nsc = p->kron_nsc;
   d.kron_lds_p = p->kron_lds_p;
   d.status = at<int>(ws, L.status);
+  d.shell = p->shell;
+  d.mat_field = p->mat_field;
+  d.ngp = p->ng1 * p->ng2;
+  d.nb = (p->p1 + 1) * (p->p2 + 1);
+  d.gtab = at<double>(ws, L.gtab);
+  d.rtab = at<double>(ws, L.rtab);
+  d.Ectl = at<double>(sb, L.Ectl);
+  d.Epts = at<double>(sb, L.Epts);
   d.D = at<double>(sb, L.D); d.Ec = at<double>(sb, L.Ec); d.P = at<double>(sb, L.P);
   d.Escat = p->harm_ply ? d.Eply : d.Ec;
   d.Qc = at<double>(sb, L.Qc); d.M = at<double>(sb, L.M);
@@ -335,9 +348,7 @@ __device__ __forceinline__ void moments_1d(const double *__restrict__ tab, const
 // pushed through DF^{-T} (grad V = DF^{-T}(dS1,dS2,0), W = DF^{-T}(0,0,S))
 // into M_ab[k][l] = int (G_a^i)_k (G_b^j)_l |DF|.  Because each set's
 // material is constant over the plane, P_{s,ab}[r][t] = sum_kl M_ab[k][l] E_s[k][l][r][t].
-__device__ __forceinline__ void p2d_one(const Dev &d, const double *__restrict__ Ec, double *__restrict__ Pt,
-                                        double *__restrict__ Mt, int64_t k, int write_p) {
-  if (k >= d.nnz2) return;
+__device__ __forceinline__ void affine_moments(const Dev &d, int64_t k, double (&M)[4][3][3]) {
   const int is = d.krow[k], js = d.kcol[k];
   const int i1 = is % d.n1, i2 = is / d.n1, j1 = js % d.n1, j2 = js / d.n1;
   const int2 ra = d.pe1[d.kp1[k]], rb = d.pe2[d.kp2[k]];
@@ -361,7 +372,6 @@ __device__ __forceinline__ void p2d_one(const Dev &d, const double *__restrict__
   m21[1] = u[0] * v[2];
   const double m22 = u[0] * v[0];
   // M_ab[k][l], ab = 11, 12, 21, 22
-  double M[4][3][3];
   const double *J = d.jit;
 #pragma unroll
   for (int kk = 0; kk < 3; ++kk)
@@ -380,6 +390,63 @@ __device__ __forceinline__ void p2d_one(const Dev &d, const double *__restrict__
       M[2][kk][ll] = d.detj * J[kk * 3 + 2] * v21;
       M[3][kk][ll] = d.detj * J[kk * 3 + 2] * J[ll * 3 + 2] * m22;
     }
+}
+
+// The same moments on a curved shell (Assumption 2 with a curved mid-surface,
+// eq. extrusion): DF^{-T} and |DF| change from point to point and the basis may
+// be rational, so the moments are plain 2D Gauss sums over the shared
+// elements, M_ab[k][l] = sum_e sum_g w |DF| (G_a^i)_k (G_b^j)_l with
+// G_1 = DF^{-T} (dR/dxi1, dR/dxi2, 0) and G_2 = DF^{-T} (0, 0, R) (eq. B_2).
+__device__ __forceinline__ void shell_moments(const Dev &d, int64_t k, double (&M)[4][3][3]) {
+  const int is = d.krow[k], js = d.kcol[k];
+  const int i1 = is % d.n1, i2 = is / d.n1, j1 = js % d.n1, j2 = js / d.n1;
+  const int2 ra = d.pe1[d.kp1[k]], rb = d.pe2[d.kp2[k]];
+  const int P1 = d.p1 + 1;
+#pragma unroll
+  for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+    for (int e = 0; e < 9; ++e) M[ab][e / 3][e % 3] = 0.0;
+  for (int e2 = rb.x; e2 < rb.x + rb.y; ++e2) {
+    const int f2 = d.e2first[e2];
+    for (int e1 = ra.x; e1 < ra.x + ra.y; ++e1) {
+      const int f1 = d.e1first[e1];
+      const int64_t e = e1 + (int64_t)d.ne1 * e2;
+      const int bi = (i2 - f2) * P1 + (i1 - f1), bj = (j2 - f2) * P1 + (j1 - f1);
+      for (int g = 0; g < d.ngp; ++g) {
+        const double *G = d.gtab + (e * d.ngp + g) * 10;
+        const double *ri = d.rtab + ((e * d.ngp + g) * d.nb + bi) * 3;
+        const double *rj = d.rtab + ((e * d.ngp + g) * d.nb + bj) * 3;
+        double vi[2][3], vj[2][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          vi[0][c] = G[c * 3] * ri[1] + G[c * 3 + 1] * ri[2];
+          vi[1][c] = G[c * 3 + 2] * ri[0];
+          vj[0][c] = G[c * 3] * rj[1] + G[c * 3 + 1] * rj[2];
+          vj[1][c] = G[c * 3 + 2] * rj[0];
+        }
+        const double w = G[9];
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+          for (int ll = 0; ll < 3; ++ll) {
+            M[0][kk][ll] += w * vi[0][kk] * vj[0][ll];
+            M[1][kk][ll] += w * vi[0][kk] * vj[1][ll];
+            M[2][kk][ll] += w * vi[1][kk] * vj[0][ll];
+            M[3][kk][ll] += w * vi[1][kk] * vj[1][ll];
+          }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void p2d_one(const Dev &d, const double *__restrict__ Ec, double *__restrict__ Pt,
+                                        double *__restrict__ Mt, int64_t k, int write_p) {
+  if (k >= d.nnz2) return;
+  double M[4][3][3];
+  if (d.shell)
+    shell_moments(d, k, M);
+  else
+    affine_moments(d, k, M);
   // component-major tables: consecutive threads (k) store consecutive addresses
 #pragma unroll
   for (int ab = 0; ab < 4; ++ab)
@@ -477,6 +544,112 @@ __global__ void __launch_bounds__(256) k_prep(Dev d, const double *__restrict__ 
     p2d_one(d, nullptr, nullptr, d.M, (int64_t)b * 256 + threadIdx.x, 0);
   else
     q1d_one(d, theta, (int64_t)(b - nb_m) * 256 + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Materials that vary over the plane (Assumption 3): C_m(xi) = sum_i R^i(xi) C_{m,i}.
+// The rotation by the set's angle and the bracket coefficients are linear in
+// C, so each set's coefficients at a Gauss point are the basis-weighted sum of
+// its coefficients at the in-plane functions; P of each set is the 2D Gauss
+// sum of eq. P with that point's coefficients inside.  Three launches:
+
+// per (set, in-plane function): Ectl[s][i] = brackets of T(theta_s) C_{m(s),i} T^T
+__global__ void __launch_bounds__(256) k_rotate_field(Dev d, const double *__restrict__ C,
+                                                      const double *__restrict__ theta) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)d.n_sets * d.ns) return;
+  const int s = (int)(idx / d.ns), c = (int)(idx % d.ns);
+  const double *Cm = C + 36 * ((int64_t)d.set_mat[s] * d.ns + c);
+  if (c == 0) check_set(d, Cm, theta, s);
+  const double th = theta[d.set_aux[s]];
+  double D[6][6];
+  rotate_c(Cm, cos(th), sin(th), D);
+  bracket_coefficients(D, d.Ectl + 81 * idx);
+}
+
+// per (set, in-plane element, Gauss point, coefficient j):
+// Epts[s][e][g][j] = sum_b R_b(e, g) Ectl[s][function b of e][j]
+__global__ void __launch_bounds__(256) k_field_points(Dev d) {
+  const int64_t npts = (int64_t)d.ne1 * d.ne2 * d.ngp;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 81 * npts * d.n_sets) return;
+  const int j = (int)(idx % 81);
+  const int64_t pt = idx / 81, s = pt / npts, rem = pt % npts;
+  const int64_t e = rem / d.ngp;
+  const int e1 = (int)(e % d.ne1), e2 = (int)(e / d.ne1), P1 = d.p1 + 1;
+  const int f1 = d.e1first[e1], f2 = d.e2first[e2];
+  const double *R = d.rtab + rem * d.nb * 3;
+  const double *Es = d.Ectl + 81 * s * d.ns;
+  double acc = 0.0;
+  for (int b = 0; b < d.nb; ++b) {
+    const int is = (f2 + b / P1) * d.n1 + f1 + b % P1;
+    acc += R[3 * b] * Es[81 * (int64_t)is + j];
+  }
+  d.Epts[81 * pt + j] = acc;
+}
+
+// per (in-plane nonzero k, set s), k fastest: P_s[k][ab][rt] =
+// sum_e sum_g w |DF| sum_kl (G_a^i)_k (G_b^j)_l Epts[s][e][g][kl][rt], stored
+// component-major for the LDS-mode scatter
+__global__ void __launch_bounds__(256) k_p2d_field(Dev d) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.nnz2 * d.n_sets) return;
+  const int64_t k = idx % d.nnz2, s = idx / d.nnz2;
+  const int is = d.krow[k], js = d.kcol[k];
+  const int i1 = is % d.n1, i2 = is / d.n1, j1 = js % d.n1, j2 = js / d.n1;
+  const int2 ra = d.pe1[d.kp1[k]], rb = d.pe2[d.kp2[k]];
+  const int P1 = d.p1 + 1;
+  const int64_t npts = (int64_t)d.ne1 * d.ne2 * d.ngp;
+  double P[4][9];
+#pragma unroll
+  for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+    for (int rt = 0; rt < 9; ++rt) P[ab][rt] = 0.0;
+  for (int e2 = rb.x; e2 < rb.x + rb.y; ++e2) {
+    const int f2 = d.e2first[e2];
+    for (int e1 = ra.x; e1 < ra.x + ra.y; ++e1) {
+      const int f1 = d.e1first[e1];
+      const int64_t e = e1 + (int64_t)d.ne1 * e2;
+      const int bi = (i2 - f2) * P1 + (i1 - f1), bj = (j2 - f2) * P1 + (j1 - f1);
+      for (int g = 0; g < d.ngp; ++g) {
+        const double *G = d.gtab + (e * d.ngp + g) * 10;
+        const double *ri = d.rtab + ((e * d.ngp + g) * d.nb + bi) * 3;
+        const double *rj = d.rtab + ((e * d.ngp + g) * d.nb + bj) * 3;
+        const double *E = d.Epts + 81 * (s * npts + e * d.ngp + g);
+        double vi[2][3], vj[2][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          vi[0][c] = G[c * 3] * ri[1] + G[c * 3 + 1] * ri[2];
+          vi[1][c] = G[c * 3 + 2] * ri[0];
+          vj[0][c] = G[c * 3] * rj[1] + G[c * 3 + 1] * rj[2];
+          vj[1][c] = G[c * 3 + 2] * rj[0];
+        }
+        const double w = G[9];
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+          for (int ll = 0; ll < 3; ++ll) {
+            const double *Ekl = E + 9 * (kk * 3 + ll);
+            double ek[9];
+#pragma unroll
+            for (int rt = 0; rt < 9; ++rt) ek[rt] = Ekl[rt];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+              for (int b = 0; b < 2; ++b) {
+                const double m = w * vi[a][kk] * vj[b][ll];
+#pragma unroll
+                for (int rt = 0; rt < 9; ++rt) P[2 * a + b][rt] += m * ek[rt];
+              }
+          }
+      }
+    }
+  }
+  double *Po = d.P + s * 36 * d.nnz2 + k;
+#pragma unroll
+  for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+    for (int rt = 0; rt < 9; ++rt) Po[(int64_t)(ab * 9 + rt) * d.nnz2] = P[ab][rt];
 }
 
 // ---------------------------------------------------------------------------
@@ -927,15 +1100,31 @@ __global__ void __launch_bounds__(STD_THREADS) k_std3d(Dev d, double *__restrict
         const int g = idx / nloc, a = idx - g * nloc;
         const int g1 = g % d.ng1, g2 = (g / d.ng1) % d.ng2, gz = g / (d.ng1 * d.ng2);
         const int a1 = a % P1, a2 = (a / P1) % P2, at = a / (P1 * P2);
-        const double *t1 = d.tab1 + (((int64_t)e1 * d.ng1 + g1) * P1 + a1) * 2;
-        const double *t2 = d.tab2 + (((int64_t)e2 * d.ng2 + g2) * P2 + a2) * 2;
         const double *t3 = d.ztab + (((int64_t)c * d.ngz + gz) * Q1 + at) * 2;
-        const double gh[3] = {t1[1] * t2[0] * t3[0], t1[0] * t2[1] * t3[0], t1[0] * t2[0] * t3[1]};
+        double gh[3];
+        const double *Jt;  // DF^{-T} at the point
+        double wpt;        // in-plane weight times |DF|
+        if (d.shell) {     // per-point map gradient and (possibly rational) in-plane basis
+          const int64_t ep = ((int64_t)e1 + (int64_t)d.ne1 * e2) * d.ngp + g1 + d.ng1 * g2;
+          const double *rt = d.rtab + (ep * d.nb + a1 + P1 * a2) * 3;
+          gh[0] = rt[1] * t3[0];
+          gh[1] = rt[2] * t3[0];
+          gh[2] = rt[0] * t3[1];
+          Jt = d.gtab + ep * 10;
+          wpt = Jt[9];
+        } else {
+          const double *t1 = d.tab1 + (((int64_t)e1 * d.ng1 + g1) * P1 + a1) * 2;
+          const double *t2 = d.tab2 + (((int64_t)e2 * d.ng2 + g2) * P2 + a2) * 2;
+          gh[0] = t1[1] * t2[0] * t3[0];
+          gh[1] = t1[0] * t2[1] * t3[0];
+          gh[2] = t1[0] * t2[0] * t3[1];
+          Jt = d.jit;
+          wpt = d.w1[(int64_t)e1 * d.ng1 + g1] * d.w2[(int64_t)e2 * d.ng2 + g2] * d.detj;
+        }
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-          G[(g * nloc + a) * 3 + k] = d.jit[k * 3 + 0] * gh[0] + d.jit[k * 3 + 1] * gh[1] + d.jit[k * 3 + 2] * gh[2];
-        if (a == 0)
-          W[g] = d.w1[(int64_t)e1 * d.ng1 + g1] * d.w2[(int64_t)e2 * d.ng2 + g2] * d.zw[(int64_t)c * d.ngz + gz] * d.detj;
+          G[(g * nloc + a) * 3 + k] = Jt[k * 3 + 0] * gh[0] + Jt[k * 3 + 1] * gh[1] + Jt[k * 3 + 2] * gh[2];
+        if (a == 0) W[g] = wpt * d.zw[(int64_t)c * d.ngz + gz];
       }
       __syncthreads();
       if (valid) {
@@ -1346,6 +1535,19 @@ void launch_assemble(const lam_plan *p, const Dev &d, const double *C, const dou
                      void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   int64_t nq = p->nnzz * (p->kron_nsc > 0 ? p->kron_nsc : p->maxact);
+  if (p->mat_field) {
+    // material fields: P of every set from the field at the Gauss points, LDS-mode scatter
+    const int64_t npts = (int64_t)p->ne1 * p->ne2 * p->ng1 * p->ng2;
+    hipLaunchKernelGGL(k_rotate_field, dim3((unsigned)(((int64_t)p->n_sets * p->ns + 255) / 256)), dim3(256), 0, s, d,
+                       C, theta);
+    hipLaunchKernelGGL(k_field_points, dim3((unsigned)((81 * npts * p->n_sets + 255) / 256)), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_p2d_field, dim3((unsigned)((p->nnz2 * p->n_sets + 255) / 256)), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_q1d, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, d, theta);
+    void *prof = lam::profile_begin(0, stream);
+    launch_kron(p, d, vals, s);
+    lam::profile_end(prof, stream);
+    return;
+  }
   hipLaunchKernelGGL(k_rotate, dim3((p->n_sets + 63) / 64), dim3(64), 0, s, d, C, theta);
   if (p->harm_ply) hipLaunchKernelGGL(k_harm_ply, dim3((p->n_ply + 63) / 64), dim3(64), 0, s, d, theta);
   if (p->kron_nsc > 0) {
@@ -1596,7 +1798,7 @@ extern "C" LAM_API lam_status lam_assemble_standard(const lam_plan *p, void *ws,
   const int P1 = p->p1 + 1, P2 = p->p2 + 1, Q1 = p->q + 1;
   const int nloc = P1 * P2 * Q1, ng = p->ng1 * p->ng2 * p->ngz;
   const size_t lds = sizeof(double) * ((size_t)ng * nloc * 3 + ng);
-  if (lds > 160 * 1024) return LAM_EUNSUP;
+  if (lds > 160 * 1024 || p->mat_field) return LAM_EUNSUP;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Dev d = make_dev(p, ws);
   void *prof = lam::profile_begin(1, stream);

@@ -211,7 +211,8 @@ namespace lam {
 
 // min_nsc: smallest number of set slots of the register-mode scatter (the
 // batched path compiles one slot count for every laminate).
-lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int min_nsc, lam_plan **out) {
+lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int min_nsc, lam_plan **out,
+                       const lam_shell *shell) {
   if (!d || !out) return LAM_EINVAL;
   *out = nullptr;
   lam_status st;
@@ -230,20 +231,34 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
   }
   int ng1 = d->ng1 ? d->ng1 : d->p1 + 1, ng2 = d->ng2 ? d->ng2 : d->p2 + 1, ngz = d->ngz ? d->ngz : d->q + 1;
   if (ng1 < 1 || ng1 > MAXG || ng2 < 1 || ng2 > MAXG || ngz < 1 || ngz > MAXG) return LAM_EUNSUP;
-  const double *J = d->jac;
-  for (int a = 0; a < 9; ++a)
-    if (!std::isfinite(J[a])) return LAM_EMAT;
-  double cof[9] = {J[4] * J[8] - J[5] * J[7], -(J[3] * J[8] - J[5] * J[6]), J[3] * J[7] - J[4] * J[6],
-                   -(J[1] * J[8] - J[2] * J[7]), J[0] * J[8] - J[2] * J[6], -(J[0] * J[7] - J[1] * J[6]),
-                   J[1] * J[5] - J[2] * J[4], -(J[0] * J[5] - J[2] * J[3]), J[0] * J[4] - J[1] * J[3]};
-  double det = J[0] * cof[0] + J[1] * cof[1] + J[2] * cof[2];
-  if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return LAM_EMAT;
+  if (shell) {
+    if (!shell->ctrl || (shell->mat_field != 0 && shell->mat_field != 1)) return LAM_EINVAL;
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(shell->a[a])) return LAM_EMAT;
+    // a material field is assembled per set from its own 2D integrals (no
+    // harmonic decomposition of a field)
+    if (shell->mat_field && d->set_mode != LAM_SETS_BUCKET && d->set_mode != LAM_SETS_PLY) return LAM_EUNSUP;
+  }
+  double cof[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, det = 1.0;
+  if (!shell) {
+    const double *J = d->jac;
+    for (int a = 0; a < 9; ++a)
+      if (!std::isfinite(J[a])) return LAM_EMAT;
+    double c9[9] = {J[4] * J[8] - J[5] * J[7], -(J[3] * J[8] - J[5] * J[6]), J[3] * J[7] - J[4] * J[6],
+                    -(J[1] * J[8] - J[2] * J[7]), J[0] * J[8] - J[2] * J[6], -(J[0] * J[7] - J[1] * J[6]),
+                    J[1] * J[5] - J[2] * J[4], -(J[0] * J[5] - J[2] * J[3]), J[0] * J[4] - J[1] * J[3]};
+    std::memcpy(cof, c9, sizeof(cof));
+    det = J[0] * cof[0] + J[1] * cof[1] + J[2] * cof[2];
+    if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return LAM_EMAT;
+  }
 
   lam_plan *P = new (std::nothrow) lam_plan();
   if (!P) return LAM_EINVAL;
-  // DF^{-1} = cof^T / det, so DF^{-T} = cof / det
+  // DF^{-1} = cof^T / det, so DF^{-T} = cof / det (a shell's vary per point: gtab)
   for (int a = 0; a < 9; ++a) P->jit[a] = cof[a] / det;
   P->detj = std::fabs(det);
+  P->shell = shell ? 1 : 0;
+  P->mat_field = shell ? shell->mat_field : 0;
   P->p1 = d->p1;
   P->p2 = d->p2;
   P->q = d->q;
@@ -263,6 +278,79 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
   P->ne1 = d1.ne;
   P->ne2 = d2.ne;
   P->ns = d1.n * d2.n;
+
+  // ---- curved shell: basis (B-spline products or NURBS quotients) and the
+  // map gradient DF = [dS/dxi1 | dS/dxi2 | a] at every in-plane Gauss point
+  std::vector<double> gtab, rtab;
+  if (shell) {
+    const int P1 = d->p1 + 1, P2 = d->p2 + 1, nb = P1 * P2, ngp = ng1 * ng2;
+    for (int i = 0; i < 3 * P->ns; ++i)
+      if (!std::isfinite(shell->ctrl[i])) {
+        delete P;
+        return LAM_EMAT;
+      }
+    if (shell->weights)
+      for (int i = 0; i < P->ns; ++i)
+        if (!std::isfinite(shell->weights[i]) || !(shell->weights[i] > 0.0)) {
+          delete P;
+          return LAM_EMAT;
+        }
+    gtab.assign((size_t)d1.ne * d2.ne * ngp * 10, 0.0);
+    rtab.assign((size_t)d1.ne * d2.ne * ngp * nb * 3, 0.0);
+    for (int e2 = 0; e2 < d2.ne; ++e2)
+      for (int e1 = 0; e1 < d1.ne; ++e1) {
+        const int e = e1 + d1.ne * e2, f1 = d1.span[e1] - d->p1, f2 = d2.span[e2] - d->p2;
+        for (int g2 = 0; g2 < ng2; ++g2)
+          for (int g1 = 0; g1 < ng1; ++g1) {
+            const int g = g1 + ng1 * g2;
+            double *rb = &rtab[((size_t)e * ngp + g) * nb * 3];
+            const double *t1 = &d1.tab[((size_t)e1 * ng1 + g1) * P1 * 2];
+            const double *t2 = &d2.tab[((size_t)e2 * ng2 + g2) * P2 * 2];
+            double W = 0.0, W1 = 0.0, W2 = 0.0;
+            for (int b2 = 0; b2 < P2; ++b2)
+              for (int b1 = 0; b1 < P1; ++b1) {
+                const int b = b2 * P1 + b1;
+                const double w = shell->weights ? shell->weights[(f2 + b2) * P->n1 + f1 + b1] : 1.0;
+                rb[3 * b + 0] = w * t1[2 * b1] * t2[2 * b2];
+                rb[3 * b + 1] = w * t1[2 * b1 + 1] * t2[2 * b2];
+                rb[3 * b + 2] = w * t1[2 * b1] * t2[2 * b2 + 1];
+                W += rb[3 * b];
+                W1 += rb[3 * b + 1];
+                W2 += rb[3 * b + 2];
+              }
+            if (shell->weights)  // R = w N / W; dR = (w dN - R dW) / W
+              for (int b = 0; b < nb; ++b) {
+                const double r = rb[3 * b] / W;
+                rb[3 * b + 1] = (rb[3 * b + 1] - r * W1) / W;
+                rb[3 * b + 2] = (rb[3 * b + 2] - r * W2) / W;
+                rb[3 * b] = r;
+              }
+            double Jm[9] = {0, 0, shell->a[0], 0, 0, shell->a[1], 0, 0, shell->a[2]};
+            for (int b2 = 0; b2 < P2; ++b2)
+              for (int b1 = 0; b1 < P1; ++b1) {
+                const int b = b2 * P1 + b1;
+                const double *X = shell->ctrl + 3 * (size_t)((f2 + b2) * P->n1 + f1 + b1);
+                for (int r = 0; r < 3; ++r) {
+                  Jm[3 * r + 0] += rb[3 * b + 1] * X[r];
+                  Jm[3 * r + 1] += rb[3 * b + 2] * X[r];
+                }
+              }
+            const double c9[9] = {Jm[4] * Jm[8] - Jm[5] * Jm[7], -(Jm[3] * Jm[8] - Jm[5] * Jm[6]),
+                                  Jm[3] * Jm[7] - Jm[4] * Jm[6], -(Jm[1] * Jm[8] - Jm[2] * Jm[7]),
+                                  Jm[0] * Jm[8] - Jm[2] * Jm[6], -(Jm[0] * Jm[7] - Jm[1] * Jm[6]),
+                                  Jm[1] * Jm[5] - Jm[2] * Jm[4], -(Jm[0] * Jm[5] - Jm[2] * Jm[3]),
+                                  Jm[0] * Jm[4] - Jm[1] * Jm[3]};
+            const double dt = Jm[0] * c9[0] + Jm[1] * c9[1] + Jm[2] * c9[2];
+            if (!(std::fabs(dt) > 0.0) || !std::isfinite(dt)) {
+              delete P;
+              return LAM_EMAT;
+            }
+            double *gb = &gtab[((size_t)e * ngp + g) * 10];
+            for (int a = 0; a < 9; ++a) gb[a] = c9[a] / dt;
+            gb[9] = d1.w[(size_t)e1 * ng1 + g1] * d2.w[(size_t)e2 * ng2 + g2] * std::fabs(dt);
+          }
+      }
+  }
 
   // ---- thickness: cells = (ply, nonzero knot span) intersections, bottom to top
   Dir zs;
@@ -455,7 +543,9 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
   }
   int nsc_cap = 2;  // fewer slots keep more waves resident; chunks reload P from cache
   if (tune && tune->set_slots > 0) nsc_cap = tune->set_slots;
-  const bool reg_mode = P->maxact <= 8;
+  // material fields: P of every set is integrated over the plane with the
+  // field inside, stored, and read by the LDS-mode scatter
+  const bool reg_mode = P->maxact <= 8 && !P->mat_field;
   int sc, tkmax = tk_target;
   int64_t qbudget = 8 * 1024, lds_budget = 80 * 1024;
   if (tune && tune->lds_kib > 0) lds_budget = std::max<int64_t>(16 * 1024, (int64_t)tune->lds_kib * 1024);
@@ -691,6 +781,7 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
     }
   }
 
+  if (P->mat_field) P->adj_ok = 0;  // the adjoint's per-ply 6x6 gradient does not describe a field
   std::vector<int> plymat(d->ply_mat, d->ply_mat + d->n_ply);
 
   // ---- layout
@@ -743,6 +834,8 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
   L.chunk_sptr = B.take(sizeof(int) * chunk_sptr.size());
   L.chunk_set = B.take(sizeof(int) * chunk_set.size());
   L.zaslot = B.take(sizeof(int) * zaslot.size());
+  L.gtab = B.take(sizeof(double) * gtab.size());
+  L.rtab = B.take(sizeof(double) * rtab.size());
   L.status = B.take(sizeof(int) * lam::N_STATUS);
   L.const_bytes = B.cur;
   L.D = B.take(sizeof(double) * 36 * P->n_sets);
@@ -753,6 +846,8 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
   L.Qc = B.take(sizeof(double) * 4 * (int64_t)std::max(P->maxact, P->kron_nsc) * P->nnzz);
   L.M = B.take(sizeof(double) * 36 * P->nnz2);
   L.Eply = B.take(sizeof(double) * 81 * P->n_ply);
+  L.Ectl = B.take(P->mat_field ? sizeof(double) * 81 * (int64_t)P->n_sets * P->ns : 0);
+  L.Epts = B.take(P->mat_field ? sizeof(double) * 81 * (int64_t)P->n_sets * P->ne1 * P->ne2 * ng1 * ng2 : 0);
   L.fwd_end = B.cur;  // scratch of the fast assembly ends here
   // adjoint scratch: per-ply 1D operators by slot (padded per thickness row), per (ply, tile) partial sums,
   // per-ply totals and dL/dD_l
@@ -829,6 +924,8 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
   put(img, L.chunk_sptr, chunk_sptr);
   put(img, L.chunk_set, chunk_set);
   put(img, L.zaslot, zaslot);
+  put(img, L.gtab, gtab);
+  put(img, L.rtab, rtab);
   *out = P;
   return LAM_OK;
 }
@@ -847,6 +944,17 @@ extern "C" LAM_API lam_status lam_plan_create_tuned(const lam_laminate_desc *d, 
                   tuning->set_slots != 4 && tuning->set_slots != 8)))
     return LAM_EINVAL;
   return lam::plan_create(d, tuning, 1, out);
+}
+
+extern "C" LAM_API lam_status lam_plan_create_shell(const lam_laminate_desc *d, const lam_shell *shell,
+                                                   const lam_tuning *tuning, lam_plan **out) {
+  if (!shell) return LAM_EINVAL;
+  if (tuning && (tuning->tile_k < 0 || tuning->tile_k > 85 || tuning->target_blocks < 0 || tuning->lds_kib < 0 ||
+                 tuning->lds_kib > 160 ||
+                 (tuning->set_slots != 0 && tuning->set_slots != 1 && tuning->set_slots != 2 &&
+                  tuning->set_slots != 4 && tuning->set_slots != 8)))
+    return LAM_EINVAL;
+  return lam::plan_create(d, tuning, 1, out, shell);
 }
 
 extern "C" LAM_API void lam_plan_destroy(lam_plan *p) { delete p; }

@@ -43,6 +43,29 @@ class _Desc(ctypes.Structure):
     ]
 
 
+class _Shell(ctypes.Structure):
+    _fields_ = [("ctrl", _dp), ("weights", _dp), ("a", ctypes.c_double * 3), ("mat_field", ctypes.c_int32)]
+
+
+def _make_shell(lam):
+    """lam_shell for a curved laminate (None for an affine one) and the arrays it points into."""
+    if getattr(lam, "ctrl", None) is None:
+        return None, []
+    ctrl = np.ascontiguousarray(np.asarray(lam.ctrl, dtype=np.float64).reshape(-1))
+    keep = [ctrl]
+    sh = _Shell()
+    sh.ctrl = ctrl.ctypes.data_as(_dp)
+    if getattr(lam, "weights", None) is not None:
+        w = np.ascontiguousarray(np.asarray(lam.weights, dtype=np.float64).reshape(-1))
+        keep.append(w)
+        sh.weights = w.ctypes.data_as(_dp)
+    a = np.asarray(lam.a_ext, dtype=np.float64).reshape(3)
+    for k in range(3):
+        sh.a[k] = float(a[k])
+    sh.mat_field = 1 if getattr(lam, "mat_field", False) else 0
+    return sh, keep
+
+
 class _Tuning(ctypes.Structure):
     _fields_ = [("tile_k", ctypes.c_int32), ("set_slots", ctypes.c_int32), ("target_blocks", ctypes.c_int32),
                 ("lds_kib", ctypes.c_int32)]
@@ -60,7 +83,7 @@ def _make_tuning(t):
 
 _lib = None
 
-EXPORTED = ("lam_plan_create", "lam_plan_create_tuned", "lam_plan_destroy", "lam_plan_info", "lam_plan_upload", "lam_check",
+EXPORTED = ("lam_plan_create", "lam_plan_create_tuned", "lam_plan_create_shell", "lam_plan_destroy", "lam_plan_info", "lam_plan_upload", "lam_check",
             "lam_pattern",
             "lam_assemble", "lam_assemble_static", "lam_assemble_standard", "lam_apply", "lam_cg", "lam_cg_work_bytes", "lam_adjoint", "lam_adjoint_rank1",
             "lam_batch_create", "lam_batch_create_tuned", "lam_batch_destroy", "lam_batch_info", "lam_batch_laminate", "lam_batch_upload",
@@ -80,6 +103,8 @@ def lib():
         L.lam_plan_create_tuned.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(_Tuning), ctypes.POINTER(vp)]
         L.lam_batch_create_tuned.argtypes = [ctypes.c_int32, ctypes.POINTER(_Desc), ctypes.POINTER(_Tuning), i64,
                                              ctypes.POINTER(vp)]
+        L.lam_plan_create_shell.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(_Shell), ctypes.POINTER(_Tuning),
+                                            ctypes.POINTER(vp)]
         L.lam_plan_destroy.argtypes = [vp]
         L.lam_plan_destroy.restype = None
         L.lam_plan_info.argtypes = [vp, i64p, i64p, i64p, _i32p, _i32p, _i32p]
@@ -181,8 +206,16 @@ class Plan:
         self._desc = d
         h = ctypes.c_void_p()
         t = _make_tuning(tuning)
-        _check(lib().lam_plan_create_tuned(ctypes.byref(d), ctypes.byref(t) if t is not None else None,
-                                           ctypes.byref(h)), "lam_plan_create")
+        sh, keep_sh = _make_shell(lam)
+        self._keep += keep_sh
+        self.mat_field = bool(sh is not None and sh.mat_field)
+        if sh is None:
+            _check(lib().lam_plan_create_tuned(ctypes.byref(d), ctypes.byref(t) if t is not None else None,
+                                               ctypes.byref(h)), "lam_plan_create")
+        else:
+            _check(lib().lam_plan_create_shell(ctypes.byref(d), ctypes.byref(sh),
+                                               ctypes.byref(t) if t is not None else None, ctypes.byref(h)),
+                   "lam_plan_create_shell")
         self._h = h
         nr, nz, wb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         ns, npl, nm = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
@@ -210,8 +243,9 @@ class Plan:
     def _inputs(self, C, theta):
         C = torch.as_tensor(C, dtype=torch.float64, device=self.device).contiguous()
         theta = torch.as_tensor(theta, dtype=torch.float64, device=self.device).contiguous()
-        if C.numel() != 36 * self.n_mat or theta.numel() != self.n_ply:
-            raise ValueError("C must hold n_mat*36 values and theta n_ply values")
+        per = self.lam.n1 * self.lam.n2 if self.mat_field else 1
+        if C.numel() != 36 * self.n_mat * per or theta.numel() != self.n_ply:
+            raise ValueError("C must hold n_mat*36 values (times n1*n2 for a material field) and theta n_ply values")
         return C, theta
 
     def check(self):
