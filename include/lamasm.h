@@ -251,9 +251,14 @@ LAM_API lam_status lam_apply(const lam_plan *plan, void *ws, int64_t ws_bytes, c
  * solves (P K P + I - P) x = P b (fixed as for lam_apply, NULL for none, then
  * K itself must be nonsingular on the data), starting from the x given
  * (device, n_rows doubles, overwritten), until ||r|| <= tol ||P b|| or
- * max_iter iterations.  Every product is lam_apply's; vector updates and dot
- * products are kernels of their own with device-side scalars.  work: device,
- * at least lam_cg_work_bytes(plan) bytes, 8-byte aligned.  Unlike the other
+ * max_iter iterations, preconditioned by thickness lines: for every in-plane
+ * function, the operator's block coupling all its thickness functions and
+ * displacement components (banded, half bandwidth 3q + 2), taken from the
+ * split of Sec. 3 at the in-plane diagonal (the 1D integrals times the
+ * diagonal's 2D ones) and factored once by a banded Cholesky.  Every
+ * product is lam_apply's; vector updates and dot products are kernels of
+ * their own with device-side scalars.  work: device, at least
+ * lam_cg_work_bytes(plan) bytes, 8-byte aligned.  Unlike the other
  * entry points it waits on the stream, after every 8 iterations (to test the
  * residual), so up to 7 iterations may run past the tolerance; *iters and
  * *rel_res (host) receive the iteration count and the final relative

@@ -240,14 +240,13 @@ constexpr int NH = 12;
 //  - harmonic5 sets: a material with a nonzero {11,22,33,12}-{13,23} entry
 //    (relative to its largest entry, above 1e-13), whose rotation has odd
 //    harmonics that five terms do not hold (Remark on orientations).
-__device__ __forceinline__ void check_set(const Dev &d, const double *__restrict__ Cm,
-                                          const double *__restrict__ theta, int s) {
-  if (d.set_mode == LAM_SETS_BUCKET) {
-    const double th = theta[d.set_aux[s]];
-    bool bad = false;
-    for (int l = 0; l < d.n_ply; ++l) bad |= d.ply_set[l] == s && !(theta[l] == th);
-    if (bad) d.status[0] = 1;
-  } else if (d.n_harm == 5 && d.set_aux[s] == 0) {
+// (the bucket check runs per ply, check_ply; the harmonic5 one per material)
+__device__ __forceinline__ void check_ply(const Dev &d, const double *__restrict__ theta, int l) {
+  if (d.set_mode == LAM_SETS_BUCKET && l < d.n_ply && !(theta[l] == theta[d.set_aux[d.ply_set[l]]])) d.status[0] = 1;
+}
+
+__device__ __forceinline__ void check_set(const Dev &d, const double *__restrict__ Cm, int s) {
+  if (d.set_mode != LAM_SETS_BUCKET && d.n_harm == 5 && d.set_aux[s] == 0) {
     double big = 0.0, cpl = 0.0;
     for (int e = 0; e < 36; ++e) big = fmax(big, fabs(Cm[e]));
     for (int I = 0; I < 4; ++I)
@@ -260,7 +259,7 @@ __device__ __forceinline__ void rotate_one(const Dev &d, const double *__restric
                                            int s) {
   if (s >= d.n_sets) return;
   const double *Cm = C + 36 * d.set_mat[s];
-  check_set(d, Cm, theta, s);
+  check_set(d, Cm, s);
   double D[6][6];
   if (d.set_mode == LAM_SETS_BUCKET) {
     double th = theta[d.set_aux[s]];
@@ -284,8 +283,11 @@ __device__ __forceinline__ void rotate_one(const Dev &d, const double *__restric
   bracket_coefficients(D, d.Ec + 81 * s);
 }
 
+// One thread per set (rotation) and per ply (its bucket check): the grid covers both.
 __global__ void __launch_bounds__(64) k_rotate(Dev d, const double *__restrict__ C, const double *__restrict__ theta) {
-  rotate_one(d, C, theta, blockIdx.x * blockDim.x + threadIdx.x);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  check_ply(d, theta, t);
+  rotate_one(d, C, theta, t);
 }
 
 // Standard assembly: every ply's rotated tensor as bracket coefficients.
@@ -478,11 +480,15 @@ __global__ void __launch_bounds__(256) k_p2d(Dev d, const double *__restrict__ E
 //   Qc[zk][j][ab] = sum_{cells c shared by it, jt} w_{s,ply(c)} sum_g w_g tau_a^{it} tau_b^{jt}
 // with tau_1 = T, tau_2 = dT/dxi3, a on the test function it, and
 // w_{s,l} = [set of l == s] (bucket) or [mat(l) == mat(s)] * harmonic_s(theta_l).
-__device__ __forceinline__ void q1d_one(const Dev &d, const double *__restrict__ theta, int64_t idx) {
+// One wave per entry (thickness nonzero zk, set slot j): the lanes split the
+// cells the pair shares (with one thickness element through many plies every
+// ply is such a cell, so a single thread would sum m (q+1) terms in turn) and
+// a fixed butterfly over the wave adds the lanes' sums (deterministic).
+__device__ __forceinline__ void q1d_wave(const Dev &d, const double *__restrict__ theta, int64_t idx, int lane) {
   // register mode: one entry per chunk set slot (zeros where the slot's set
   // does not act on the pair); LDS mode: one per set active on the row
   const int width = d.kron_nsc > 0 ? d.kron_nsc : d.maxact;
-  if (idx >= d.nnzz * width) return;
+  if (idx >= d.nnzz * width) return;  // uniform over the wave
   const int zk = (int)(idx / width), j = (int)(idx % width);
   const int it = d.zkrow[zk], jt = d.zcol[zk];
   int s = -1;
@@ -496,7 +502,7 @@ __device__ __forceinline__ void q1d_one(const Dev &d, const double *__restrict__
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (s >= 0) {
     const int Q1 = d.q + 1;
-    for (int ci = d.zcptr[zk]; ci < d.zcptr[zk + 1]; ++ci) {
+    for (int ci = d.zcptr[zk] + lane; ci < d.zcptr[zk + 1]; ci += 64) {
       const int c = d.zcell[ci], l = d.zply[c];
       double wgt;
       if (d.harm_ply) {
@@ -524,26 +530,34 @@ __device__ __forceinline__ void q1d_one(const Dev &d, const double *__restrict__
       acc[3] += wgt * q22;
     }
   }
-  double *o = d.Qc + 4 * idx;
-  o[0] = acc[0];
-  o[1] = acc[1];
-  o[2] = acc[2];
-  o[3] = acc[3];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[e] += __shfl_xor(acc[e], off, 64);
+  if (lane == 0) {
+    double *o = d.Qc + 4 * idx;
+    o[0] = acc[0];
+    o[1] = acc[1];
+    o[2] = acc[2];
+    o[3] = acc[3];
+  }
 }
 
-__global__ void k_q1d(Dev d, const double *__restrict__ theta) {
-  q1d_one(d, theta, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+// four entries per 256-thread block, one per wave
+__global__ void __launch_bounds__(256) k_q1d(Dev d, const double *__restrict__ theta) {
+  q1d_wave(d, theta, (int64_t)blockIdx.x * 4 + threadIdx.x / 64, threadIdx.x & 63);
 }
 
 // Register mode: the 2D moments and the folded 1D coefficients do not depend
 // on each other or on the set tensors, so one launch computes both (blocks
-// [0, nb_m): moments, the rest: 1D coefficients).
+// [0, nb_m): moments, a thread per in-plane nonzero; the rest: 1D
+// coefficients, a wave per entry).
 __global__ void __launch_bounds__(256) k_prep(Dev d, const double *__restrict__ theta, int nb_m) {
   const int b = blockIdx.x;
   if (b < nb_m)
     p2d_one(d, nullptr, nullptr, d.M, (int64_t)b * 256 + threadIdx.x, 0);
   else
-    q1d_one(d, theta, (int64_t)(b - nb_m) * 256 + threadIdx.x);
+    q1d_wave(d, theta, (int64_t)(b - nb_m) * 4 + threadIdx.x / 64, threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------------------
@@ -560,7 +574,7 @@ __global__ void __launch_bounds__(256) k_rotate_field(Dev d, const double *__res
   if (idx >= (int64_t)d.n_sets * d.ns) return;
   const int s = (int)(idx / d.ns), c = (int)(idx % d.ns);
   const double *Cm = C + 36 * ((int64_t)d.set_mat[s] * d.ns + c);
-  if (c == 0) check_set(d, Cm, theta, s);
+  if (idx < d.n_ply) check_ply(d, theta, (int)idx);
   const double th = theta[d.set_aux[s]];
   double D[6][6];
   rotate_c(Cm, cos(th), sin(th), D);
@@ -1542,23 +1556,23 @@ void launch_assemble(const lam_plan *p, const Dev &d, const double *C, const dou
                        C, theta);
     hipLaunchKernelGGL(k_field_points, dim3((unsigned)((81 * npts * p->n_sets + 255) / 256)), dim3(256), 0, s, d);
     hipLaunchKernelGGL(k_p2d_field, dim3((unsigned)((p->nnz2 * p->n_sets + 255) / 256)), dim3(256), 0, s, d);
-    hipLaunchKernelGGL(k_q1d, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, d, theta);
+    hipLaunchKernelGGL(k_q1d, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, d, theta);
     void *prof = lam::profile_begin(0, stream);
     launch_kron(p, d, vals, s);
     lam::profile_end(prof, stream);
     return;
   }
-  hipLaunchKernelGGL(k_rotate, dim3((p->n_sets + 63) / 64), dim3(64), 0, s, d, C, theta);
+  hipLaunchKernelGGL(k_rotate, dim3((std::max(p->n_sets, p->n_ply) + 63) / 64), dim3(64), 0, s, d, C, theta);
   if (p->harm_ply) hipLaunchKernelGGL(k_harm_ply, dim3((p->n_ply + 63) / 64), dim3(64), 0, s, d, theta);
   if (p->kron_nsc > 0) {
     // register-mode scatter contracts P itself from the moments: one launch
     // for the moments and the 1D coefficients
-    const int nb_m = (int)((p->nnz2 + 255) / 256), nb_q = (int)((nq + 255) / 256);
+    const int nb_m = (int)((p->nnz2 + 255) / 256), nb_q = (int)((nq + 3) / 4);
     hipLaunchKernelGGL(k_prep, dim3((unsigned)(nb_m + nb_q)), dim3(256), 0, s, d, theta, nb_m);
   } else {
     // LDS mode reads P, which needs the set tensors
     hipLaunchKernelGGL(k_p2d, dim3((unsigned)((p->nnz2 + 255) / 256)), dim3(256), 0, s, d, d.Ec, d.P, d.M, 1);
-    hipLaunchKernelGGL(k_q1d, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, d, theta);
+    hipLaunchKernelGGL(k_q1d, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, d, theta);
   }
   void *prof = lam::profile_begin(0, stream);
   launch_kron(p, d, vals, s);
@@ -1623,8 +1637,8 @@ namespace {
 // scatter and the matrix-free product read.
 void launch_prep(const lam_plan *p, const Dev &d, const double *C, const double *theta, hipStream_t s) {
   const int64_t nq = p->nnzz * p->kron_nsc;
-  const int nb_m = (int)((p->nnz2 + 255) / 256), nb_q = (int)((nq + 255) / 256);
-  hipLaunchKernelGGL(k_rotate, dim3((p->n_sets + 63) / 64), dim3(64), 0, s, d, C, theta);
+  const int nb_m = (int)((p->nnz2 + 255) / 256), nb_q = (int)((nq + 3) / 4);
+  hipLaunchKernelGGL(k_rotate, dim3((std::max(p->n_sets, p->n_ply) + 63) / 64), dim3(64), 0, s, d, C, theta);
   if (p->harm_ply) hipLaunchKernelGGL(k_harm_ply, dim3((p->n_ply + 63) / 64), dim3(64), 0, s, d, theta);
   hipLaunchKernelGGL(k_prep, dim3((unsigned)(nb_m + nb_q)), dim3(256), 0, s, d, theta, nb_m);
 }
@@ -1660,53 +1674,209 @@ extern "C" LAM_API lam_status lam_apply(const lam_plan *p, void *ws, int64_t ws_
 // ---------------------------------------------------------------------------
 // Conjugate gradients on the Dirichlet-eliminated operator A = P K P + (I - P)
 // (P: projection on the free rows) with right-hand side P b, so the fixed
-// entries of the solution go to zero: every vector operation is a kernel,
-// the scalars stay on the device, the dot products are two-stage fixed-order
-// sums (deterministic).  work (doubles): r, p, q = A p (n each), CG_PARTS
-// partial sums, 4 scalars {r.r, p.q, new r.r, P b . P b}.
+// entries of the solution go to zero, preconditioned by thickness lines: for
+// every in-plane function is, the block of A that couples all thickness
+// functions and displacement components of is (3 nt unknowns, banded with
+// half bandwidth 3q + 2), factored once by a banded Cholesky and solved at
+// every iteration.  In a thin laminate the coupling through the thickness is
+// the stiff one (plies much thinner than the in-plane elements), which a
+// pointwise preconditioner leaves untouched.  Every vector operation is a
+// kernel, the scalars stay on the device, the dot products are two-stage
+// fixed-order sums (deterministic).  work (doubles): r, p, q = A p,
+// z = M^{-1} r (n each), the line factors (ns * 3 nt * (3q + 3)), 2 CG_PARTS
+// partial sums, 6 scalars {r.z, p.q, new r.z, P b . P b, r.r, spare}.
 constexpr int CG_PARTS = 512;
 // iterations between two host reads of the residual (each read waits for the
 // stream); up to CG_CHECK - 1 iterations may run past the tolerance
 constexpr int CG_CHECK = 8;
 
+// Thickness line of in-plane function is: A's entries between (it, r) and
+// (jt, t), from the split (eq. Km_2) at the in-plane diagonal nonzero k_d of
+// is: sum over row it's set slots u and ab of Qc[(it, jt)][u][ab] P_u[k_d][ab][r][t],
+// P_u = sum_kl M_ab[kl][k_d] E_u[kl] (the register-mode scatter's moments and
+// brackets).  Fixed components take a unit row and column.  The lower band
+// (row i = 3 it + r, column i - c for c = 0..3q+2) is stored at
+// fac[(i (3q + 3) + c) ns + is] (consecutive lines on consecutive addresses)
+// and overwritten by its Cholesky factor.  One thread per line.
+template <int NSC>
+__global__ void __launch_bounds__(256) k_cg_lines(Dev d, const double *__restrict__ qd,
+                                                  const uint8_t *__restrict__ fixed, double *__restrict__ fac) {
+  const int is = blockIdx.x * blockDim.x + threadIdx.x;
+  if (is >= d.ns) return;
+  const int hb = 3 * d.q + 2, wb = hb + 1, n = 3 * d.nt;
+  const int64_t ns = d.ns;
+  const int i1 = is % d.n1, i2 = is / d.n1;
+  const int64_t k = d.srow[is] + (int64_t)(i2 - d.a2f[i2]) * d.a1c[i1] + (i1 - d.a1f[i1]);
+  double mv[4][9];
+#pragma unroll
+  for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+    for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[(int64_t)(ab * 9 + kl) * d.nnz2 + k];
+  for (int64_t e = 0; e < (int64_t)n * wb; ++e) fac[e * ns + is] = 0.0;
+  for (int it = 0; it < d.nt; ++it) {
+    const int ch = d.zchunk[it], c0 = d.chunk_sptr[ch], nsc = d.chunk_sptr[ch + 1] - c0;
+    double pu[NSC][4][9];  // P of the row's slots at the diagonal in-plane nonzero
+#pragma unroll
+    for (int u = 0; u < NSC; ++u) {
+      const double *E = d.Escat + 81 * (int64_t)(u < nsc ? d.chunk_set[c0 + u] : d.chunk_set[c0]);
+#pragma unroll
+      for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+        for (int rt = 0; rt < 9; ++rt) {
+          double a = 0.0;
+#pragma unroll
+          for (int kl = 0; kl < 9; ++kl) a += mv[ab][kl] * E[kl * 9 + rt];
+          pu[u][ab][rt] = u < nsc ? a : 0.0;
+        }
+    }
+    const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
+    for (int x = 0; x < Lz; ++x) {
+      const int jt = d.zcol[zb + x];
+      if (jt > it) break;  // columns ascend: the rest is above the diagonal
+      const double *q = qd + 4 * ((int64_t)(zb + x) * NSC);
+      for (int r = 0; r < 3; ++r)
+        for (int t = 0; t < 3; ++t) {
+          const int i = 3 * it + r, j = 3 * jt + t;
+          if (j > i) continue;
+          double v = 0.0;
+#pragma unroll
+          for (int u = 0; u < NSC; ++u)
+#pragma unroll
+            for (int ab = 0; ab < 4; ++ab) v += q[4 * u + ab] * pu[u][ab][3 * r + t];
+          const int64_t gi = 3 * ((int64_t)it * ns + is) + r, gj = 3 * ((int64_t)jt * ns + is) + t;
+          if (fixed && (fixed[gi] || fixed[gj])) v = (i == j) ? 1.0 : 0.0;
+          fac[((int64_t)i * wb + (i - j)) * ns + is] = v;
+        }
+    }
+  }
+  // banded Cholesky in place: L[i][j] at band column i - j
+  for (int i = 0; i < n; ++i) {
+    const int j0 = i - hb > 0 ? i - hb : 0;
+    for (int j = j0; j <= i; ++j) {
+      double sum = fac[((int64_t)i * wb + (i - j)) * ns + is];
+      const int p0 = (i - hb > j - hb ? i - hb : j - hb) > 0 ? (i - hb > j - hb ? i - hb : j - hb) : 0;
+      for (int pp = p0; pp < j; ++pp)
+        sum -= fac[((int64_t)i * wb + (i - pp)) * ns + is] * fac[((int64_t)j * wb + (j - pp)) * ns + is];
+      if (i == j)
+        fac[((int64_t)i * wb) * ns + is] = sum > 0.0 ? sqrt(sum) : 1.0;  // SPD: sum > 0; guard keeps it finite
+      else
+        fac[((int64_t)i * wb + (i - j)) * ns + is] = sum / fac[((int64_t)j * wb) * ns + is];
+    }
+  }
+}
+
+// z = M^{-1} r on every thickness line (forward and backward substitution
+// with the banded factor); with p given, p = z too.  One thread per line.  The
+// last HB = 3Q + 2 values of each substitution stay in registers (a window
+// shifted by one per row), so a row waits on no memory round trip of its own
+// results; the factor's entries have known addresses and stream in.
+template <int Q>
+__global__ void __launch_bounds__(256) k_cg_line_solve(Dev d, const double *__restrict__ fac,
+                                                       const double *__restrict__ r, double *__restrict__ z,
+                                                       double *__restrict__ p) {
+  constexpr int HB = 3 * Q + 2, WB = HB + 1;
+  const int is = blockIdx.x * blockDim.x + threadIdx.x;
+  if (is >= d.ns) return;
+  const int n = 3 * d.nt;
+  const int64_t ns = d.ns;
+  auto row = [&](int i) { return 3 * ((int64_t)(i / 3) * ns + is) + i % 3; };
+  double win[HB];  // win[HB - c] = y[i - c] for c = 1..HB (zeros before the first row)
+#pragma unroll
+  for (int c = 0; c < HB; ++c) win[c] = 0.0;
+  for (int i = 0; i < n; ++i) {  // L y = r (y kept in z)
+    const double *Li = fac + (int64_t)i * WB * ns + is;
+    double sum = r[row(i)];
+#pragma unroll
+    for (int c = 1; c <= HB; ++c)
+      if (i - c >= 0) sum -= Li[c * ns] * win[HB - c];
+    const double y = sum / Li[0];
+#pragma unroll
+    for (int c = 0; c + 1 < HB; ++c) win[c] = win[c + 1];
+    win[HB - 1] = y;
+    z[row(i)] = y;
+  }
+#pragma unroll
+  for (int c = 0; c < HB; ++c) win[c] = 0.0;  // win[c - 1] = z[i + c] for c = 1..HB (zeros past the last)
+  for (int i = n - 1; i >= 0; --i) {  // L^T z = y
+    double sum = z[row(i)];
+#pragma unroll
+    for (int c = 1; c <= HB; ++c)
+      if (i + c < n) sum -= fac[((int64_t)(i + c) * WB + c) * ns + is] * win[c - 1];
+    const double v = sum / fac[(int64_t)i * WB * ns + is];
+#pragma unroll
+    for (int c = HB - 1; c > 0; --c) win[c] = win[c - 1];
+    win[0] = v;
+    z[row(i)] = v;
+    if (p) p[row(i)] = v;
+  }
+}
+
+void launch_line_solve(const lam_plan *pl, const Dev &d, const double *fac, const double *r, double *z, double *pv,
+                       hipStream_t s) {
+  const dim3 lg((unsigned)((pl->ns + 255) / 256)), vb(256);
+  switch (pl->q) {
+    case 1: hipLaunchKernelGGL((k_cg_line_solve<1>), lg, vb, 0, s, d, fac, r, z, pv); break;
+    case 2: hipLaunchKernelGGL((k_cg_line_solve<2>), lg, vb, 0, s, d, fac, r, z, pv); break;
+    case 3: hipLaunchKernelGGL((k_cg_line_solve<3>), lg, vb, 0, s, d, fac, r, z, pv); break;
+    default: hipLaunchKernelGGL((k_cg_line_solve<4>), lg, vb, 0, s, d, fac, r, z, pv); break;
+  }
+}
+
+// partial sums of a.b (and, if c is given, of a.c) over blocks of a grid-stride loop
 __global__ void __launch_bounds__(256) k_dot_partial(const double *__restrict__ a, const double *__restrict__ b,
-                                                     const uint8_t *__restrict__ fixed, int64_t n,
-                                                     double *__restrict__ part) {
-  __shared__ double sh[256];
-  double acc = 0.0;
+                                                     const double *__restrict__ c, const uint8_t *__restrict__ fixed,
+                                                     int64_t n, double *__restrict__ part) {
+  __shared__ double sh[2][256];
+  double ab = 0.0, ac = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    if (!(fixed && fixed[i])) acc += a[i] * b[i];
-  sh[threadIdx.x] = acc;
+    if (!(fixed && fixed[i])) {
+      ab += a[i] * b[i];
+      if (c) ac += a[i] * c[i];
+    }
+  sh[0][threadIdx.x] = ab;
+  sh[1][threadIdx.x] = ac;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    if ((int)threadIdx.x < h) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + h];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + h];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = sh[0][0];
+    part[CG_PARTS + blockIdx.x] = sh[1][0];
+  }
 }
 
-__global__ void __launch_bounds__(256) k_dot_final(const double *__restrict__ part, double *__restrict__ out) {
-  __shared__ double sh[256];
-  sh[threadIdx.x] = part[threadIdx.x] + part[threadIdx.x + 256];
+// out[0] = sum of part[0..CG_PARTS), out[two] = sum of part[CG_PARTS..2 CG_PARTS) if two > 0
+__global__ void __launch_bounds__(256) k_dot_final(const double *__restrict__ part, double *__restrict__ out, int two) {
+  __shared__ double sh[2][256];
+  sh[0][threadIdx.x] = part[threadIdx.x] + part[threadIdx.x + 256];
+  sh[1][threadIdx.x] = part[CG_PARTS + threadIdx.x] + part[CG_PARTS + threadIdx.x + 256];
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    if ((int)threadIdx.x < h) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + h];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + h];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = sh[0];
+  if (threadIdx.x == 0) {
+    out[0] = sh[0][0];
+    if (two > 0) out[two] = sh[1][0];
+  }
 }
 
-// r = P b - A x, p = r
+// r = P b - A x
 __global__ void k_cg_init(int64_t n, const double *__restrict__ b, const double *__restrict__ ax,
-                          const uint8_t *__restrict__ fixed, double *__restrict__ r, double *__restrict__ p) {
+                          const uint8_t *__restrict__ fixed, double *__restrict__ r) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double v = (fixed && fixed[i] ? 0.0 : b[i]) - ax[i];
-  r[i] = v;
-  p[i] = v;
+  r[i] = (fixed && fixed[i] ? 0.0 : b[i]) - ax[i];
 }
 
-// alpha = (r.r) / (p.q); x += alpha p; r -= alpha q.  alpha = 0 once p.q is
+// alpha = (r.z) / (p.q); x += alpha p; r -= alpha q.  alpha = 0 once p.q is
 // zero (p = 0: an iteration after the exact solution, see CG_CHECK)
 __global__ void k_cg_step(int64_t n, const double *__restrict__ scal, const double *__restrict__ p,
                           const double *__restrict__ q, double *__restrict__ x, double *__restrict__ r) {
@@ -1717,12 +1887,12 @@ __global__ void k_cg_step(int64_t n, const double *__restrict__ scal, const doub
   r[i] -= alpha * q[i];
 }
 
-// beta = (new r.r) / (r.r); p = r + beta p (beta = 0 once r.r is zero)
-__global__ void k_cg_dir(int64_t n, const double *__restrict__ scal, const double *__restrict__ r,
+// beta = (new r.z) / (r.z); p = z + beta p (beta = 0 once r.z is zero)
+__global__ void k_cg_dir(int64_t n, const double *__restrict__ scal, const double *__restrict__ z,
                          double *__restrict__ p) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  p[i] = r[i] + (scal[0] != 0.0 ? scal[2] / scal[0] : 0.0) * p[i];
+  p[i] = z[i] + (scal[0] != 0.0 ? scal[2] / scal[0] : 0.0) * p[i];
 }
 
 __global__ void k_scalar_copy(double *__restrict__ scal, int to, int from) {
@@ -1731,16 +1901,23 @@ __global__ void k_scalar_copy(double *__restrict__ scal, int to, int from) {
 
 namespace {
 
-void launch_dot(const double *a, const double *b, const uint8_t *fixed, int64_t n, double *part, double *out,
-                hipStream_t s) {
-  hipLaunchKernelGGL(k_dot_partial, dim3(CG_PARTS), dim3(256), 0, s, a, b, fixed, n, part);
-  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, part, out);
+// out[0] = a.b (fixed rows skipped if fixed is given); with c, out[two] = a.c too
+void launch_dot(const double *a, const double *b, const double *c, const uint8_t *fixed, int64_t n, double *part,
+                double *out, int two, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(CG_PARTS), dim3(256), 0, s, a, b, c, fixed, n, part);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, part, out, two);
 }
 
 }  // namespace
 
+namespace {
+
+int64_t cg_factor_doubles(const lam_plan *p) { return (int64_t)p->ns * 3 * p->nt * (3 * p->q + 3); }
+
+}  // namespace
+
 extern "C" LAM_API int64_t lam_cg_work_bytes(const lam_plan *p) {
-  return p ? (int64_t)sizeof(double) * (3 * p->nrows + CG_PARTS + 4) : 0;
+  return p ? (int64_t)sizeof(double) * (4 * p->nrows + cg_factor_doubles(p) + 2 * CG_PARTS + 6) : 0;
 }
 
 extern "C" LAM_API lam_status lam_cg(const lam_plan *p, void *ws, int64_t ws_bytes, const double *C,
@@ -1755,31 +1932,38 @@ extern "C" LAM_API lam_status lam_cg(const lam_plan *p, void *ws, int64_t ws_byt
   hipStream_t s = static_cast<hipStream_t>(stream);
   Dev d = make_dev(p, ws);
   const int64_t n = n_rows;
-  double *r = static_cast<double *>(work), *pv = r + n, *q = pv + n, *part = q + n, *scal = part + CG_PARTS;
-  const dim3 vg((unsigned)((n + 255) / 256)), vb(256);
+  double *r = static_cast<double *>(work), *pv = r + n, *q = pv + n, *z = q + n, *fac = z + n;
+  double *part = fac + cg_factor_doubles(p), *scal = part + 2 * CG_PARTS;
+  const dim3 vg((unsigned)((n + 255) / 256)), lg((unsigned)((p->ns + 255) / 256)), vb(256);
   launch_prep(p, d, C, theta, s);
+  if (p->kron_nsc == 1)
+    hipLaunchKernelGGL((k_cg_lines<1>), lg, vb, 0, s, d, d.Qc, fixed, fac);
+  else
+    hipLaunchKernelGGL((k_cg_lines<2>), lg, vb, 0, s, d, d.Qc, fixed, fac);
   launch_apply(p, d, x, fixed, q, stream);
-  hipLaunchKernelGGL(k_cg_init, vg, vb, 0, s, n, b, q, fixed, r, pv);
-  launch_dot(b, b, fixed, n, part, scal + 3, s);
-  launch_dot(r, r, nullptr, n, part, scal + 0, s);
-  double host[4];
-  if (hipMemcpyAsync(host, scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  hipLaunchKernelGGL(k_cg_init, vg, vb, 0, s, n, b, q, fixed, r);
+  launch_line_solve(p, d, fac, r, z, pv, s);
+  launch_dot(b, b, nullptr, fixed, n, part, scal + 3, 0, s);
+  launch_dot(r, z, r, nullptr, n, part, scal + 0, 4, s);  // r.z -> scal[0], r.r -> scal[4]
+  double host[6];
+  if (hipMemcpyAsync(host, scal, 6 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return LAM_EHIP;
   const double bb = host[3];
-  double rr = host[0];
+  double rr = host[4];
   int it = 0;
   while (it < max_iter && !(bb > 0.0 ? rr <= tol * tol * bb : rr == 0.0)) {
     const int batch = max_iter - it < CG_CHECK ? max_iter - it : CG_CHECK;
     for (int k = 0; k < batch; ++k) {
       launch_apply(p, d, pv, fixed, q, stream);
-      launch_dot(pv, q, nullptr, n, part, scal + 1, s);
+      launch_dot(pv, q, nullptr, nullptr, n, part, scal + 1, 0, s);
       hipLaunchKernelGGL(k_cg_step, vg, vb, 0, s, n, scal, pv, q, x, r);
-      launch_dot(r, r, nullptr, n, part, scal + 2, s);
-      hipLaunchKernelGGL(k_cg_dir, vg, vb, 0, s, n, scal, r, pv);
+      launch_line_solve(p, d, fac, r, z, nullptr, s);
+      launch_dot(r, z, r, nullptr, n, part, scal + 2, 2, s);  // new r.z -> scal[2], r.r -> scal[4]
+      hipLaunchKernelGGL(k_cg_dir, vg, vb, 0, s, n, scal, z, pv);
       hipLaunchKernelGGL(k_scalar_copy, dim3(1), dim3(64), 0, s, scal, 0, 2);
     }
-    if (hipMemcpyAsync(&rr, scal + 2, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+    if (hipMemcpyAsync(&rr, scal + 4, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return LAM_EHIP;
     it += batch;

@@ -150,7 +150,9 @@ def test_product_cg_rank1_argument_errors():
     buf = np.zeros(max(n, 64), dtype=np.float64)
     p = buf.ctypes.data
     it, res = ctypes.c_int32(), ctypes.c_double()
-    assert lib.lam_cg_work_bytes(h) == 8 * (3 * n + 512 + 4)
+    # r, p, q, z; the banded factor of every thickness line (ns lines of 3 nt rows, 3q + 3 band
+    # columns); partial sums; scalars.  The 8x8 bilinear plate: ns = 81, nt = 5, q = 1
+    assert lib.lam_cg_work_bytes(h) == 8 * (4 * n + 81 * 15 * 6 + 2 * 512 + 6)
     # wrong row count
     assert lib.lam_apply(h, ws, wb, p, p, p, None, n + 1, p, None) == -5
     assert lib.lam_adjoint_rank1(h, ws, wb, p, p, p, n - 1, p, p, None) == -5
