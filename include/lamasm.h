@@ -282,9 +282,9 @@ LAM_API lam_status lam_adjoint_rank1(const lam_plan *plan, void *ws, int64_t ws_
                                      double *grad_theta, void *stream);
 
 /* Batched assembly: many laminates (different meshes, degrees, ply counts,
- * materials) in one persistent kernel launch per memory wave (Sec. 3 applied
- * per laminate; each laminate's values are exactly those of lam_assemble on
- * its own plan).
+ * materials) assembled wave by wave, each laminate's values exactly those of
+ * lam_assemble on its own plan (Sec. 3 applied per laminate; the device code
+ * is the same).
  *
  * lam_batch_create plans every descriptor (host only) and splits the
  * laminates, in the given order, into waves: runs of consecutive laminates
@@ -292,16 +292,17 @@ LAM_API lam_status lam_adjoint_rank1(const lam_plan *plan, void *ws, int64_t ws_
  * larger than wave_bytes forms a wave of its own.  Fails with the first
  * failing descriptor's status, or LAM_EUNSUP for a laminate whose scatter
  * needs more than two set slots per thickness chunk (many distinct sets on
- * one row: use lam_assemble for it).
+ * one row, e.g. harmonic sets: use lam_assemble for it).  Affine laminates
+ * only (no curved shells).
  *
  * Device memory: one workspace of ws_bytes (lam_batch_info), 256-byte
  * aligned, holding every plan's constant tables, one scratch arena reused by
- * all waves, and the work queues.  C_all packs the laminates' n_mat*36
- * tensors and theta_all their n_ply angles at the offsets lam_batch_laminate
- * reports (device doubles).  Values of wave w go to vals_wave (device,
- * vals_len >= that wave's length <= max_wave_vals doubles), laminate i at
- * vals_offset (a multiple of 32 doubles) within its wave; gaps between
- * laminates are not written. */
+ * all waves, the work lists and a status word.  C_all packs the laminates'
+ * n_mat*36 tensors and theta_all their n_ply angles at the offsets
+ * lam_batch_laminate reports (device doubles).  Values of wave w go to
+ * vals_wave (device, vals_len >= that wave's length <= max_wave_vals doubles),
+ * laminate i at vals_offset (a multiple of 32 doubles) within its wave; gaps
+ * between laminates are not written. */
 typedef struct lam_batch lam_batch;
 
 LAM_API lam_status lam_batch_create(int32_t n, const lam_laminate_desc *descs, int64_t wave_bytes, lam_batch **out);
@@ -321,18 +322,22 @@ LAM_API lam_status lam_batch_upload(const lam_batch *batch, void *ws, int64_t ws
 /* CSR pattern of laminate i, as lam_pattern. */
 LAM_API lam_status lam_batch_pattern(const lam_batch *batch, const void *ws, int64_t ws_bytes, int32_t i,
                                      int64_t *rowptr, int32_t *colind, void *stream);
-/* Assembles every laminate of wave `wave`: a kernel clearing the queue heads,
- * the rotation / 1D-coefficient kernel, the 2D-operator kernel over all the
- * wave's laminates, then the persistent scatter kernel.  Asynchronous; may be
- * captured in a HIP graph (no memset, no allocation, no host
- * synchronization).  Waves share the scratch arena: waves on different
- * streams must not overlap. */
+/* Assembles every laminate of wave `wave`: a launch for the rotated tensors
+ * and brackets of every laminate's sets and their folded 1D coefficients, a
+ * launch for the 2D moments of all the wave's laminates, then one scatter
+ * launch per scatter block size (at most four), each block one (tile, group
+ * of thickness chunks) item, items cut into eight ranges of equal output
+ * bytes, one per XCD.  Asynchronous; may be captured in a HIP graph (no
+ * memset, no allocation, no host synchronization).  Waves share the scratch
+ * arena: waves on different streams must not overlap. */
 LAM_API lam_status lam_batch_assemble(const lam_batch *batch, void *ws, int64_t ws_bytes, int32_t wave,
                                       const double *C_all, const double *theta_all, double *vals_wave,
                                       int64_t vals_len, void *stream);
-/* Checks the last assembled wave (synchronizes stream): *error is nonzero if
- * the persistent scatter left any of the wave's items untaken. */
-LAM_API lam_status lam_batch_check(const lam_batch *batch, const void *ws, int64_t ws_bytes, int32_t *error,
+/* Reads and clears the status flags of every laminate (synchronizes stream):
+ * *flags (host) receives the OR over the laminates of the LAM_CHECK_* bits of
+ * lam_check, raised by any assembly since the last check (bucket sets whose
+ * plies were given different angles in theta_all). */
+LAM_API lam_status lam_batch_check(const lam_batch *batch, void *ws, int64_t ws_bytes, int32_t *flags,
                                    void *stream);
 
 /* Kernel timing for measurement.  While enabled, every device entry point

@@ -1,28 +1,28 @@
 // batch.hip -- many laminates of uneven size, degree and ply count,
-// assembled wave by wave with one persistent scatter launch per memory wave.
+// assembled wave by wave.
 //
 // Every laminate keeps its own plan (tables, tiles, chunks, sets).  Its
 // constant tables sit in the batch workspace for the whole batch; its scratch
-// (per-set rotated tensors, P, Q coefficients, moments) sits in a wave arena
-// reused by every wave; its CSR values go to the caller's wave buffer.  A
-// wave is a run of laminates whose values and scratch fit the budget.
+// (per-set rotated tensors and brackets, moments, folded 1D coefficients) sits
+// in a wave arena reused by every wave; its CSR values go to the caller's wave
+// buffer.  A wave is a run of laminates whose values and scratch fit the budget.
 //
-// A wave runs as four launches on one stream (all capturable in a HIP graph):
-//   k_batch_reset  clears the eight queue heads (a kernel, not a memset);
-//   k_batch_prep   one block per small item: rotated tensors / harmonics of a
-//                  laminate's sets, or 256 of its folded 1D coefficients;
+// A wave runs as these launches on one stream (all capturable in a HIP graph):
+//   k_batch_prep   one block per small item: the rotated tensors and brackets
+//                  of a laminate's sets (and the bucket check of its plies), or
+//                  four of its folded 1D coefficients (one wave each);
 //   k_batch_p2d    one block per 256 in-plane nonzeros of any laminate: the
 //                  set-independent 2D moments (the scatter contracts P from them);
-//   k_batch_kron   the persistent scatter.  The wave's scatter items (one tile
-//                  of whole in-plane rows x one group of consecutive thickness
-//                  chunks of one laminate, in laminate, tile, group order) are cut into eight
-//                  contiguous ranges of equal output bytes, one per XCD; the
-//                  blocks of an XCD take items of their range from that range's
-//                  atomic head, so each XCD writes long contiguous runs of the
-//                  CSR values (no cache line written from two L2s) and the
-//                  hardware dispatcher plus the heads balance uneven items.
-// Dependencies between the phases are stream order only: no block waits on
-// another, so the persistent kernel needs no spin or fence.
+//   k_batch_kron_grid, once per scatter block size (64, 128, 192, 256 threads,
+//                  the laminates' tile widths): one block per item (one tile of
+//                  whole in-plane rows x one group of consecutive thickness
+//                  chunks of one laminate).  A size's items are cut into eight
+//                  contiguous ranges of equal output bytes, one per XCD; block b
+//                  takes item b / 8 of range b mod 8 (blocks go to the XCDs in
+//                  turn), so each XCD writes long contiguous runs of the CSR
+//                  values and no cache line is written from two L2s.
+// The device code of every item is the single-laminate path's (device.h):
+// each laminate's values are bit for bit those of lam_assemble on its plan.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,6 +34,7 @@
 #include "device.h"
 
 using lamdev::Dev;
+using namespace lamdev;
 
 struct lam_batch {
   int n = 0;
@@ -49,7 +50,7 @@ struct lam_batch {
   int64_t total_nnz = 0;
   // device layout of the batch workspace
   int64_t tables_bytes = 0, arena_off = 0, arena_bytes = 0;
-  int64_t devs_off = 0, meta_off = 0, items_off = 0, counters_off = 0, total = 0;
+  int64_t devs_off = 0, meta_off = 0, items_off = 0, status_off = 0, total = 0;
   // per wave: first item and count of the prep, 2D and scatter lists, and the
   // scatter list's eight per-XCD ranges (9 bounds, relative to its first item)
   std::vector<int64_t> wave_prep_off, wave_p2d_off, wave_kron_off;
@@ -57,9 +58,6 @@ struct lam_batch {
   std::vector<int> wave_xcd;  // 9 per wave
   std::vector<int4> items;    // all lists of all waves, concatenated
   int64_t lds_bytes = 0;
-  int grid = 1024;  // persistent scatter blocks (a multiple of 8)
-  bool persistent = false;  // scatter as a persistent queue kernel (else one block per item)
-  mutable int last_wave = -1;  // wave of the last lam_batch_assemble (for lam_batch_check)
 };
 
 namespace {
@@ -88,14 +86,9 @@ struct BatchArgs {
   const int4 *__restrict__ items;  // this launch's list
   int n_items;
   int xcd_bound[N_XCD + 1];        // scatter: per-XCD item ranges
-  int *heads;                      // scatter: one head per XCD
   const double *C_all, *th_all;
   double *vals;
 };
-
-__global__ void k_batch_reset(int *heads) {
-  if (threadIdx.x < N_XCD) heads[threadIdx.x] = 0;
-}
 
 // One block per prep item: {lam, ITEM_ROTATE, 0, 0} or {lam, ITEM_Q1D, i, 0}.
 __global__ void __launch_bounds__(BATCH_THREADS) k_batch_prep(BatchArgs a) {
@@ -104,10 +97,12 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_prep(BatchArgs a) {
   const Meta m = a.meta[w.x];
   const double *th = a.th_all + m.t_off;
   if (w.y == ITEM_ROTATE) {
-    for (int s = threadIdx.x; s < d.n_sets; s += BATCH_THREADS) lamdev::item_rotate_set(d, a.C_all + m.c_off, th, s);
+    for (int s = threadIdx.x; s < std::max(d.n_sets, d.n_ply); s += BATCH_THREADS) {
+      check_ply(d, th, s);
+      rotate_one(d, a.C_all + m.c_off, th, s);
+    }
   } else {
-    const int64_t idx = (int64_t)w.z * BATCH_THREADS + threadIdx.x;
-    if (idx < d.nnzz * lamdev::q1d_width(d)) lamdev::item_q1d(d, th, idx);
+    q1d_wave(d, th, (int64_t)w.z * (BATCH_THREADS / 64) + threadIdx.x / 64, threadIdx.x & 63);
   }
 }
 
@@ -115,39 +110,11 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_prep(BatchArgs a) {
 __global__ void __launch_bounds__(BATCH_THREADS) k_batch_p2d(BatchArgs a) {
   const int4 w = a.items[blockIdx.x];
   const Dev &d = a.devs[w.x];
-  const int64_t k = (int64_t)w.y * BATCH_THREADS + threadIdx.x;
-  if (k < d.nnz2) lamdev::item_p2d(d, d.Ec, d.P, d.M, k, 0);  // moments only
+  p2d_one(d, d.Ec, d.P, d.M, (int64_t)w.y * BATCH_THREADS + threadIdx.x, 0);  // moments only
 }
 
-// Persistent scatter over items {lam, tile, chunk group, 0}.  Control flow around
-// the barriers is uniform and visibly so to the compiler (the item index and
-// fields are read into scalar registers, each iteration opens with a
-// barrier): otherwise the loop may be compiled into nested exec-masked loops
-// in which lanes re-enter the loop-top barrier without the thread that
-// refreshes the item index.
-__global__ void __launch_bounds__(BATCH_THREADS) k_batch_kron(BatchArgs a) {
-  extern __shared__ double lds[];
-  __shared__ int s_item;
-  const int tid = threadIdx.x;
-  const int x = (int)(blockIdx.x % N_XCD);
-  const int first = a.xcd_bound[x], count = a.xcd_bound[x + 1] - first;
-  for (;;) {
-    __syncthreads();  // the previous item's LDS staging is no longer read
-    if (tid == 0) s_item = atomicAdd(a.heads + x, 1);
-    __syncthreads();
-    const int j = __builtin_amdgcn_readfirstlane(s_item);
-    if (j >= count) break;
-    const int4 wv = a.items[first + j];
-    const int lam = __builtin_amdgcn_readfirstlane(wv.x);
-    const int tile = __builtin_amdgcn_readfirstlane(wv.y), g = __builtin_amdgcn_readfirstlane(wv.z);
-    const Dev &d = a.devs[lam];
-    double *vals = a.vals + a.meta[lam].vals_off;
-    lamdev::item_kron_reg<2>(d, d.Qc, vals, tile, g, lds, tid, (int)blockDim.x);
-  }
-}
-
-// The same scatter without a queue loop: block b takes item b / 8 of XCD
-// b % 8's range, the hardware dispatcher being the queue.
+// The scatter: block b takes item b / 8 of XCD b % 8's range, the hardware
+// dispatcher being the queue.
 __global__ void __launch_bounds__(BATCH_THREADS) k_batch_kron_grid(BatchArgs a) {
   extern __shared__ double lds[];
   const int x = (int)(blockIdx.x % N_XCD), j = (int)(blockIdx.x / N_XCD);
@@ -155,7 +122,27 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_kron_grid(BatchArgs a) 
   if (j >= count) return;
   const int4 wv = a.items[first + j];
   const Dev &d = a.devs[wv.x];
-  lamdev::item_kron_reg<2>(d, d.Qc, a.vals + a.meta[wv.x].vals_off, wv.y, wv.z, lds, threadIdx.x, (int)blockDim.x);
+  kron_group<2>(d, d.Qc, a.vals + a.meta[wv.x].vals_off, wv.y, wv.z, lds, threadIdx.x, (int)blockDim.x);
+}
+
+// OR of every laminate's status words into *out (bit 0: a bucket set's plies
+// disagree, bit 1: harmonic5 coupling, as lam_check), which are cleared.
+__global__ void __launch_bounds__(BATCH_THREADS) k_batch_status(const Dev *__restrict__ devs, int n, int *out) {
+  __shared__ int flags[BATCH_THREADS];
+  int f = 0;
+  for (int i = threadIdx.x; i < n; i += BATCH_THREADS) {
+    int *st = devs[i].status;
+    f |= (st[0] ? 1 : 0) | (st[1] ? 2 : 0);
+    st[0] = 0;
+    st[1] = 0;
+  }
+  flags[threadIdx.x] = f;
+  __syncthreads();
+  for (int h = BATCH_THREADS / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) flags[threadIdx.x] |= flags[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = flags[0];
 }
 
 }  // namespace
@@ -178,7 +165,6 @@ extern "C" LAM_API lam_status lam_batch_create_tuned(int32_t n, const lam_lamina
   lam_batch *B = new (std::nothrow) lam_batch();
   if (!B) return LAM_EINVAL;
   B->n = n;
-  if (const char *e = std::getenv("LAMASM_BATCH_KRON")) B->persistent = std::strcmp(e, "persistent") == 0;
   int64_t cbytes = 0, ctot = 0, ttot = 0;
   for (int i = 0; i < n; ++i) {
     lam_plan *p = nullptr;
@@ -237,9 +223,8 @@ extern "C" LAM_API lam_status lam_batch_create_tuned(int32_t n, const lam_lamina
     for (int i = f; i < f + c; ++i) {
       const lam_plan *p = B->plans[i];
       B->items.push_back(make_int4(i, ITEM_ROTATE, 0, 0));
-      const int64_t nq = p->nnzz * std::max(p->kron_nsc, 1);
-      for (int64_t j = 0; j < (nq + BATCH_THREADS - 1) / BATCH_THREADS; ++j)
-        B->items.push_back(make_int4(i, ITEM_Q1D, (int)j, 0));
+      const int64_t nq = p->nnzz * std::max(p->kron_nsc, 1), per = BATCH_THREADS / 64;  // a wave per entry
+      for (int64_t j = 0; j < (nq + per - 1) / per; ++j) B->items.push_back(make_int4(i, ITEM_Q1D, (int)j, 0));
     }
     B->wave_prep_n.push_back((int)((int64_t)B->items.size() - B->wave_prep_off.back()));
     B->wave_p2d_off.push_back((int64_t)B->items.size());
@@ -275,7 +260,7 @@ extern "C" LAM_API lam_status lam_batch_create_tuned(int32_t n, const lam_lamina
       }
     }
   }
-  // batch workspace: tables | arena | Dev[n] | Meta[n] | items | queue heads
+  // batch workspace: tables | arena | Dev[n] | Meta[n] | items | status word
   int64_t off = a256(B->tables_bytes);
   B->arena_off = off;
   B->arena_bytes = a256(arena);
@@ -286,8 +271,8 @@ extern "C" LAM_API lam_status lam_batch_create_tuned(int32_t n, const lam_lamina
   off = a256(off + (int64_t)sizeof(Meta) * n);
   B->items_off = off;
   off = a256(off + (int64_t)sizeof(int4) * B->items.size());
-  B->counters_off = off;
-  off = a256(off + (int64_t)sizeof(int) * N_XCD);
+  B->status_off = off;
+  off = a256(off + (int64_t)sizeof(int));
   B->total = off;
   *out = B;
   return LAM_OK;
@@ -330,7 +315,7 @@ extern "C" LAM_API lam_status lam_batch_upload(const lam_batch *b, void *ws, int
     if (hipMemcpyAsync(base + b->const_off[i], p->image.data(), p->L.const_bytes, hipMemcpyHostToDevice, s) !=
         hipSuccess)
       return LAM_EHIP;
-    devs[i] = lamdev::make_dev_split(p, base + b->const_off[i], base + b->arena_off + b->scratch_off[i]);
+    devs[i] = lamdev::make_dev(p, base + b->const_off[i], base + b->arena_off + b->scratch_off[i]);
     meta[i].c_off = b->c_off[i];
     meta[i].t_off = b->t_off[i];
     meta[i].vals_off = b->vals_off[i];
@@ -368,7 +353,6 @@ extern "C" LAM_API lam_status lam_batch_assemble(const lam_batch *b, void *ws, i
   BatchArgs a;
   a.devs = reinterpret_cast<const Dev *>(base + b->devs_off);
   a.meta = reinterpret_cast<const Meta *>(base + b->meta_off);
-  a.heads = reinterpret_cast<int *>(base + b->counters_off);
   a.C_all = C_all;
   a.th_all = theta_all;
   a.vals = vals_wave;
@@ -386,38 +370,27 @@ extern "C" LAM_API lam_status lam_batch_assemble(const lam_batch *b, void *ws, i
     a.n_items = b->wave_kron_n[gi];
     for (int x = 0; x <= N_XCD; ++x) a.xcd_bound[x] = b->wave_xcd[(N_XCD + 1) * gi + x];
     const dim3 block(64 * (g + 1));
-    if (b->persistent) {
-      hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, a.heads);
-      hipLaunchKernelGGL(k_batch_kron, dim3(b->grid), block, (size_t)b->lds_bytes, s, a);
-    } else {
-      int most = 0;
-      for (int x = 0; x < N_XCD; ++x) most = std::max(most, a.xcd_bound[x + 1] - a.xcd_bound[x]);
-      hipLaunchKernelGGL(k_batch_kron_grid, dim3(N_XCD * most), block, (size_t)b->lds_bytes, s, a);
-    }
+    int most = 0;
+    for (int x = 0; x < N_XCD; ++x) most = std::max(most, a.xcd_bound[x + 1] - a.xcd_bound[x]);
+    hipLaunchKernelGGL(k_batch_kron_grid, dim3(N_XCD * most), block, (size_t)b->lds_bytes, s, a);
   }
   lam::profile_end(prof, stream);
-  b->last_wave = wave;
   return hipGetLastError() == hipSuccess ? LAM_OK : LAM_EHIP;
 }
 
-extern "C" LAM_API lam_status lam_batch_check(const lam_batch *b, const void *ws, int64_t ws_bytes, int32_t *error,
+extern "C" LAM_API lam_status lam_batch_check(const lam_batch *b, void *ws, int64_t ws_bytes, int32_t *flags,
                                               void *stream) {
-  if (!b || !ws || !error) return LAM_EINVAL;
+  if (!b || !ws || !flags) return LAM_EINVAL;
   if (ws_bytes < b->total) return LAM_ESIZE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  int heads[N_XCD] = {0};
-  if (hipMemcpyAsync(heads, static_cast<const char *>(ws) + b->counters_off, sizeof(heads), hipMemcpyDeviceToHost,
-                     s) != hipSuccess ||
+  char *base = static_cast<char *>(ws);
+  int *out = reinterpret_cast<int *>(base + b->status_off);
+  hipLaunchKernelGGL(k_batch_status, dim3(1), dim3(BATCH_THREADS), 0, s, reinterpret_cast<const Dev *>(base + b->devs_off),
+                     b->n, out);
+  int host = 0;
+  if (hipMemcpyAsync(&host, out, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return LAM_EHIP;
-  // every scatter item of the last wave must have been taken from its range
-  *error = 0;
-  if (b->persistent && b->last_wave >= 0) {
-    int g = N_GROUPS - 1;  // the last group launched in that wave
-    while (g > 0 && b->wave_kron_n[N_GROUPS * b->last_wave + g] == 0) --g;
-    const int *xb = &b->wave_xcd[(N_XCD + 1) * (N_GROUPS * b->last_wave + g)];
-    for (int x = 0; x < N_XCD; ++x)
-      if (heads[x] < xb[x + 1] - xb[x]) *error = 1;
-  }
+  *flags = host;
   return LAM_OK;
 }

@@ -1,6 +1,9 @@
-// device.h -- device-side plan view and the work items of the batched
-// persistent kernel (batch.hip): the same per-laminate arithmetic as the
-// single-laminate kernels, written as block-level items.  Not part of the ABI.
+// device.h -- the device view of a plan and the device code that the
+// single-laminate kernels (kernels.hip) and the batched ones (batch.hip)
+// share: material rotation and bracket coefficients, the set checks, the 2D
+// moments (affine and curved shells), the folded 1D coefficients and the
+// register-mode scatter of one item.  One source for both paths.  Not part
+// of the ABI.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -38,11 +41,16 @@ struct Dev {
   const int *a1f, *a1c, *a2f, *a2c, *zs_first, *zs_cptr, *zs_cell;
   int ne1, ne2, nzs;
   double *Eply;
-  const double *Escat;  // bracket coefficients of the scatter's sets (Ec: batches hold no per-ply harmonic plans)
+  const double *Escat;  // bracket coefficients of the scatter's sets: Ec, or Eply for harmonic plans
   int harm_ply;
   const int *rowply, *rowfin;
   double *Qp, *adj_part, *adj_y, *adj_dD;
-  int *status;  // lam::N_STATUS flags, set by kernels, cleared by lam_check / lam_batch_check
+  int *status;  // lam::N_STATUS flags, set by kernels, cleared by lam_check
+  // curved shells: per-point map gradients and in-plane basis (constant);
+  // material fields: set brackets per in-plane function and per point (scratch)
+  int shell, mat_field, ngp, nb;
+  const double *gtab, *rtab;
+  double *Ectl, *Epts;
   // scratch
   double *D, *Ec, *P, *Qc, *M;
 };
@@ -52,13 +60,14 @@ inline T *at(void *ws, const Region &r) {
   return reinterpret_cast<T *>(static_cast<char *>(ws) + r.off);
 }
 
-// Device view of a plan whose constant tables live at cbase and whose scratch
-// regions (offsets >= const_bytes) start at sbase: region r lives at
-// sbase + (r.off - const_bytes).  In one workspace holding both, sbase is
-// ws + const_bytes (make_dev), never ws itself: that would put D at ws and
-// the other scratch regions over the constant tables.
-inline Dev make_dev_split(const lam_plan *p, void *cbase, void *sbase) {
-  char *sb = static_cast<char *>(sbase) - p->L.const_bytes;
+// Device view of a plan: constant tables (and status words) in the caller's
+// workspace ws; the fast assembly's scratch regions [const_bytes, fwd_end) at
+// sbase + (offset - const_bytes), by default right after the tables in ws.
+// With an outside sbase (the static scratch of lam_assemble_static) the
+// regions of the standard assembly and the adjoint are left null.
+inline Dev make_dev(const lam_plan *p, void *ws, void *sbase = nullptr) {
+  const bool own = sbase == nullptr;
+  char *sb = (own ? static_cast<char *>(ws) + p->L.const_bytes : static_cast<char *>(sbase)) - p->L.const_bytes;
   Dev d;
   d.p1 = p->p1; d.p2 = p->p2; d.q = p->q;
   d.n1 = p->n1; d.n2 = p->n2; d.nt = p->nt; d.ns = p->ns;
@@ -69,53 +78,59 @@ inline Dev make_dev_split(const lam_plan *p, void *cbase, void *sbase) {
   for (int a = 0; a < 9; ++a) d.jit[a] = p->jit[a];
   d.detj = p->detj;
   const lam::Layout &L = p->L;
-  d.tab1 = at<double>(cbase, L.tab1); d.w1 = at<double>(cbase, L.w1);
-  d.tab2 = at<double>(cbase, L.tab2); d.w2 = at<double>(cbase, L.w2);
-  d.e1first = at<int>(cbase, L.e1first); d.e2first = at<int>(cbase, L.e2first);
-  d.pe1 = at<int2>(cbase, L.pe1); d.pe2 = at<int2>(cbase, L.pe2);
-  d.srow = at<int>(cbase, L.srow); d.krow = at<int>(cbase, L.krow); d.kcol = at<int>(cbase, L.kcol);
-  d.kp1 = at<int>(cbase, L.kp1); d.kp2 = at<int>(cbase, L.kp2);
-  d.zfirst = at<int>(cbase, L.zfirst); d.zply = at<int>(cbase, L.zply);
-  d.ztab = at<double>(cbase, L.ztab); d.zw = at<double>(cbase, L.zw);
-  d.zrow = at<int>(cbase, L.zrow); d.zcol = at<int>(cbase, L.zcol); d.zkrow = at<int>(cbase, L.zkrow);
-  d.zcptr = at<int>(cbase, L.zcptr); d.zcell = at<int>(cbase, L.zcell);
-  d.zaptr = at<int>(cbase, L.zaptr); d.zaset = at<int>(cbase, L.zaset);
-  d.set_mat = at<int>(cbase, L.set_mat); d.set_aux = at<int>(cbase, L.set_aux);
-  d.ply_mat = at<int>(cbase, L.ply_mat); d.ply_set = at<int>(cbase, L.ply_set);
-  d.tiles = at<int>(cbase, L.tiles);
-  d.chunk_ptr = at<int>(cbase, L.chunk_ptr);
-  d.chunk_sptr = at<int>(cbase, L.chunk_sptr);
-  d.chunk_set = at<int>(cbase, L.chunk_set);
-  d.zaslot = at<int>(cbase, L.zaslot);
+  d.tab1 = at<double>(ws, L.tab1); d.w1 = at<double>(ws, L.w1);
+  d.tab2 = at<double>(ws, L.tab2); d.w2 = at<double>(ws, L.w2);
+  d.e1first = at<int>(ws, L.e1first); d.e2first = at<int>(ws, L.e2first);
+  d.pe1 = at<int2>(ws, L.pe1); d.pe2 = at<int2>(ws, L.pe2);
+  d.srow = at<int>(ws, L.srow); d.krow = at<int>(ws, L.krow); d.kcol = at<int>(ws, L.kcol);
+  d.kp1 = at<int>(ws, L.kp1); d.kp2 = at<int>(ws, L.kp2);
+  d.zfirst = at<int>(ws, L.zfirst); d.zply = at<int>(ws, L.zply);
+  d.ztab = at<double>(ws, L.ztab); d.zw = at<double>(ws, L.zw);
+  d.zrow = at<int>(ws, L.zrow); d.zcol = at<int>(ws, L.zcol); d.zkrow = at<int>(ws, L.zkrow);
+  d.zcptr = at<int>(ws, L.zcptr); d.zcell = at<int>(ws, L.zcell);
+  d.zaptr = at<int>(ws, L.zaptr); d.zaset = at<int>(ws, L.zaset);
+  d.set_mat = at<int>(ws, L.set_mat); d.set_aux = at<int>(ws, L.set_aux);
+  d.ply_mat = at<int>(ws, L.ply_mat); d.ply_set = at<int>(ws, L.ply_set);
+  d.tiles = at<int>(ws, L.tiles);
+  d.chunk_ptr = at<int>(ws, L.chunk_ptr);
+  d.chunk_sptr = at<int>(ws, L.chunk_sptr);
+  d.chunk_set = at<int>(ws, L.chunk_set);
+  d.zaslot = at<int>(ws, L.zaslot);
   d.n_chunks = p->n_chunks;
-  d.group_ptr = at<int>(cbase, L.group_ptr);
-  d.group_sptr = at<int>(cbase, L.group_sptr);
-  d.group_set = at<int>(cbase, L.group_set);
-  d.chunk_lset = at<int>(cbase, L.chunk_lset);
+  d.group_ptr = at<int>(ws, L.group_ptr);
+  d.group_sptr = at<int>(ws, L.group_sptr);
+  d.group_set = at<int>(ws, L.group_set);
+  d.chunk_lset = at<int>(ws, L.chunk_lset);
   d.n_groups = p->n_groups;
   d.chunk_sets = p->chunk_sets;
   d.kron_lds_q = p->kron_lds_q;
-  d.zchunk = at<int>(cbase, L.zchunk);
-  d.a1f = at<int>(cbase, L.a1f); d.a1c = at<int>(cbase, L.a1c);
-  d.a2f = at<int>(cbase, L.a2f); d.a2c = at<int>(cbase, L.a2c);
-  d.zs_first = at<int>(cbase, L.zs_first); d.zs_cptr = at<int>(cbase, L.zs_cptr); d.zs_cell = at<int>(cbase, L.zs_cell);
+  d.zchunk = at<int>(ws, L.zchunk);
+  d.a1f = at<int>(ws, L.a1f); d.a1c = at<int>(ws, L.a1c);
+  d.a2f = at<int>(ws, L.a2f); d.a2c = at<int>(ws, L.a2c);
+  d.zs_first = at<int>(ws, L.zs_first); d.zs_cptr = at<int>(ws, L.zs_cptr); d.zs_cell = at<int>(ws, L.zs_cell);
   d.ne1 = p->ne1; d.ne2 = p->ne2; d.nzs = p->nzs;
   d.Eply = at<double>(sb, L.Eply);
   d.harm_ply = p->harm_ply;
-  d.rowply = at<int>(cbase, L.rowply); d.rowfin = at<int>(cbase, L.rowfin);
-  d.Qp = at<double>(sb, L.Qp); d.adj_part = at<double>(sb, L.adj_part);
-  d.adj_y = at<double>(sb, L.adj_y); d.adj_dD = at<double>(sb, L.adj_dD);
+  d.rowply = at<int>(ws, L.rowply); d.rowfin = at<int>(ws, L.rowfin);
+  d.Qp = own ? at<double>(sb, L.Qp) : nullptr;
+  d.adj_part = own ? at<double>(sb, L.adj_part) : nullptr;
+  d.adj_y = own ? at<double>(sb, L.adj_y) : nullptr;
+  d.adj_dD = own ? at<double>(sb, L.adj_dD) : nullptr;
   d.kron_nsc = p->kron_nsc;
   d.kron_lds_p = p->kron_lds_p;
-  d.status = at<int>(cbase, L.status);
+  d.status = at<int>(ws, L.status);
+  d.shell = p->shell;
+  d.mat_field = p->mat_field;
+  d.ngp = p->ng1 * p->ng2;
+  d.nb = (p->p1 + 1) * (p->p2 + 1);
+  d.gtab = at<double>(ws, L.gtab);
+  d.rtab = at<double>(ws, L.rtab);
+  d.Ectl = at<double>(sb, L.Ectl);
+  d.Epts = at<double>(sb, L.Epts);
   d.D = at<double>(sb, L.D); d.Ec = at<double>(sb, L.Ec); d.P = at<double>(sb, L.P);
-  d.Escat = d.Ec;
+  d.Escat = p->harm_ply ? d.Eply : d.Ec;
   d.Qc = at<double>(sb, L.Qc); d.M = at<double>(sb, L.M);
   return d;
-}
-
-inline Dev make_dev(const lam_plan *p, void *ws) {
-  return make_dev_split(p, ws, static_cast<char *>(ws) + p->L.const_bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -206,8 +221,33 @@ __device__ inline void bracket_coefficients(const double D[6][6], double *E) {
 // degree <= 4 once NH >= 9).
 constexpr int NH = 12;
 
-__device__ __forceinline__ void item_rotate_set(const Dev &d, const double *__restrict__ C, const double *__restrict__ theta, int s) {
+// Inputs a plan cannot honour raise a status word (plain stores of 1, never
+// cleared here; lam_check reads and clears them):
+//  - bucket sets: a ply given another angle than its set's first ply (the set
+//    is rotated by that one angle, so K would not be K(theta));
+//  - harmonic5 sets: a material with a nonzero {11,22,33,12}-{13,23} entry
+//    (relative to its largest entry, above 1e-13), whose rotation has odd
+//    harmonics that five terms do not hold (Remark on orientations).
+// (the bucket check runs per ply, check_ply; the harmonic5 one per material)
+__device__ __forceinline__ void check_ply(const Dev &d, const double *__restrict__ theta, int l) {
+  if (d.set_mode == LAM_SETS_BUCKET && l < d.n_ply && !(theta[l] == theta[d.set_aux[d.ply_set[l]]])) d.status[0] = 1;
+}
+
+__device__ __forceinline__ void check_set(const Dev &d, const double *__restrict__ Cm, int s) {
+  if (d.set_mode != LAM_SETS_BUCKET && d.n_harm == 5 && d.set_aux[s] == 0) {
+    double big = 0.0, cpl = 0.0;
+    for (int e = 0; e < 36; ++e) big = fmax(big, fabs(Cm[e]));
+    for (int I = 0; I < 4; ++I)
+      for (int J = 4; J < 6; ++J) cpl = fmax(cpl, fmax(fabs(Cm[6 * I + J]), fabs(Cm[6 * J + I])));
+    if (!(cpl <= 1e-13 * big)) d.status[1] = 1;
+  }
+}
+
+__device__ __forceinline__ void rotate_one(const Dev &d, const double *__restrict__ C, const double *__restrict__ theta,
+                                           int s) {
+  if (s >= d.n_sets) return;
   const double *Cm = C + 36 * d.set_mat[s];
+  check_set(d, Cm, s);
   double D[6][6];
   if (d.set_mode == LAM_SETS_BUCKET) {
     double th = theta[d.set_aux[s]];
@@ -230,7 +270,6 @@ __device__ __forceinline__ void item_rotate_set(const Dev &d, const double *__re
     for (int J = 0; J < 6; ++J) d.D[36 * s + 6 * I + J] = D[I][J];
   bracket_coefficients(D, d.Ec + 81 * s);
 }
-
 
 // 1D moments of functions i and j of one in-plane direction over the elements
 // of their common support (range: first element, count), by Gauss quadrature:
@@ -263,8 +302,7 @@ __device__ __forceinline__ void moments_1d(const double *__restrict__ tab, const
 // pushed through DF^{-T} (grad V = DF^{-T}(dS1,dS2,0), W = DF^{-T}(0,0,S))
 // into M_ab[k][l] = int (G_a^i)_k (G_b^j)_l |DF|.  Because each set's
 // material is constant over the plane, P_{s,ab}[r][t] = sum_kl M_ab[k][l] E_s[k][l][r][t].
-__device__ __forceinline__ void item_p2d(const Dev &d, const double *__restrict__ Ec, double *__restrict__ Pt,
-                                double *__restrict__ Mt, int64_t k, int write_p) {
+__device__ __forceinline__ void affine_moments(const Dev &d, int64_t k, double (&M)[4][3][3]) {
   const int is = d.krow[k], js = d.kcol[k];
   const int i1 = is % d.n1, i2 = is / d.n1, j1 = js % d.n1, j2 = js / d.n1;
   const int2 ra = d.pe1[d.kp1[k]], rb = d.pe2[d.kp2[k]];
@@ -288,7 +326,6 @@ __device__ __forceinline__ void item_p2d(const Dev &d, const double *__restrict_
   m21[1] = u[0] * v[2];
   const double m22 = u[0] * v[0];
   // M_ab[k][l], ab = 11, 12, 21, 22
-  double M[4][3][3];
   const double *J = d.jit;
 #pragma unroll
   for (int kk = 0; kk < 3; ++kk)
@@ -307,6 +344,63 @@ __device__ __forceinline__ void item_p2d(const Dev &d, const double *__restrict_
       M[2][kk][ll] = d.detj * J[kk * 3 + 2] * v21;
       M[3][kk][ll] = d.detj * J[kk * 3 + 2] * J[ll * 3 + 2] * m22;
     }
+}
+
+// The same moments on a curved shell (Assumption 2 with a curved mid-surface,
+// eq. extrusion): DF^{-T} and |DF| change from point to point and the basis may
+// be rational, so the moments are plain 2D Gauss sums over the shared
+// elements, M_ab[k][l] = sum_e sum_g w |DF| (G_a^i)_k (G_b^j)_l with
+// G_1 = DF^{-T} (dR/dxi1, dR/dxi2, 0) and G_2 = DF^{-T} (0, 0, R) (eq. B_2).
+__device__ __forceinline__ void shell_moments(const Dev &d, int64_t k, double (&M)[4][3][3]) {
+  const int is = d.krow[k], js = d.kcol[k];
+  const int i1 = is % d.n1, i2 = is / d.n1, j1 = js % d.n1, j2 = js / d.n1;
+  const int2 ra = d.pe1[d.kp1[k]], rb = d.pe2[d.kp2[k]];
+  const int P1 = d.p1 + 1;
+#pragma unroll
+  for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+    for (int e = 0; e < 9; ++e) M[ab][e / 3][e % 3] = 0.0;
+  for (int e2 = rb.x; e2 < rb.x + rb.y; ++e2) {
+    const int f2 = d.e2first[e2];
+    for (int e1 = ra.x; e1 < ra.x + ra.y; ++e1) {
+      const int f1 = d.e1first[e1];
+      const int64_t e = e1 + (int64_t)d.ne1 * e2;
+      const int bi = (i2 - f2) * P1 + (i1 - f1), bj = (j2 - f2) * P1 + (j1 - f1);
+      for (int g = 0; g < d.ngp; ++g) {
+        const double *G = d.gtab + (e * d.ngp + g) * 10;
+        const double *ri = d.rtab + ((e * d.ngp + g) * d.nb + bi) * 3;
+        const double *rj = d.rtab + ((e * d.ngp + g) * d.nb + bj) * 3;
+        double vi[2][3], vj[2][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          vi[0][c] = G[c * 3] * ri[1] + G[c * 3 + 1] * ri[2];
+          vi[1][c] = G[c * 3 + 2] * ri[0];
+          vj[0][c] = G[c * 3] * rj[1] + G[c * 3 + 1] * rj[2];
+          vj[1][c] = G[c * 3 + 2] * rj[0];
+        }
+        const double w = G[9];
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+          for (int ll = 0; ll < 3; ++ll) {
+            M[0][kk][ll] += w * vi[0][kk] * vj[0][ll];
+            M[1][kk][ll] += w * vi[0][kk] * vj[1][ll];
+            M[2][kk][ll] += w * vi[1][kk] * vj[0][ll];
+            M[3][kk][ll] += w * vi[1][kk] * vj[1][ll];
+          }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void p2d_one(const Dev &d, const double *__restrict__ Ec, double *__restrict__ Pt,
+                                        double *__restrict__ Mt, int64_t k, int write_p) {
+  if (k >= d.nnz2) return;
+  double M[4][3][3];
+  if (d.shell)
+    shell_moments(d, k, M);
+  else
+    affine_moments(d, k, M);
   // component-major tables: consecutive threads (k) store consecutive addresses
 #pragma unroll
   for (int ab = 0; ab < 4; ++ab)
@@ -334,12 +428,15 @@ __device__ __forceinline__ void item_p2d(const Dev &d, const double *__restrict_
 //   Qc[zk][j][ab] = sum_{cells c shared by it, jt} w_{s,ply(c)} sum_g w_g tau_a^{it} tau_b^{jt}
 // with tau_1 = T, tau_2 = dT/dxi3, a on the test function it, and
 // w_{s,l} = [set of l == s] (bucket) or [mat(l) == mat(s)] * harmonic_s(theta_l).
-// register mode: one entry per chunk set slot (zeros where the slot's set
-// does not act on the pair); LDS mode: one per set active on the row
-__device__ inline int q1d_width(const Dev &d) { return d.kron_nsc > 0 ? d.kron_nsc : d.maxact; }
-
-__device__ __forceinline__ void item_q1d(const Dev &d, const double *__restrict__ theta, int64_t idx) {
-  const int width = q1d_width(d);
+// One wave per entry (thickness nonzero zk, set slot j): the lanes split the
+// cells the pair shares (with one thickness element through many plies every
+// ply is such a cell, so a single thread would sum m (q+1) terms in turn) and
+// a fixed butterfly over the wave adds the lanes' sums (deterministic).
+__device__ __forceinline__ void q1d_wave(const Dev &d, const double *__restrict__ theta, int64_t idx, int lane) {
+  // register mode: one entry per chunk set slot (zeros where the slot's set
+  // does not act on the pair); LDS mode: one per set active on the row
+  const int width = d.kron_nsc > 0 ? d.kron_nsc : d.maxact;
+  if (idx >= d.nnzz * width) return;  // uniform over the wave
   const int zk = (int)(idx / width), j = (int)(idx % width);
   const int it = d.zkrow[zk], jt = d.zcol[zk];
   int s = -1;
@@ -353,10 +450,12 @@ __device__ __forceinline__ void item_q1d(const Dev &d, const double *__restrict_
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (s >= 0) {
     const int Q1 = d.q + 1;
-    for (int ci = d.zcptr[zk]; ci < d.zcptr[zk + 1]; ++ci) {
+    for (int ci = d.zcptr[zk] + lane; ci < d.zcptr[zk + 1]; ci += 64) {
       const int c = d.zcell[ci], l = d.zply[c];
       double wgt;
-      if (d.set_mode == LAM_SETS_BUCKET) {
+      if (d.harm_ply) {
+        wgt = l == s ? 1.0 : 0.0;  // the scatter's sets are the plies
+      } else if (d.set_mode == LAM_SETS_BUCKET) {
         wgt = d.ply_set[l] == s ? 1.0 : 0.0;
       } else {
         wgt = d.ply_mat[l] == d.set_mat[s] ? harmonic_weight(d.n_harm, d.set_aux[s], theta[l]) : 0.0;
@@ -379,16 +478,23 @@ __device__ __forceinline__ void item_q1d(const Dev &d, const double *__restrict_
       acc[3] += wgt * q22;
     }
   }
-  double *o = d.Qc + 4 * idx;
-  o[0] = acc[0];
-  o[1] = acc[1];
-  o[2] = acc[2];
-  o[3] = acc[3];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[e] += __shfl_xor(acc[e], off, 64);
+  if (lane == 0) {
+    double *o = d.Qc + 4 * idx;
+    o[0] = acc[0];
+    o[1] = acc[1];
+    o[2] = acc[2];
+    o[3] = acc[3];
+  }
 }
 
 
 constexpr int KRON_THREADS = 256;  // 3 * tile_k <= KRON_THREADS
 constexpr int KRON_AB = 5;         // thickness columns per register block
+
 
 // One thickness row of the register-mode scatter with its width LZ known at
 // compile time (no per-column predicates): value (x, r) = sum over the
@@ -416,100 +522,102 @@ __device__ __forceinline__ void kron_row(const double *qq, const double (&pr)[NS
     for (int x = 0; x < LZ; ++x) out[r * rstride + (int64_t)x * astride] = acc[x][r];
 }
 
-// Register mode of the scatter for one (tile, group of chunks) item: the
-// group's slot-dense coefficients Qd[zk][slot][ab] and the bracket
-// coefficients of the group's sets are staged in LDS behind one barrier; then
-// per chunk each thread contracts P of the chunk's NSC set slots for its (k, t)
-// into registers and writes the chunk's rows, with no vector load after the
-// barrier.  Block-cooperative: every thread of the block calls it with the same
-// item (it contains a barrier); lq holds kron_lds_q bytes of coefficients,
-// then 81 doubles per set of the group and 81 zeros.
+
+// Register-mode scatter of one (tile of whole in-plane rows, group of
+// consecutive thickness chunks) item with one or two set slots per chunk (every
+// bucket and per-ply plan): the block stages the group's slot-dense
+// coefficients Qd[zk][slot][ab] and the bracket coefficients of the group's
+// sets in LDS behind one barrier; then per chunk each thread (in-plane nonzero
+// k, component t) contracts P of the chunk's slots from the set-independent
+// moments M_ab[kl] and the slot's brackets E_s[kl][rt] (eq. P; P is never
+// stored) and writes the chunk's rows.  After the barrier the block issues no
+// vector load, so no wait on a load also waits for the stores in flight.
+// Block-cooperative: every thread of the block calls it with the same item
+// (it holds a barrier; threads past 3 * tile_k return after it).  lq: LDS of
+// kron_lds_q bytes of coefficients, then 81 doubles per set of the group and
+// 81 zeros.  The single-laminate scatter and the batched one both run it.
 template <int NSC>
-__device__ __forceinline__ void item_kron_reg(const Dev &d, const double *__restrict__ qd, double *__restrict__ vals, int tile,
-                                     int g, double *lq, int sig, int nthreads) {
+__device__ __forceinline__ void kron_group(const Dev &d, const double *__restrict__ qd, double *__restrict__ vals,
+                                           int tile, int g, double *lq, int sig, int nthreads) {
   static_assert(NSC <= 2, "grouped scatter items keep at most two set slots");
   const int k0 = d.tiles[tile], tk = d.tiles[tile + 1] - k0;
   const bool act = sig < 3 * tk;
   const int kk = act ? sig / 3 : 0, t = act ? sig - 3 * kk : 0, k = k0 + kk;
-  // P of a chunk's set slots at (k, t) from the set-independent moments
-  // (loaded once per item) and the slot's bracket coefficients (eq. P); P is
-  // never stored
   double mv[4][9];
 #pragma unroll
   for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
     for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[(int64_t)(ab * 9 + kl) * d.nnz2 + k];
-  const int ch0 = d.group_ptr[g], ch1 = d.group_ptr[g + 1];
-  const int zk0 = d.zrow[d.chunk_ptr[ch0]], nq = 4 * NSC * (d.zrow[d.chunk_ptr[ch1]] - zk0);
-  const int s0 = d.group_sptr[g], ns = d.group_sptr[g + 1] - s0;
-  double *le = lq + d.kron_lds_q / 8;
-  for (int e = sig; e < 81 * (ns + 1); e += nthreads) {
-    const int u = e / 81;
-    le[e] = u < ns ? d.Ec[81 * (int64_t)d.group_set[s0 + u] + (e - 81 * u)] : 0.0;
-  }
-  for (int e = sig; e < nq; e += nthreads) lq[e] = qd[4 * (int64_t)NSC * zk0 + e];
   const int is = d.krow[k], sr = d.srow[is];
   const int Ls = d.srow[is + 1] - sr, off = 3 * (k - sr) + t;
   const int64_t astride = 3 * (int64_t)Ls;
+  double *le = lq + d.kron_lds_q / 8;
+  const int ch0 = d.group_ptr[g], ch1 = d.group_ptr[g + 1];
+  const int zk0 = d.zrow[d.chunk_ptr[ch0]], nq = 4 * NSC * (d.zrow[d.chunk_ptr[ch1]] - zk0);
+  const int s0 = d.group_sptr[g], ns = d.group_sptr[g + 1] - s0;
+  for (int e = sig; e < 81 * (ns + 1); e += nthreads) {
+    const int u = e / 81;
+    le[e] = u < ns ? d.Escat[81 * (int64_t)d.group_set[s0 + u] + (e - 81 * u)] : 0.0;
+  }
+  for (int e = sig; e < nq; e += nthreads) lq[e] = qd[4 * (int64_t)NSC * zk0 + e];
   __syncthreads();
-  if (act) {
-    double pr[NSC][4][3];
-    int slot_set[NSC];  // group-local set of each slot's P
+  if (!act) return;  // no barrier follows
+  double pr[NSC][4][3];
+  int slot_set[NSC];  // group-local set of each slot's P
 #pragma unroll
-    for (int u = 0; u < NSC; ++u) slot_set[u] = -1;
-    for (int ch = ch0; ch < ch1; ++ch) {
-      const int it0 = d.chunk_ptr[ch], it1 = d.chunk_ptr[ch + 1];
-      const int c0 = d.chunk_sptr[ch], nsc = d.chunk_sptr[ch + 1] - c0;
+  for (int u = 0; u < NSC; ++u) slot_set[u] = -1;
+  for (int ch = ch0; ch < ch1; ++ch) {
+    const int it0 = d.chunk_ptr[ch], it1 = d.chunk_ptr[ch + 1];
+    const int c0 = d.chunk_sptr[ch], nsc = d.chunk_sptr[ch + 1] - c0;
 #pragma unroll
-      for (int u = 0; u < NSC; ++u) {
-        const int ls = u < nsc ? d.chunk_lset[c0 + u] : ns;  // unused slots: the zero block
-        if (ls == slot_set[u]) continue;  // the slot keeps its set (and P) from the previous chunk
-        slot_set[u] = ls;
-        const double *eu = le + 81 * ls;
+    for (int u = 0; u < NSC; ++u) {
+      const int ls = u < nsc ? d.chunk_lset[c0 + u] : ns;  // unused slots: the zero block
+      if (ls == slot_set[u]) continue;  // the slot keeps its set (and P) from the previous chunk
+      slot_set[u] = ls;
+      const double *eu = le + 81 * ls;
 #pragma unroll
-        for (int ab = 0; ab < 4; ++ab)
+      for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
-          for (int r = 0; r < 3; ++r) {
-            double a = 0.0;
+        for (int r = 0; r < 3; ++r) {
+          double a = 0.0;
 #pragma unroll
-            for (int kl = 0; kl < 9; ++kl) a += mv[ab][kl] * eu[kl * 9 + 3 * r + t];
-            pr[u][ab][r] = a;
-          }
-      }
-      for (int it = it0; it < it1; ++it) {
-        const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
-        double *out = vals + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
-        const int64_t rstride = 3 * (int64_t)Lz * Ls;
-        const double *qz = lq + 4 * NSC * (zb - zk0);
-        switch (Lz) {  // thickness row widths q + 1 and 2q + 1 of q = 1..3, uniform over the block
-          case 2: kron_row<NSC, 2>(qz, pr, out, rstride, astride); break;
-          case 3: kron_row<NSC, 3>(qz, pr, out, rstride, astride); break;
-          case 4: kron_row<NSC, 4>(qz, pr, out, rstride, astride); break;
-          case 5: kron_row<NSC, 5>(qz, pr, out, rstride, astride); break;
-          default:
-            for (int ab0 = 0; ab0 < Lz; ab0 += KRON_AB) {
-              double acc[KRON_AB][3];
+          for (int kl = 0; kl < 9; ++kl) a += mv[ab][kl] * eu[kl * 9 + 3 * r + t];
+          pr[u][ab][r] = a;
+        }
+    }
+    for (int it = it0; it < it1; ++it) {
+      const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
+      double *out = vals + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
+      const int64_t rstride = 3 * (int64_t)Lz * Ls;
+      const double *qz = lq + 4 * NSC * (zb - zk0);
+      switch (Lz) {  // widths 2..5 (q + 1 up to q = 4, 2q + 1 up to q = 2) fixed; 7 and 9 take the loop
+        case 2: kron_row<NSC, 2>(qz, pr, out, rstride, astride); break;
+        case 3: kron_row<NSC, 3>(qz, pr, out, rstride, astride); break;
+        case 4: kron_row<NSC, 4>(qz, pr, out, rstride, astride); break;
+        case 5: kron_row<NSC, 5>(qz, pr, out, rstride, astride); break;
+        default:
+          for (int ab0 = 0; ab0 < Lz; ab0 += KRON_AB) {
+            double acc[KRON_AB][3];
 #pragma unroll
-              for (int x = 0; x < KRON_AB; ++x) {
-                acc[x][0] = acc[x][1] = acc[x][2] = 0.0;
-                if (ab0 + x < Lz) {
-                  const double *qq = lq + 4 * NSC * (zb + ab0 + x - zk0);
+            for (int x = 0; x < KRON_AB; ++x) {
+              acc[x][0] = acc[x][1] = acc[x][2] = 0.0;
+              if (ab0 + x < Lz) {
+                const double *qq = lq + 4 * NSC * (zb + ab0 + x - zk0);
 #pragma unroll
-                  for (int u = 0; u < NSC; ++u) {
-                    const double q0 = qq[4 * u], q1 = qq[4 * u + 1], q2 = qq[4 * u + 2], q3 = qq[4 * u + 3];
+                for (int u = 0; u < NSC; ++u) {
+                  const double q0 = qq[4 * u], q1 = qq[4 * u + 1], q2 = qq[4 * u + 2], q3 = qq[4 * u + 3];
 #pragma unroll
-                    for (int r = 0; r < 3; ++r)
-                      acc[x][r] += q0 * pr[u][0][r] + q1 * pr[u][1][r] + q2 * pr[u][2][r] + q3 * pr[u][3][r];
-                  }
+                  for (int r = 0; r < 3; ++r)
+                    acc[x][r] += q0 * pr[u][0][r] + q1 * pr[u][1][r] + q2 * pr[u][2][r] + q3 * pr[u][3][r];
                 }
               }
-#pragma unroll
-              for (int r = 0; r < 3; ++r)
-#pragma unroll
-                for (int x = 0; x < KRON_AB; ++x)
-                  if (ab0 + x < Lz) out[r * rstride + (int64_t)(ab0 + x) * astride] = acc[x][r];
             }
-        }
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+              for (int x = 0; x < KRON_AB; ++x)
+                if (ab0 + x < Lz) out[r * rstride + (int64_t)(ab0 + x) * astride] = acc[x][r];
+          }
       }
     }
   }

@@ -366,7 +366,7 @@ def profile_read():
 
 
 class BatchPlan:
-    """Many laminates assembled by one persistent kernel per memory wave.
+    """Many laminates assembled wave by wave (lam_batch_*).
 
     Laminate i's values are exactly those of Plan(lams[i]).assemble.  Waves
     are runs of consecutive laminates whose values plus scratch fit
@@ -440,12 +440,14 @@ class BatchPlan:
         return out
 
     def check(self):
-        """Raises if a dependency wait of the last wave gave up."""
-        e = ctypes.c_int32()
-        _check(lib().lam_batch_check(self._h, self.ws.data_ptr(), self.ws_bytes, ctypes.byref(e), _stream()),
+        """Reads and clears every laminate's status flags (lam_batch_check;
+        waits for the stream) and raises if an assembly since the last check
+        was given angles that a laminate's bucket sets cannot honour."""
+        f = ctypes.c_int32()
+        _check(lib().lam_batch_check(self._h, self.ws.data_ptr(), self.ws_bytes, ctypes.byref(f), _stream()),
                "lam_batch_check")
-        if e.value:
-            raise RuntimeError("batched assembly: a dependency wait timed out; values incomplete")
+        if f.value:
+            raise ValueError("lam_batch_check: " + "; ".join(m for b, m in CHECK_FLAGS.items() if f.value & b))
 
     def laminate_vals(self, i, wave_buf):
         o = self.vals_offset[i]

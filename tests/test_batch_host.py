@@ -85,7 +85,7 @@ def test_bad_arguments(L):
 
 def test_many_set_slots_unsupported(L):
     """Nine harmonic sets act on every thickness row: more than the two set
-    slots per chunk the persistent kernel holds."""
+    slots per chunk the batched scatter holds."""
     rng = np.random.default_rng(8)
     lam = W.random_small(rng, p=2, q=2, max_ply=3, n_mat=1)
     st, h, keep = _create(L, [W.config_q1_8x8(), lam], 0, mode="harmonic9")

@@ -1,4 +1,5 @@
-"""Batched assembly (one persistent kernel per memory wave) on the GPU.
+"""Batched assembly (lam_batch_*: per wave a prep, a 2D-moment and per-block-size
+scatter launches running the single-laminate device code) on the GPU.
 
 Bars: every laminate's values are bit-identical to its single-laminate
 lam_assemble (same arithmetic, other schedule), for one wave and for many
@@ -125,3 +126,22 @@ def test_uneven_batch_sampled_oracle(oracle, L):
             print("  laminate", i, lam.p1, lam.n_ply, "rel", "%.2e" % err, flush=True)
             worst = max(worst, err)
     assert worst <= TOL
+
+
+def test_batch_flags_disagreeing_bucket_angles(L):
+    """lam_batch_check reports a laminate whose bucket set was given two
+    different angles (and clears the flag); consistent angles pass."""
+    lams = _small_batch(n=5, seed=33)
+    lams[2] = W.plate(2, 3, 2, [0, 90, 0, 90], [W.material(W.CARBON)], [0] * 4, ne2=2, name="bucket4")
+    B = L.BatchPlan(lams, set_mode="bucket")
+    C_all, th_all = B.pack()
+    buf = torch.empty(B.max_wave_vals, dtype=torch.float64, device="cuda")
+    B.assemble_wave(0, C_all, th_all, buf)
+    B.check()
+    th = [np.array(lam.theta) for lam in lams]
+    th[2][2] += 0.25  # ply 2 leaves the set of ply 0
+    C_all, th_all = B.pack(thetas=th)
+    B.assemble_wave(0, C_all, th_all, buf)
+    with pytest.raises(ValueError, match="bucket set"):
+        B.check()
+    B.check()  # cleared
