@@ -39,12 +39,31 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, spec
 OUT_BUFFERS = 3              # output allocations the headline steps cycle through
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector / matrix, spec
-# Algorithmic flops of the standard 3D assembly (Sec. 2.4): per 3D element
-# with n_f local functions and n_q Gauss points, 2 n_q (54 n_f + 27 n_f (n_f+1)/2)
-# (D B for every function, then B^T (D B) for the symmetric half of the local
-# pairs).  Degree 2 in-plane, layerwise degree 2, 3x3x3 points on the 64x64
-# 32-ply plate: 131,072 elements x 629,856 = 8.26e10 flops, 340 per nonzero.
-STD_FLOPS_PER_NNZ_P2Q2 = 340.0
+
+
+def _standard_roofline(lam, nnz, ms):
+    """Roofline of the standard 3D assembly (Sec. 2.4) on this laminate: per 3D
+    cell (in-plane element x ply x thickness knot span) with n_f local
+    functions and n_q Gauss points, 2 n_q (54 n_f + 27 n_f (n_f + 1) / 2)
+    algorithmic FP64 flops (D B for every function, then B^T (D B) over the
+    symmetric half of the pairs), and a read-modify-write of its n_f^2 3x3
+    blocks (16 B per entry) after a zero fill of the values (8 B per nonzero).
+    The bound is the larger of the two times at the spec peaks."""
+    import numpy as np
+    brk = np.unique(np.concatenate([np.asarray(lam.k3, dtype=np.float64), np.asarray(lam.iface, dtype=np.float64)]))
+    ne1 = len(np.unique(np.asarray(lam.k1))) - 1
+    ne2 = len(np.unique(np.asarray(lam.k2))) - 1
+    cells = ne1 * ne2 * (len(brk) - 1)
+    ng = [g if g else d + 1 for g, d in zip(getattr(lam, "ng", (0, 0, 0)), (lam.p1, lam.p2, lam.q))]
+    nq = ng[0] * ng[1] * ng[2]
+    nf = (lam.p1 + 1) * (lam.p2 + 1) * (lam.q + 1)
+    flops = cells * 2.0 * nq * (54 * nf + 27 * nf * (nf + 1) / 2)
+    rmw = cells * nf * nf * 9 * 16.0 + 8.0 * nnz
+    t_f = flops / (FP64_PEAK_TFLOPS * 1e12) * 1e3
+    t_m = rmw / (HBM_PEAK_GBS * 1e9) * 1e3
+    return {"flops": flops, "rmw_bytes": rmw, "fp64_bound_ms": t_f, "hbm_bound_ms": t_m,
+            "roofline_ms": max(t_f, t_m), "frac": max(t_f, t_m) / ms,
+            "fp64_tflops_algorithmic": flops / (ms * 1e-3) / 1e12}
 
 
 def _parse():
@@ -166,7 +185,8 @@ def _adjoint_workload(torch, np, L, W, O, steps, warmup):
         if mode == "bucket":
             ms_std, _ = _time_steps(torch, lambda: plan.assemble_standard(C, th, out=vals), 3, 1, L, "standard")
             res["standard"] = {"ms_per_step": ms_std, "nnz_per_s": plan.nnz / (ms_std * 1e-3),
-                               "speedup_fast_vs_standard": ms_std / ms}
+                               "speedup_fast_vs_standard": ms_std / ms,
+                               "roofline": _standard_roofline(lam, plan.nnz, ms_std)}
         del vals, plan
         torch.cuda.empty_cache()
     plan = L.Plan(lam, set_mode="bucket")
@@ -370,6 +390,7 @@ def _shell_workloads(torch, np, L, W, O, steps, warmup):
         if std:
             ms_std, _ = _time_steps(torch, lambda: plan.assemble_standard(C, th, out=vals), 3, 1, L, "standard")
             rec["standard"] = {"ms_per_step": ms_std, "speedup_fast_vs_standard": ms_std / ms,
+                               "roofline": _standard_roofline(lam, plan.nnz, ms_std),
                                "parity_sample_relF": _sample_parity(O, lam, plan, vals, rowptr, n_rows=50)}
         out[key] = rec
         print("shell %s: %.3f ms" % (key, ms), file=sys.stderr, flush=True)
@@ -505,11 +526,9 @@ def _c2_workload(torch, np, L, W, O, args):
     try:
         ms_std, ms_std_k = _time_steps(torch, lambda: plan.assemble_standard(C, th, out=vals),
                                        max(3, args.steps // 4), 1, L, "standard")
-        flops = STD_FLOPS_PER_NNZ_P2Q2 * plan.nnz
         res["standard"] = {"nnz_per_s": plan.nnz / (ms_std * 1e-3), "ms_per_step": ms_std,
                            "speedup_fast_vs_standard": ms_std / ms, "element_kernel_ms": ms_std_k,
-                           "fp64_tflops_algorithmic": flops / (ms_std * 1e-3) / 1e12,
-                           "fp64_frac": flops / (ms_std * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
+                           "roofline": _standard_roofline(lam, plan.nnz, ms_std)}
     except L.LamError as e:
         res["standard"] = {"skipped": str(e)}
     del vals, rowptr, colind, plan
@@ -601,6 +620,7 @@ def main():
             extra["standard_same_plate"] = {"ms_per_step": ms_std, "nnz_per_s": plan.nnz / (ms_std * 1e-3),
                                             "speedup_fast_vs_standard": ms_std / ms_step,
                                             "element_kernel_ms": ms_std_k,
+                                            "roofline": _standard_roofline(lam, plan.nnz, ms_std),
                                             "parity_sample_relF": _sample_parity(O, lam, plan, vals, rowptr,
                                                                                  n_rows=50)}
         except L.LamError as e:

@@ -511,11 +511,17 @@ __global__ void __launch_bounds__(KRON_THREADS) k_apply(Dev d, const double *__r
 // the ply cells inside the span; elements of one colour
 // (e1 mod p1+1, e2 mod p2+1, span mod q+1) share no basis function, so a
 // launch per colour adds its element matrices into the CSR without atomics.
-// Per cell, the physical gradients of the (p1+1)(p2+1)(q+1) local functions
-// at the (ng1 ng2 ngz) Gauss points go to LDS; a thread per local pair (a, b)
-// accumulates the moments m_kl = sum_g w_g G_a(g)_k G_b(g)_l and, the ply's
-// tensor being constant in the cell, the block K_ab[r][t] += sum_kl m_kl E_l[kl][rt].
+// Per cell, the physical gradients G_a(g) of the nloc = (p1+1)(p2+1)(q+1)
+// local functions at the Gauss points and the weights go to LDS, with the
+// ply's bracket coefficients E (its tensor is constant in the cell).  A thread
+// takes STD_LA test functions a against one trial function b and accumulates
+// the moments m_a[kl] = sum_g w_g G_a(g)_k G_b(g)_l (the test functions'
+// gradients are the same for the lanes of a wave: broadcast reads), then adds
+// the blocks K_ab[r][t] = sum_kl m_a[kl] E[kl][rt] into the CSR.  When the
+// table of all points does not fit the LDS budget (degree 4), the points are
+// taken in chunks and the table is rebuilt for every chunk and pass.
 constexpr int STD_THREADS = 256;
+constexpr int STD_LA = 4;  // test functions per thread
 
 __global__ void k_fill_zero(double *__restrict__ v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -523,93 +529,115 @@ __global__ void k_fill_zero(double *__restrict__ v, int64_t n) {
 }
 
 __global__ void __launch_bounds__(STD_THREADS) k_std3d(Dev d, double *__restrict__ vals, int c1, int c2, int c3,
-                                                       int n1c, int n2c) {
+                                                       int n1c, int n2c, int gchunk) {
   extern __shared__ double sm[];
   const int P1 = d.p1 + 1, P2 = d.p2 + 1, Q1 = d.q + 1;
   const int nloc = P1 * P2 * Q1, ng = d.ng1 * d.ng2 * d.ngz;
-  double *G = sm;              // [ng][nloc][3]
-  double *W = sm + ng * nloc * 3;  // [ng]
+  double *G = sm;                           // [gchunk][nloc][3]
+  double *W = sm + (int64_t)gchunk * nloc * 3;  // [gchunk]
+  double *Es = W + gchunk;                  // [81]
   const int b = blockIdx.x;
   const int e1 = c1 + P1 * (b % n1c), e2 = c2 + P2 * ((b / n1c) % n2c), zsp = c3 + Q1 * (b / (n1c * n2c));
   const int f1 = d.e1first[e1], f2 = d.e2first[e2], fz = d.zs_first[zsp];
-  const int npairs = nloc * nloc;
-  for (int p0 = 0; p0 < npairs; p0 += STD_THREADS) {
-    const int pair = p0 + (int)threadIdx.x;
-    const bool valid = pair < npairs;
-    const int la = valid ? pair / nloc : 0, lb = valid ? pair - la * nloc : 0;
-    double ke[9];
-#pragma unroll
-    for (int e = 0; e < 9; ++e) ke[e] = 0.0;
-    for (int ci = d.zs_cptr[zsp]; ci < d.zs_cptr[zsp + 1]; ++ci) {
-      const int c = d.zs_cell[ci], ply = d.zply[c];
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < ng * nloc; idx += STD_THREADS) {
-        const int g = idx / nloc, a = idx - g * nloc;
-        const int g1 = g % d.ng1, g2 = (g / d.ng1) % d.ng2, gz = g / (d.ng1 * d.ng2);
-        const int a1 = a % P1, a2 = (a / P1) % P2, at = a / (P1 * P2);
-        const double *t3 = d.ztab + (((int64_t)c * d.ngz + gz) * Q1 + at) * 2;
-        double gh[3];
-        const double *Jt;  // DF^{-T} at the point
-        double wpt;        // in-plane weight times |DF|
-        if (d.shell) {     // per-point map gradient and (possibly rational) in-plane basis
-          const int64_t ep = ((int64_t)e1 + (int64_t)d.ne1 * e2) * d.ngp + g1 + d.ng1 * g2;
-          const double *rt = d.rtab + (ep * d.nb + a1 + P1 * a2) * 3;
-          gh[0] = rt[1] * t3[0];
-          gh[1] = rt[2] * t3[0];
-          gh[2] = rt[0] * t3[1];
-          Jt = d.gtab + ep * 10;
-          wpt = Jt[9];
-        } else {
-          const double *t1 = d.tab1 + (((int64_t)e1 * d.ng1 + g1) * P1 + a1) * 2;
-          const double *t2 = d.tab2 + (((int64_t)e2 * d.ng2 + g2) * P2 + a2) * 2;
-          gh[0] = t1[1] * t2[0] * t3[0];
-          gh[1] = t1[0] * t2[1] * t3[0];
-          gh[2] = t1[0] * t2[0] * t3[1];
-          Jt = d.jit;
-          wpt = d.w1[(int64_t)e1 * d.ng1 + g1] * d.w2[(int64_t)e2 * d.ng2 + g2] * d.detj;
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-          G[(g * nloc + a) * 3 + k] = Jt[k * 3 + 0] * gh[0] + Jt[k * 3 + 1] * gh[1] + Jt[k * 3 + 2] * gh[2];
-        if (a == 0) W[g] = wpt * d.zw[(int64_t)c * d.ngz + gz];
+  const int ntask = ((nloc + STD_LA - 1) / STD_LA) * nloc;
+  const bool whole = gchunk >= ng;  // every point's table at once: built once per cell
+  // the table of points g0 .. g0 + gn - 1 of cell c
+  auto build = [&](int c, int g0, int gn) {
+    for (int idx = threadIdx.x; idx < gn * nloc; idx += STD_THREADS) {
+      const int gl = idx / nloc, a = idx - gl * nloc, g = g0 + gl;
+      const int g1 = g % d.ng1, g2 = (g / d.ng1) % d.ng2, gz = g / (d.ng1 * d.ng2);
+      const int a1 = a % P1, a2 = (a / P1) % P2, at = a / (P1 * P2);
+      const double *t3 = d.ztab + (((int64_t)c * d.ngz + gz) * Q1 + at) * 2;
+      double gh[3];
+      const double *Jt;  // DF^{-T} at the point
+      double wpt;        // in-plane weight times |DF|
+      if (d.shell) {     // per-point map gradient and (possibly rational) in-plane basis
+        const int64_t ep = ((int64_t)e1 + (int64_t)d.ne1 * e2) * d.ngp + g1 + d.ng1 * g2;
+        const double *rt = d.rtab + (ep * d.nb + a1 + P1 * a2) * 3;
+        gh[0] = rt[1] * t3[0];
+        gh[1] = rt[2] * t3[0];
+        gh[2] = rt[0] * t3[1];
+        Jt = d.gtab + ep * 10;
+        wpt = Jt[9];
+      } else {
+        const double *t1 = d.tab1 + (((int64_t)e1 * d.ng1 + g1) * P1 + a1) * 2;
+        const double *t2 = d.tab2 + (((int64_t)e2 * d.ng2 + g2) * P2 + a2) * 2;
+        gh[0] = t1[1] * t2[0] * t3[0];
+        gh[1] = t1[0] * t2[1] * t3[0];
+        gh[2] = t1[0] * t2[0] * t3[1];
+        Jt = d.jit;
+        wpt = d.w1[(int64_t)e1 * d.ng1 + g1] * d.w2[(int64_t)e2 * d.ng2 + g2] * d.detj;
       }
-      __syncthreads();
-      if (valid) {
-        double m[9];
 #pragma unroll
-        for (int e = 0; e < 9; ++e) m[e] = 0.0;
-        for (int g = 0; g < ng; ++g) {
-          const double w = W[g];
-          const double *ga = G + (g * nloc + la) * 3, *gb = G + (g * nloc + lb) * 3;
-          const double wa0 = w * ga[0], wa1 = w * ga[1], wa2 = w * ga[2];
-          const double b0 = gb[0], b1 = gb[1], b2 = gb[2];
-          m[0] += wa0 * b0; m[1] += wa0 * b1; m[2] += wa0 * b2;
-          m[3] += wa1 * b0; m[4] += wa1 * b1; m[5] += wa1 * b2;
-          m[6] += wa2 * b0; m[7] += wa2 * b1; m[8] += wa2 * b2;
-        }
-        const double *E = d.Eply + 81 * ply;
-#pragma unroll
-        for (int rt = 0; rt < 9; ++rt) {
-          double acc = 0.0;
-#pragma unroll
-          for (int kl = 0; kl < 9; ++kl) acc += m[kl] * E[kl * 9 + rt];
-          ke[rt] += acc;
-        }
-      }
+      for (int k = 0; k < 3; ++k)
+        G[((int64_t)gl * nloc + a) * 3 + k] = Jt[k * 3 + 0] * gh[0] + Jt[k * 3 + 1] * gh[1] + Jt[k * 3 + 2] * gh[2];
+      if (a == 0) W[gl] = wpt * d.zw[(int64_t)c * d.ngz + gz];
     }
-    if (valid) {
-      const int i1 = f1 + la % P1, i2 = f2 + (la / P1) % P2, it = fz + la / (P1 * P2);
-      const int j1 = f1 + lb % P1, j2 = f2 + (lb / P1) % P2, jt = fz + lb / (P1 * P2);
-      const int is = i1 + d.n1 * i2;
-      const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
-      const int sr = d.srow[is], Ls = d.srow[is + 1] - sr;
-      const int az = jt - d.zcol[zb];
-      const int bs = (j2 - d.a2f[i2]) * d.a1c[i1] + (j1 - d.a1f[i1]);
-      double *row = vals + 9 * d.nnz2 * (int64_t)zb + 3 * (int64_t)Lz * 3 * sr + (int64_t)az * 3 * Ls + 3 * bs;
+  };
+  for (int ci = d.zs_cptr[zsp]; ci < d.zs_cptr[zsp + 1]; ++ci) {
+    const int c = d.zs_cell[ci], ply = d.zply[c];
+    __syncthreads();  // the previous cell's tables are no longer read
+    for (int e = threadIdx.x; e < 81; e += STD_THREADS) Es[e] = d.Eply[81 * ply + e];
+    if (whole) build(c, 0, ng);
+    for (int t0 = 0; t0 < ntask; t0 += STD_THREADS) {
+      const int task = t0 + (int)threadIdx.x;
+      const bool valid = task < ntask;
+      const int lb = valid ? task % nloc : 0, la0 = valid ? STD_LA * (task / nloc) : 0;
+      double m[STD_LA][9];
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
+      for (int u = 0; u < STD_LA; ++u)
 #pragma unroll
-        for (int t = 0; t < 3; ++t) row[(int64_t)r * 3 * Lz * Ls + t] += ke[r * 3 + t];
+        for (int e = 0; e < 9; ++e) m[u][e] = 0.0;
+      for (int g0 = 0; g0 < ng; g0 += gchunk) {
+        const int gn = ng - g0 < gchunk ? ng - g0 : gchunk;
+        if (!whole) {
+          __syncthreads();
+          build(c, g0, gn);
+        }
+        __syncthreads();
+        if (valid)
+          for (int g = 0; g < gn; ++g) {
+            const double w = W[g];
+            const double *gb = G + ((int64_t)g * nloc + lb) * 3;
+            const double b0 = gb[0], b1 = gb[1], b2 = gb[2];
+#pragma unroll
+            for (int u = 0; u < STD_LA; ++u) {
+              const int la = la0 + u < nloc ? la0 + u : nloc - 1;  // past the last: a valid read, unused
+              const double *ga = G + ((int64_t)g * nloc + la) * 3;
+              const double wa0 = w * ga[0], wa1 = w * ga[1], wa2 = w * ga[2];
+              m[u][0] += wa0 * b0; m[u][1] += wa0 * b1; m[u][2] += wa0 * b2;
+              m[u][3] += wa1 * b0; m[u][4] += wa1 * b1; m[u][5] += wa1 * b2;
+              m[u][6] += wa2 * b0; m[u][7] += wa2 * b1; m[u][8] += wa2 * b2;
+            }
+          }
+      }
+      if (valid) {
+        const int j1 = f1 + lb % P1, j2 = f2 + (lb / P1) % P2, jt = fz + lb / (P1 * P2);
+#pragma unroll
+        for (int u = 0; u < STD_LA; ++u) {
+          const int la = la0 + u;
+          if (la >= nloc) break;
+          double ke[9];
+#pragma unroll
+          for (int rt = 0; rt < 9; ++rt) {
+            double acc = 0.0;
+#pragma unroll
+            for (int kl = 0; kl < 9; ++kl) acc += m[u][kl] * Es[kl * 9 + rt];
+            ke[rt] = acc;
+          }
+          const int i1 = f1 + la % P1, i2 = f2 + (la / P1) % P2, it = fz + la / (P1 * P2);
+          const int is = i1 + d.n1 * i2;
+          const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
+          const int sr = d.srow[is], Ls = d.srow[is + 1] - sr;
+          const int az = jt - d.zcol[zb];
+          const int bs = (j2 - d.a2f[i2]) * d.a1c[i1] + (j1 - d.a1f[i1]);
+          double *row = vals + 9 * d.nnz2 * (int64_t)zb + 3 * (int64_t)Lz * 3 * sr + (int64_t)az * 3 * Ls + 3 * bs;
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int t = 0; t < 3; ++t) row[(int64_t)r * 3 * Lz * Ls + t] += ke[r * 3 + t];
+        }
+      }
     }
   }
 }
@@ -1414,8 +1442,12 @@ extern "C" LAM_API lam_status lam_assemble_standard(const lam_plan *p, void *ws,
   if (nnz != p->nnz) return LAM_ESIZE;
   const int P1 = p->p1 + 1, P2 = p->p2 + 1, Q1 = p->q + 1;
   const int nloc = P1 * P2 * Q1, ng = p->ng1 * p->ng2 * p->ngz;
-  const size_t lds = sizeof(double) * ((size_t)ng * nloc * 3 + ng);
-  if (lds > 160 * 1024 || p->mat_field) return LAM_EUNSUP;
+  if (p->mat_field) return LAM_EUNSUP;
+  // the points' gradient table in LDS: all of them if within the budget
+  // (two blocks per compute unit), else chunks of points
+  const int64_t budget = 72 * 1024, per_pt = sizeof(double) * (3 * (int64_t)nloc + 1), fixed = sizeof(double) * 81;
+  const int gchunk = (int)std::max<int64_t>(1, std::min<int64_t>(ng, (budget - fixed) / per_pt));
+  const size_t lds = (size_t)(gchunk * per_pt + fixed);
   hipStream_t s = static_cast<hipStream_t>(stream);
   Dev d = make_dev(p, ws);
   void *prof = lam::profile_begin(1, stream);
@@ -1428,7 +1460,8 @@ extern "C" LAM_API lam_status lam_assemble_standard(const lam_plan *p, void *ws,
         const int n3c = (p->nzs - c3 + Q1 - 1) / Q1;
         const int64_t nb = (int64_t)n1c * n2c * n3c;
         if (nb <= 0) continue;
-        hipLaunchKernelGGL(k_std3d, dim3((unsigned)nb), dim3(STD_THREADS), lds, s, d, vals, c1, c2, c3, n1c, n2c);
+        hipLaunchKernelGGL(k_std3d, dim3((unsigned)nb), dim3(STD_THREADS), lds, s, d, vals, c1, c2, c3, n1c, n2c,
+                           gchunk);
       }
   lam::profile_end(prof, stream);
   return hip_status();

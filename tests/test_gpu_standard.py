@@ -29,13 +29,22 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b), np.abs(a - b).max() / np.abs(b).max()
 
 
-@pytest.mark.parametrize("case", range(6))
+@pytest.mark.parametrize("case", range(9))
 def test_standard_matches_oracle(oracle, L, case):
+    """Cases 6-8 are degree 4 (the gradient table of all points exceeds the
+    LDS budget: the kernel takes the points in chunks), in layerwise and
+    one-element-through-the-thickness spaces."""
     rng = np.random.default_rng(3000 + case)
     if case == 0:
         lam = W.config_q1_8x8()
     elif case == 1:
         lam = W.plate(2, 5, 2, [0, 45, 90], [W.material(W.CARBON), W.material(W.GLASS)], [0, 1, 0], ne2=4)
+    elif case == 6:
+        lam = W.plate(4, 3, 2, [0, 45, 90], [W.material(W.CARBON), W.material(W.GLASS)], [0, 1, 0], ne2=2)
+    elif case == 7:
+        lam = W.paper_plate(4, 2, 3, "0/45/-45/90")
+    elif case == 8:
+        lam = W.random_small(rng, p=4, q=4, max_ply=3)
     else:
         lam = W.random_small(rng, paper_regime=(case % 2 == 1), max_ply=4)
     print("case", case, lam.p1, lam.p2, lam.q, lam.n_ply, flush=True)
