@@ -42,23 +42,27 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector / matrix, spec
 
 
 def _standard_roofline(lam, nnz, ms):
-    """Roofline of the standard 3D assembly (Sec. 2.4) on this laminate: per 3D
-    cell (in-plane element x ply x thickness knot span) with n_f local
-    functions and n_q Gauss points, 2 n_q (54 n_f + 27 n_f (n_f + 1) / 2)
+    """Roofline of the standard 3D assembly (Sec. 2.4) on this laminate.  Flops
+    per ply cell (in-plane element x ply x thickness knot span) with n_f local
+    functions and n_q Gauss points: 2 n_q (54 n_f + 27 n_f (n_f + 1) / 2)
     algorithmic FP64 flops (D B for every function, then B^T (D B) over the
-    symmetric half of the pairs), and a read-modify-write of its n_f^2 3x3
-    blocks (16 B per entry) after a zero fill of the values (8 B per nonzero).
-    The bound is the larger of the two times at the spec peaks."""
+    symmetric half of the pairs).  Bytes: a zero fill of the values (8 B per
+    nonzero) and a read-modify-write of each 3D element's n_f^2 3x3 blocks
+    (16 B per entry; an element is an in-plane element x a thickness knot span
+    and holds the ply cells inside the span).  The bound is the larger of the
+    two times at the spec peaks."""
     import numpy as np
-    brk = np.unique(np.concatenate([np.asarray(lam.k3, dtype=np.float64), np.asarray(lam.iface, dtype=np.float64)]))
+    k3 = np.unique(np.asarray(lam.k3, dtype=np.float64))
+    brk = np.unique(np.concatenate([k3, np.asarray(lam.iface, dtype=np.float64)]))
     ne1 = len(np.unique(np.asarray(lam.k1))) - 1
     ne2 = len(np.unique(np.asarray(lam.k2))) - 1
     cells = ne1 * ne2 * (len(brk) - 1)
+    elems = ne1 * ne2 * (len(k3) - 1)
     ng = [g if g else d + 1 for g, d in zip(getattr(lam, "ng", (0, 0, 0)), (lam.p1, lam.p2, lam.q))]
     nq = ng[0] * ng[1] * ng[2]
     nf = (lam.p1 + 1) * (lam.p2 + 1) * (lam.q + 1)
     flops = cells * 2.0 * nq * (54 * nf + 27 * nf * (nf + 1) / 2)
-    rmw = cells * nf * nf * 9 * 16.0 + 8.0 * nnz
+    rmw = elems * nf * nf * 9 * 16.0 + 8.0 * nnz
     t_f = flops / (FP64_PEAK_TFLOPS * 1e12) * 1e3
     t_m = rmw / (HBM_PEAK_GBS * 1e9) * 1e3
     return {"flops": flops, "rmw_bytes": rmw, "fp64_bound_ms": t_f, "hbm_bound_ms": t_m,

@@ -221,7 +221,8 @@ LAM_API lam_status lam_assemble_static(const lam_plan *plan, void *ws, int64_t w
 /* Standard 3D assembly (Sec. 2.4): element by element over every
  * (in-plane element x ply x thickness knot span) cell with the tensor Gauss
  * rule, element matrices added into the same CSR (colour by colour, no
- * atomics).  Same arguments and output as lam_assemble. */
+ * atomics: the values do not depend on the schedule).  Same arguments and
+ * output as lam_assemble; LAM_EUNSUP for in-plane material fields. */
 LAM_API lam_status lam_assemble_standard(const lam_plan *plan, void *ws, int64_t ws_bytes, const double *C,
                                          const double *theta, double *vals, int64_t nnz, void *stream);
 

@@ -169,6 +169,10 @@ extern "C" LAM_API lam_status lam_batch_create_tuned(int32_t n, const lam_lamina
   for (int i = 0; i < n; ++i) {
     lam_plan *p = nullptr;
     lam_tuning t = tunings ? tunings[i] : lam_tuning{0, 0, 0, 0};
+    if (!lam::tuning_ok(&t)) {
+      lam_batch_destroy(B);
+      return LAM_EINVAL;
+    }
     t.set_slots = 2;
     lam_status st = lam::plan_create(&descs[i], &t, 2, &p);
     if (st != LAM_OK) {

@@ -77,6 +77,8 @@ struct Layout {
 // min_nsc = 1.
 lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int min_nsc, lam_plan **out,
                        const lam_shell *shell = nullptr);
+// Every field of a tuning within its documented range (NULL: automatic, valid).
+bool tuning_ok(const lam_tuning *t);
 
 // Kernel timing hooks (profile.cpp): a slot recorded around the dominant
 // kernel of entry point `which` (0 assemble, 1 standard, 2 adjoint).

@@ -506,140 +506,300 @@ __global__ void __launch_bounds__(KRON_THREADS) k_apply(Dev d, const double *__r
 }
 
 // ---------------------------------------------------------------------------
-// Standard 3D assembly (the comparator of the method, Sec. 2.4).  One block
-// per 3D element = (in-plane element e1, e2) x (thickness knot span), with all
-// the ply cells inside the span; elements of one colour
-// (e1 mod p1+1, e2 mod p2+1, span mod q+1) share no basis function, so a
-// launch per colour adds its element matrices into the CSR without atomics.
-// Per cell, the physical gradients G_a(g) of the nloc = (p1+1)(p2+1)(q+1)
-// local functions at the Gauss points and the weights go to LDS, with the
-// ply's bracket coefficients E (its tensor is constant in the cell).  A thread
-// takes STD_LA test functions a against one trial function b and accumulates
-// the moments m_a[kl] = sum_g w_g G_a(g)_k G_b(g)_l (the test functions'
-// gradients are the same for the lanes of a wave: broadcast reads), then adds
-// the blocks K_ab[r][t] = sum_kl m_a[kl] E[kl][rt] into the CSR.  When the
-// table of all points does not fit the LDS budget (degree 4), the points are
-// taken in chunks and the table is rebuilt for every chunk and pass.
-constexpr int STD_THREADS = 256;
-constexpr int STD_LA = 4;  // test functions per thread
+// Standard 3D assembly (the comparator of the method, Sec. 2.4).  A 3D element
+// is (in-plane element e1, e2) x (thickness knot span) with the ply cells
+// inside the span.
+//
+// With the ply tensor constant in a cell, the element matrix of the cell is
+//   K_ab[r][t] = sum_kl M_kl(a, b) E[kl][rt],  M_kl(a, b) = sum_g w_g G_a(g)_k G_b(g)_l,
+// G_a(g) the physical gradient of local function a at Gauss point g and E the
+// ply's bracket coefficients.  M is a dense product over the points, done on
+// the FP64 matrix cores: the nloc local functions are cut into 16-wide tiles
+// and a wavefront takes one tile pair (I <= J) of an element at a time,
+// running the nine chains M_kl (k, l = 0..2) of v_mfma_f64_16x16x4f64, four
+// points per step: lane i + 16 kk holds the operands w G_a(g)_k for
+// a = 16 I + i and G_b(g)_l for b = 16 J + i at point g = 4 s + kk (read from
+// a gradient table the block builds in LDS, or evaluated in the lane from
+// the 1D or shell basis tables).  After each ply cell the
+// nine M tiles are contracted with that ply's E into the element matrix,
+// which is added to the CSR once: the tile (I, J) as K_ab and, for I < J, its
+// transpose as K_ba (K is symmetric: E[kl][rt] = E[lk][tr]).  Padded
+// functions and points carry zero operands.
+//
+// The adds are plain read-modify-writes, conflict-free by colouring (one
+// launch per colour: e1 mod p1 + 1, e2 mod p2 + 1, span mod q + 1; elements
+// of one colour share no basis function), so the result does not depend on
+// the schedule.
+
+// v_mfma_f64_16x16x4f64 leaves D[lane / 16 + 4 v][lane % 16] in item v of the lane
+typedef double std_dbl4 __attribute__((ext_vector_type(4)));
+constexpr int STD_WAVES = 4;      // wavefronts (tile pairs) per block, operands from the tables
+constexpr int STD_LDS_WAVES = 8;  // most tile pairs (one wavefront each) of the LDS-table kernel
 
 __global__ void k_fill_zero(double *__restrict__ v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     v[i] = 0.0;
 }
 
-__global__ void __launch_bounds__(STD_THREADS) k_std3d(Dev d, double *__restrict__ vals, int c1, int c2, int c3,
-                                                       int n1c, int n2c, int gchunk) {
-  extern __shared__ double sm[];
-  const int P1 = d.p1 + 1, P2 = d.p2 + 1, Q1 = d.q + 1;
-  const int nloc = P1 * P2 * Q1, ng = d.ng1 * d.ng2 * d.ngz;
-  double *G = sm;                           // [gchunk][nloc][3]
-  double *W = sm + (int64_t)gchunk * nloc * 3;  // [gchunk]
-  double *Es = W + gchunk;                  // [81]
-  const int b = blockIdx.x;
-  const int e1 = c1 + P1 * (b % n1c), e2 = c2 + P2 * ((b / n1c) % n2c), zsp = c3 + Q1 * (b / (n1c * n2c));
-  const int f1 = d.e1first[e1], f2 = d.e2first[e2], fz = d.zs_first[zsp];
-  const int ntask = ((nloc + STD_LA - 1) / STD_LA) * nloc;
-  const bool whole = gchunk >= ng;  // every point's table at once: built once per cell
-  // the table of points g0 .. g0 + gn - 1 of cell c
-  auto build = [&](int c, int g0, int gn) {
-    for (int idx = threadIdx.x; idx < gn * nloc; idx += STD_THREADS) {
-      const int gl = idx / nloc, a = idx - gl * nloc, g = g0 + gl;
-      const int g1 = g % d.ng1, g2 = (g / d.ng1) % d.ng2, gz = g / (d.ng1 * d.ng2);
-      const int a1 = a % P1, a2 = (a / P1) % P2, at = a / (P1 * P2);
-      const double *t3 = d.ztab + (((int64_t)c * d.ngz + gz) * Q1 + at) * 2;
-      double gh[3];
-      const double *Jt;  // DF^{-T} at the point
-      double wpt;        // in-plane weight times |DF|
-      if (d.shell) {     // per-point map gradient and (possibly rational) in-plane basis
-        const int64_t ep = ((int64_t)e1 + (int64_t)d.ne1 * e2) * d.ngp + g1 + d.ng1 * g2;
-        const double *rt = d.rtab + (ep * d.nb + a1 + P1 * a2) * 3;
-        gh[0] = rt[1] * t3[0];
-        gh[1] = rt[2] * t3[0];
-        gh[2] = rt[0] * t3[1];
-        Jt = d.gtab + ep * 10;
-        wpt = Jt[9];
-      } else {
-        const double *t1 = d.tab1 + (((int64_t)e1 * d.ng1 + g1) * P1 + a1) * 2;
-        const double *t2 = d.tab2 + (((int64_t)e2 * d.ng2 + g2) * P2 + a2) * 2;
-        gh[0] = t1[1] * t2[0] * t3[0];
-        gh[1] = t1[0] * t2[1] * t3[0];
-        gh[2] = t1[0] * t2[0] * t3[1];
-        Jt = d.jit;
-        wpt = d.w1[(int64_t)e1 * d.ng1 + g1] * d.w2[(int64_t)e2 * d.ng2 + g2] * d.detj;
-      }
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-        G[((int64_t)gl * nloc + a) * 3 + k] = Jt[k * 3 + 0] * gh[0] + Jt[k * 3 + 1] * gh[1] + Jt[k * 3 + 2] * gh[2];
-      if (a == 0) W[gl] = wpt * d.zw[(int64_t)c * d.ngz + gz];
-    }
-  };
-  for (int ci = d.zs_cptr[zsp]; ci < d.zs_cptr[zsp + 1]; ++ci) {
-    const int c = d.zs_cell[ci], ply = d.zply[c];
-    __syncthreads();  // the previous cell's tables are no longer read
-    for (int e = threadIdx.x; e < 81; e += STD_THREADS) Es[e] = d.Eply[81 * ply + e];
-    if (whole) build(c, 0, ng);
-    for (int t0 = 0; t0 < ntask; t0 += STD_THREADS) {
-      const int task = t0 + (int)threadIdx.x;
-      const bool valid = task < ntask;
-      const int lb = valid ? task % nloc : 0, la0 = valid ? STD_LA * (task / nloc) : 0;
-      double m[STD_LA][9];
-#pragma unroll
-      for (int u = 0; u < STD_LA; ++u)
-#pragma unroll
-        for (int e = 0; e < 9; ++e) m[u][e] = 0.0;
-      for (int g0 = 0; g0 < ng; g0 += gchunk) {
-        const int gn = ng - g0 < gchunk ? ng - g0 : gchunk;
-        if (!whole) {
-          __syncthreads();
-          build(c, g0, gn);
-        }
-        __syncthreads();
-        if (valid)
-          for (int g = 0; g < gn; ++g) {
-            const double w = W[g];
-            const double *gb = G + ((int64_t)g * nloc + lb) * 3;
-            const double b0 = gb[0], b1 = gb[1], b2 = gb[2];
-#pragma unroll
-            for (int u = 0; u < STD_LA; ++u) {
-              const int la = la0 + u < nloc ? la0 + u : nloc - 1;  // past the last: a valid read, unused
-              const double *ga = G + ((int64_t)g * nloc + la) * 3;
-              const double wa0 = w * ga[0], wa1 = w * ga[1], wa2 = w * ga[2];
-              m[u][0] += wa0 * b0; m[u][1] += wa0 * b1; m[u][2] += wa0 * b2;
-              m[u][3] += wa1 * b0; m[u][4] += wa1 * b1; m[u][5] += wa1 * b2;
-              m[u][6] += wa2 * b0; m[u][7] += wa2 * b1; m[u][8] += wa2 * b2;
-            }
-          }
-      }
-      if (valid) {
-        const int j1 = f1 + lb % P1, j2 = f2 + (lb / P1) % P2, jt = fz + lb / (P1 * P2);
-#pragma unroll
-        for (int u = 0; u < STD_LA; ++u) {
-          const int la = la0 + u;
-          if (la >= nloc) break;
-          double ke[9];
-#pragma unroll
-          for (int rt = 0; rt < 9; ++rt) {
-            double acc = 0.0;
-#pragma unroll
-            for (int kl = 0; kl < 9; ++kl) acc += m[u][kl] * Es[kl * 9 + rt];
-            ke[rt] = acc;
-          }
-          const int i1 = f1 + la % P1, i2 = f2 + (la / P1) % P2, it = fz + la / (P1 * P2);
-          const int is = i1 + d.n1 * i2;
-          const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
-          const int sr = d.srow[is], Ls = d.srow[is + 1] - sr;
-          const int az = jt - d.zcol[zb];
-          const int bs = (j2 - d.a2f[i2]) * d.a1c[i1] + (j1 - d.a1f[i1]);
-          double *row = vals + 9 * d.nnz2 * (int64_t)zb + 3 * (int64_t)Lz * 3 * sr + (int64_t)az * 3 * Ls + 3 * bs;
-#pragma unroll
-          for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int t = 0; t < 3; ++t) row[(int64_t)r * 3 * Lz * Ls + t] += ke[r * 3 + t];
-        }
-      }
-    }
+// physical gradient of local function (a1, a2, at) at point (g1, g2, gz) of cell c
+// of in-plane element (e1, e2), and the point's weight (in-plane, |DF|, thickness)
+__device__ inline void std_gradient(const Dev &d, int e1, int e2, int c, int g1, int g2, int gz, int a1, int a2, int at,
+                                    double G[3], double &w) {
+  const int P1 = d.p1 + 1, Q1 = d.q + 1;
+  const double *t3 = d.ztab + (((int64_t)c * d.ngz + gz) * Q1 + at) * 2;
+  double gh[3];
+  const double *Jt;
+  if (d.shell) {
+    const int64_t ep = ((int64_t)e1 + (int64_t)d.ne1 * e2) * d.ngp + g1 + d.ng1 * g2;
+    const double *rt = d.rtab + (ep * d.nb + a1 + P1 * a2) * 3;
+    gh[0] = rt[1] * t3[0];
+    gh[1] = rt[2] * t3[0];
+    gh[2] = rt[0] * t3[1];
+    Jt = d.gtab + ep * 10;
+    w = Jt[9];
+  } else {
+    const int P2 = d.p2 + 1;
+    const double *t1 = d.tab1 + (((int64_t)e1 * d.ng1 + g1) * P1 + a1) * 2;
+    const double *t2 = d.tab2 + (((int64_t)e2 * d.ng2 + g2) * P2 + a2) * 2;
+    gh[0] = t1[1] * t2[0] * t3[0];
+    gh[1] = t1[0] * t2[1] * t3[0];
+    gh[2] = t1[0] * t2[0] * t3[1];
+    Jt = d.jit;
+    w = d.w1[(int64_t)e1 * d.ng1 + g1] * d.w2[(int64_t)e2 * d.ng2 + g2] * d.detj;
   }
+  w *= d.zw[(int64_t)c * d.ngz + gz];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) G[k] = Jt[k * 3 + 0] * gh[0] + Jt[k * 3 + 1] * gh[1] + Jt[k * 3 + 2] * gh[2];
+}
+
+// the CSR entry of (row function i, component r) x (column function j, component t):
+// returns the address of component (r, t) = (0, 0); r steps by rstride, t by 1
+__device__ inline double *std_entry(const Dev &d, double *vals, int i1, int i2, int it, int j1, int j2, int jt,
+                                    int64_t &rstride) {
+  const int is = i1 + d.n1 * i2;
+  const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
+  const int sr = d.srow[is], Ls = d.srow[is + 1] - sr;
+  const int az = jt - d.zcol[zb];
+  const int bs = (j2 - d.a2f[i2]) * d.a1c[i1] + (j1 - d.a1f[i1]);
+  rstride = 3 * (int64_t)Lz * Ls;
+  return vals + 9 * d.nnz2 * (int64_t)zb + 3 * (int64_t)Lz * 3 * sr + (int64_t)az * 3 * Ls + 3 * bs;
+}
+
+// ke[v] += sum_kl m[kl][v] E[kl][.]: the nine M tiles of one ply cell contracted
+// with its bracket coefficients
+__device__ inline void std_contract(const std_dbl4 m[9], const double *E, double ke[4][9]) {
+#pragma unroll
+  for (int kl = 0; kl < 9; ++kl)
+#pragma unroll
+    for (int rt = 0; rt < 9; ++rt) {
+      const double e = E[kl * 9 + rt];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ke[v][rt] += m[kl][v] * e;
+    }
+}
+
+// Adds the lane's blocks of tile pair (I, J) of element (e1, e2, zsp) into the
+// CSR: K_ab for b = 16 J + li and a = 16 I + kk + 4 v, and for I < J the
+// transposes K_ba.  Every (v, r, t) entry of the lane, direct or transposed,
+// is a distinct CSR position (the pairs differ, and for I < J the transposed
+// rows lie in tile J, the direct ones in tile I), so all reads of a block are
+// issued before any write: one memory round trip per block instead of one
+// per row.
+__device__ inline void std_add(const Dev &d, double *__restrict__ vals, int e1, int e2, int zsp, int I, int J,
+                               const double ke[4][9]) {
+  const int lane = threadIdx.x & 63, li = lane & 15, kk = lane >> 4;
+  const int P1 = d.p1 + 1, P2 = d.p2 + 1, Q1 = d.q + 1, nloc = P1 * P2 * Q1;
+  const int b = 16 * J + li;
+  if (b >= nloc) return;
+  const int f1 = d.e1first[e1], f2 = d.e2first[e2], fz = d.zs_first[zsp];
+  const int j1 = f1 + b % P1, j2 = f2 + (b / P1) % P2, jt = fz + b / (P1 * P2);
+  const int nv = min(4, (nloc - 16 * I - kk + 3) / 4);  // rows a = 16 I + kk + 4 v < nloc of the lane
+  double *rowp[4];
+  int64_t rstr[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int a = min(16 * I + kk + 4 * v, nloc - 1);  // past the last function: a valid address, not written
+    const int i1 = f1 + a % P1, i2 = f2 + (a / P1) % P2, it = fz + a / (P1 * P2);
+    rowp[v] = std_entry(d, vals, i1, i2, it, j1, j2, jt, rstr[v]);
+  }
+  {
+    double old[4][9];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (v < nv)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int t = 0; t < 3; ++t) old[v][r * 3 + t] = rowp[v][r * rstr[v] + t];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (v < nv)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int t = 0; t < 3; ++t) rowp[v][r * rstr[v] + t] = old[v][r * 3 + t] + ke[v][r * 3 + t];
+  }
+  if (I == J) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int a = min(16 * I + kk + 4 * v, nloc - 1);
+    const int i1 = f1 + a % P1, i2 = f2 + (a / P1) % P2, it = fz + a / (P1 * P2);
+    rowp[v] = std_entry(d, vals, j1, j2, jt, i1, i2, it, rstr[v]);
+  }
+  double old[4][9];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    if (v < nv)
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) old[v][t * 3 + r] = rowp[v][t * rstr[v] + r];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    if (v < nv)
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) rowp[v][t * rstr[v] + r] = old[v][t * 3 + r] + ke[v][r * 3 + t];
+}
+
+// tile pair u (0 <= u < tiles (tiles + 1) / 2) -> (I, J), I <= J
+__device__ inline void std_pair(int tiles, int u, int &I, int &J) {
+  I = 0;
+  while (u >= tiles - I) u -= tiles - I++;
+  J = I + u;
+}
+
+// Element (e1, e2, zsp) for launch index el of colour (c1, c2, c3): elements
+// c1 + (p1 + 1) k1, c2 + (p2 + 1) k2, spans c3 + (q + 1) k3, n1c x n2c of them
+// per span row.
+__device__ inline void std_element(const Dev &d, int64_t el, int c1, int c2, int c3, int n1c, int n2c, int &e1, int &e2,
+                                   int &zsp) {
+  e1 = c1 + (d.p1 + 1) * (int)(el % n1c);
+  e2 = c2 + (d.p2 + 1) * (int)((el / n1c) % n2c);
+  zsp = c3 + (d.q + 1) * (int)(el / ((int64_t)n1c * n2c));
+}
+
+// blocks round-robin over the 8 XCDs: XCD x takes the x-th contiguous range
+// (the grid is a multiple of 8 blocks, so this is a permutation)
+__device__ inline int64_t std_block() {
+  const int64_t per = gridDim.x / 8;
+  return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
+// Elements of one ply cell, at most eight tile pairs: the block (one
+// wavefront per tile pair) builds the element's gradient table in LDS,
+// G[g][k][a] (row stride gs doubles per point, padded so the four point rows
+// a step reads fall in different banks) and W[g], then every wavefront runs
+// its tile pair with the operands read from LDS.
+__global__ void __launch_bounds__(64 * STD_LDS_WAVES, 2) k_std3d_lds(Dev d, double *__restrict__ vals, int c1, int c2,
+                                                                   int c3, int n1c, int n2c, int64_t n_elem, int tiles,
+                                                                   int nlocp, int gs) {
+  extern __shared__ double sm[];
+  const int64_t el = std_block();
+  if (el >= n_elem) return;  // the whole block
+  int e1, e2, zsp;
+  std_element(d, el, c1, c2, c3, n1c, n2c, e1, e2, zsp);
+  const int P1 = d.p1 + 1, P2 = d.p2 + 1;
+  const int nloc = P1 * P2 * (d.q + 1), ng = d.ng1 * d.ng2 * d.ngz, nsteps = (ng + 3) / 4, ngp = 4 * nsteps;
+  double *G = sm, *W = sm + (int64_t)ngp * gs;
+  const int c = d.zs_cell[d.zs_cptr[zsp]];
+  for (int idx = threadIdx.x; idx < ngp * nlocp; idx += blockDim.x) {
+    const int g = idx / nlocp, a = idx - g * nlocp;
+    double Gv[3] = {0.0, 0.0, 0.0}, w = 0.0;
+    if (g < ng && a < nloc) {
+      const int g1 = g % d.ng1, g2 = (g / d.ng1) % d.ng2, gz = g / (d.ng1 * d.ng2);
+      std_gradient(d, e1, e2, c, g1, g2, gz, a % P1, (a / P1) % P2, a / (P1 * P2), Gv, w);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) G[g * gs + k * nlocp + a] = Gv[k];
+    if (a == 0) W[g] = g < ng ? w : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, li = lane & 15, kk = lane >> 4;
+  int I, J;
+  std_pair(tiles, __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), I, J);
+  std_dbl4 m[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) m[e] = std_dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int st = 0; st < nsteps; ++st) {
+    const int g = 4 * st + kk;
+    const double *Gg = G + g * gs;
+    const double w = W[g];
+    double A[3], B[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      A[k] = w * Gg[k * nlocp + 16 * I + li];
+      B[k] = Gg[k * nlocp + 16 * J + li];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) m[3 * k + l] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[k], B[l], m[3 * k + l], 0, 0, 0);
+  }
+  double ke[4][9];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int e = 0; e < 9; ++e) ke[v][e] = 0.0;
+  std_contract(m, d.Eply + 81 * d.zply[c], ke);
+  std_add(d, vals, e1, e2, zsp, I, J, ke);
+}
+
+// Elements of any number of ply cells: every (element, tile pair) is a
+// wavefront of its own, the operands evaluated in the lanes from the basis
+// tables and the element matrix summed over the span's cells in registers.
+// For elements through many plies (the matrix costs far more than its
+// read-modify-write) and for tables larger than the LDS.
+__global__ void __launch_bounds__(64 * STD_WAVES, 2) k_std3d(Dev d, double *__restrict__ vals, int c1, int c2, int c3,
+                                                             int n1c, int n2c, int64_t n_elem, int tiles) {
+  const int units = tiles * (tiles + 1) / 2;
+  // the wavefront's index, made explicitly uniform so the element's indices live in scalar registers
+  const int64_t wid = std_block() * STD_WAVES + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (wid >= n_elem * units) return;  // a whole wavefront; the kernel has no barrier
+  const int64_t el = wid / units;
+  int I, J, e1, e2, zsp;
+  std_pair(tiles, (int)(wid - el * units), I, J);
+  std_element(d, el, c1, c2, c3, n1c, n2c, e1, e2, zsp);
+  const int lane = threadIdx.x & 63, li = lane & 15, kk = lane >> 4;
+  const int P1 = d.p1 + 1, P2 = d.p2 + 1, Q1 = d.q + 1;
+  const int nloc = P1 * P2 * Q1, ng = d.ng1 * d.ng2 * d.ngz, nsteps = (ng + 3) / 4;
+  // this lane's operand functions (clamped to function 0 when padded: finite, then zeroed)
+  const int ia = 16 * I + li, ib = 16 * J + li;
+  const bool va = ia < nloc, vb = ib < nloc;
+  const int ja = va ? ia : 0, jb = vb ? ib : 0;
+  const int a1 = ja % P1, a2 = (ja / P1) % P2, at = ja / (P1 * P2);
+  const int b1 = jb % P1, b2 = (jb / P1) % P2, bt = jb / (P1 * P2);
+  double ke[4][9];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int e = 0; e < 9; ++e) ke[v][e] = 0.0;
+  for (int ci = d.zs_cptr[zsp]; ci < d.zs_cptr[zsp + 1]; ++ci) {
+    const int c = d.zs_cell[ci];
+    std_dbl4 m[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) m[e] = std_dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int st = 0; st < nsteps; ++st) {
+      // A_k = w G_a(g)_k, B_l = G_b(g)_l at g = 4 st + kk (zero past the last point or function)
+      const int g = 4 * st + kk;
+      const bool vg = g < ng;
+      const int gg = vg ? g : 0;
+      const int g1 = gg % d.ng1, g2 = (gg / d.ng1) % d.ng2, gz = gg / (d.ng1 * d.ng2);
+      double Ga[3], Gb[3], w, wb;
+      std_gradient(d, e1, e2, c, g1, g2, gz, a1, a2, at, Ga, w);
+      std_gradient(d, e1, e2, c, g1, g2, gz, b1, b2, bt, Gb, wb);
+      const double sa = (va && vg) ? w : 0.0, sb = (vb && vg) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double A = sa * Ga[k];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) m[3 * k + l] = __builtin_amdgcn_mfma_f64_16x16x4f64(A, sb * Gb[l], m[3 * k + l], 0, 0, 0);
+      }
+    }
+    std_contract(m, d.Eply + 81 * d.zply[c], ke);
+  }
+  std_add(d, vals, e1, e2, zsp, I, J, ke);
 }
 
 // ---------------------------------------------------------------------------
@@ -1441,13 +1601,15 @@ extern "C" LAM_API lam_status lam_assemble_standard(const lam_plan *p, void *ws,
   if (!C || !theta || !vals) return LAM_EINVAL;
   if (nnz != p->nnz) return LAM_ESIZE;
   const int P1 = p->p1 + 1, P2 = p->p2 + 1, Q1 = p->q + 1;
-  const int nloc = P1 * P2 * Q1, ng = p->ng1 * p->ng2 * p->ngz;
+  const int nloc = P1 * P2 * Q1;
   if (p->mat_field) return LAM_EUNSUP;
-  // the points' gradient table in LDS: all of them if within the budget
-  // (two blocks per compute unit), else chunks of points
-  const int64_t budget = 72 * 1024, per_pt = sizeof(double) * (3 * (int64_t)nloc + 1), fixed = sizeof(double) * 81;
-  const int gchunk = (int)std::max<int64_t>(1, std::min<int64_t>(ng, (budget - fixed) / per_pt));
-  const size_t lds = (size_t)(gchunk * per_pt + fixed);
+  const int tiles = (nloc + 15) / 16, units = tiles * (tiles + 1) / 2;
+  // one ply cell per element, at most eight tile pairs and a gradient table
+  // within 80 KiB: the block-per-element kernel with the table in LDS
+  const int nlocp = 16 * tiles, ngp = 4 * ((p->ng1 * p->ng2 * p->ngz + 3) / 4);
+  const int gs = 3 * nlocp + ((3 * nlocp) % 32 == 0 ? 16 : 0);
+  const size_t lds = sizeof(double) * ((size_t)ngp * gs + ngp);
+  const bool use_lds = p->max_span_cells == 1 && units <= STD_LDS_WAVES && lds <= 80 * 1024;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Dev d = make_dev(p, ws);
   void *prof = lam::profile_begin(1, stream);
@@ -1458,10 +1620,16 @@ extern "C" LAM_API lam_status lam_assemble_standard(const lam_plan *p, void *ws,
       for (int c1 = 0; c1 < P1; ++c1) {
         const int n1c = (p->ne1 - c1 + P1 - 1) / P1, n2c = (p->ne2 - c2 + P2 - 1) / P2;
         const int n3c = (p->nzs - c3 + Q1 - 1) / Q1;
-        const int64_t nb = (int64_t)n1c * n2c * n3c;
-        if (nb <= 0) continue;
-        hipLaunchKernelGGL(k_std3d, dim3((unsigned)nb), dim3(STD_THREADS), lds, s, d, vals, c1, c2, c3, n1c, n2c,
-                           gchunk);
+        const int64_t n = (int64_t)n1c * n2c * n3c;
+        if (n <= 0) continue;
+        if (use_lds) {
+          hipLaunchKernelGGL(k_std3d_lds, dim3((unsigned)((n + 7) / 8 * 8)), dim3(64 * units), lds, s, d, vals, c1,
+                             c2, c3, n1c, n2c, n, tiles, nlocp, gs);
+        } else {
+          const int64_t nb = ((n * units + STD_WAVES - 1) / STD_WAVES + 7) / 8 * 8;
+          hipLaunchKernelGGL(k_std3d, dim3((unsigned)nb), dim3(64 * STD_WAVES), 0, s, d, vals, c1, c2, c3, n1c, n2c, n,
+                             tiles);
+        }
       }
   lam::profile_end(prof, stream);
   return hip_status();

@@ -932,28 +932,28 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
 
 }  // namespace lam
 
+namespace lam {
+bool tuning_ok(const lam_tuning *t) {
+  return !t || (t->tile_k >= 0 && t->tile_k <= 85 && t->target_blocks >= 0 && t->lds_kib >= 0 && t->lds_kib <= 160 &&
+                (t->set_slots == 0 || t->set_slots == 1 || t->set_slots == 2 || t->set_slots == 4 ||
+                 t->set_slots == 8));
+}
+}  // namespace lam
+
 extern "C" LAM_API lam_status lam_plan_create(const lam_laminate_desc *d, lam_plan **out) {
   return lam::plan_create(d, nullptr, 1, out);
 }
 
 extern "C" LAM_API lam_status lam_plan_create_tuned(const lam_laminate_desc *d, const lam_tuning *tuning,
                                                    lam_plan **out) {
-  if (tuning && (tuning->tile_k < 0 || tuning->tile_k > 85 || tuning->target_blocks < 0 || tuning->lds_kib < 0 ||
-                 tuning->lds_kib > 160 ||
-                 (tuning->set_slots != 0 && tuning->set_slots != 1 && tuning->set_slots != 2 &&
-                  tuning->set_slots != 4 && tuning->set_slots != 8)))
-    return LAM_EINVAL;
+  if (!lam::tuning_ok(tuning)) return LAM_EINVAL;
   return lam::plan_create(d, tuning, 1, out);
 }
 
 extern "C" LAM_API lam_status lam_plan_create_shell(const lam_laminate_desc *d, const lam_shell *shell,
                                                    const lam_tuning *tuning, lam_plan **out) {
   if (!shell) return LAM_EINVAL;
-  if (tuning && (tuning->tile_k < 0 || tuning->tile_k > 85 || tuning->target_blocks < 0 || tuning->lds_kib < 0 ||
-                 tuning->lds_kib > 160 ||
-                 (tuning->set_slots != 0 && tuning->set_slots != 1 && tuning->set_slots != 2 &&
-                  tuning->set_slots != 4 && tuning->set_slots != 8)))
-    return LAM_EINVAL;
+  if (!lam::tuning_ok(tuning)) return LAM_EINVAL;
   return lam::plan_create(d, tuning, 1, out, shell);
 }
 
