@@ -343,16 +343,19 @@ LAM_API lam_status lam_batch_check(const lam_batch *batch, void *ws, int64_t ws_
 
 /* Kernel timing for measurement.  While enabled, every device entry point
  * records a pair of HIP events on its stream around its dominant kernel
- * (the Kronecker scatter of lam_assemble, the element kernel of
+ * (the Kronecker scatter of lam_assemble, the element kernels of
  * lam_assemble_standard, the streaming contraction of lam_adjoint and
  * lam_adjoint_rank1, the scatter of lam_batch_assemble, the product kernel
- * of lam_apply); no work is added or skipped.
+ * of lam_apply), and lam_assemble_standard also around the zero fill of its
+ * output (a plain grid-stride store stream: the write rate the output's
+ * allocation allows); no work is added or skipped.
  * lam_profile_read waits for the recorded events and returns the summed
- * milliseconds and the number of timed launches per entry point (index 0
- * assemble, 1 standard, 2 adjoint, 3 batch, 4 apply), then clears them.
- * Up to 4096 launches are kept; later ones are not timed. */
+ * milliseconds and the number of timed launches per slot (index 0 assemble,
+ * 1 standard, 2 adjoint, 3 batch, 4 apply, 5 the standard's zero fill), then
+ * clears them.  Up to 4096 launches are kept; later ones are not timed. */
+#define LAM_PROFILE_SLOTS 6
 LAM_API lam_status lam_profile_enable(int32_t on);
-LAM_API lam_status lam_profile_read(double ms[5], int64_t launches[5]);
+LAM_API lam_status lam_profile_read(double ms[LAM_PROFILE_SLOTS], int64_t launches[LAM_PROFILE_SLOTS]);
 
 LAM_API const char *lam_status_string(lam_status s);
 

@@ -1612,9 +1612,11 @@ extern "C" LAM_API lam_status lam_assemble_standard(const lam_plan *p, void *ws,
   const bool use_lds = p->max_span_cells == 1 && units <= STD_LDS_WAVES && lds <= 80 * 1024;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Dev d = make_dev(p, ws);
-  void *prof = lam::profile_begin(1, stream);
   hipLaunchKernelGGL(k_rotate_plies, dim3((p->n_ply + 63) / 64), dim3(64), 0, s, d, C, theta);
+  void *prof_fill = lam::profile_begin(5, stream);
   hipLaunchKernelGGL(k_fill_zero, dim3(4096), dim3(256), 0, s, vals, p->nnz);
+  lam::profile_end(prof_fill, stream);
+  void *prof = lam::profile_begin(1, stream);
   for (int c3 = 0; c3 < Q1; ++c3)
     for (int c2 = 0; c2 < P2; ++c2)
       for (int c1 = 0; c1 < P1; ++c1) {

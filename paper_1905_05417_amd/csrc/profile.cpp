@@ -55,10 +55,10 @@ extern "C" LAM_API lam_status lam_profile_enable(int32_t on) {
   return LAM_OK;
 }
 
-extern "C" LAM_API lam_status lam_profile_read(double ms[5], int64_t launches[5]) {
+extern "C" LAM_API lam_status lam_profile_read(double ms[LAM_PROFILE_SLOTS], int64_t launches[LAM_PROFILE_SLOTS]) {
   if (!ms || !launches) return LAM_EINVAL;
   std::lock_guard<std::mutex> g(g_mu);
-  for (int i = 0; i < 5; ++i) {
+  for (int i = 0; i < LAM_PROFILE_SLOTS; ++i) {
     ms[i] = 0.0;
     launches[i] = 0;
   }

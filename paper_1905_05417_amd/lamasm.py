@@ -357,12 +357,15 @@ def profile_enable(on: bool = True):
     _check(lib().lam_profile_enable(1 if on else 0), "lam_profile_enable")
 
 
+PROFILE_SLOTS = ("assemble", "standard", "adjoint", "batch", "apply", "standard_fill")
+
+
 def profile_read():
-    """{'assemble'|'standard'|'adjoint'|'batch'|'apply': (ms_total, launches)} since the last read."""
-    ms = (ctypes.c_double * 5)()
-    n = (ctypes.c_int64 * 5)()
+    """{slot: (ms_total, launches)} since the last read, slots as PROFILE_SLOTS."""
+    ms = (ctypes.c_double * len(PROFILE_SLOTS))()
+    n = (ctypes.c_int64 * len(PROFILE_SLOTS))()
     _check(lib().lam_profile_read(ms, n), "lam_profile_read")
-    return {k: (ms[i], n[i]) for i, k in enumerate(("assemble", "standard", "adjoint", "batch", "apply"))}
+    return {k: (ms[i], n[i]) for i, k in enumerate(PROFILE_SLOTS)}
 
 
 class BatchPlan:
