@@ -141,6 +141,13 @@ inline Dev make_dev(const lam_plan *p, void *ws, void *sbase = nullptr) {
 static __constant__ int kVi[6] = {0, 1, 2, 0, 0, 1};
 static __constant__ int kVj[6] = {0, 1, 2, 1, 2, 2};
 
+// Layout of the moments M_ab[kl] (36 per in-plane nonzero k, e = 9 ab + kl):
+// blocks of 64 consecutive nonzeros, each holding the 36 arrays of its 64
+// values.  A scatter tile (a run of about 64 consecutive nonzeros) reads one
+// or two contiguous 18 KB runs, coalesced across its lanes, instead of 36
+// runs nnz2 values apart (36 pages per block on the large plates).
+__device__ inline int64_t m_index(int64_t k, int e) { return (k >> 6) * (36 * 64) + e * 64 + (k & 63); }
+
 __device__ inline void voigt_rotation(double c, double s, double T[6][6]) {
   const double R[3][3] = {{c, -s, 0.0}, {s, c, 0.0}, {0.0, 0.0, 1.0}};
   for (int I = 0; I < 6; ++I)
@@ -405,7 +412,7 @@ __device__ __forceinline__ void p2d_one(const Dev &d, const double *__restrict__
 #pragma unroll
   for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
-    for (int e = 0; e < 9; ++e) Mt[(int64_t)(ab * 9 + e) * d.nnz2 + k] = M[ab][e / 3][e % 3];
+    for (int e = 0; e < 9; ++e) Mt[m_index(k, ab * 9 + e)] = M[ab][e / 3][e % 3];
   for (int s = 0; s < (write_p ? d.n_sets : 0); ++s) {
     const double *E = Ec + 81 * s;
     double *Po = Pt + (int64_t)s * 36 * d.nnz2 + k;
@@ -547,7 +554,7 @@ __device__ __forceinline__ void kron_group(const Dev &d, const double *__restric
 #pragma unroll
   for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
-    for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[(int64_t)(ab * 9 + kl) * d.nnz2 + k];
+    for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[m_index(k, ab * 9 + kl)];
   const int is = d.krow[k], sr = d.srow[is];
   const int Ls = d.srow[is + 1] - sr, off = 3 * (k - sr) + t;
   const int64_t astride = 3 * (int64_t)Ls;

@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron_reg(Dev d, const double *
 #pragma unroll
     for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
-      for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[(int64_t)(ab * 9 + kl) * d.nnz2 + k];
+      for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[m_index(k, ab * 9 + kl)];
     const int is = d.krow[k], sr = d.srow[is];
     const int Ls = d.srow[is + 1] - sr, off = 3 * (k - sr) + t;
     const int64_t astride = 3 * (int64_t)Ls;
@@ -424,7 +424,7 @@ __global__ void __launch_bounds__(KRON_THREADS) k_apply(Dev d, const double *__r
 #pragma unroll
   for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
-    for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[(int64_t)(ab * 9 + kl) * d.nnz2 + k];
+    for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[m_index(k, ab * 9 + kl)];
   const int js = d.kcol[k];
   const int is0 = d.krow[k0], nrow = d.krow[k0 + tk - 1] - is0 + 1;  // the tile's in-plane rows
   const int ch0 = d.group_ptr[g], ch1 = d.group_ptr[g + 1];
@@ -880,7 +880,7 @@ __global__ void __launch_bounds__(ADJ_THREADS) k_adj_stream(Dev d, const double 
   for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
     for (int kl = 0; kl < 9; ++kl) {
-      const double v = d.M[(int64_t)(ab * 9 + kl) * d.nnz2 + k];  // k is valid for every thread
+      const double v = d.M[m_index(k, ab * 9 + kl)];  // k is valid for every thread
       m[ab][kl] = act ? v : 0.0;
     }
   double z[2][4][3];
@@ -1332,7 +1332,7 @@ __global__ void __launch_bounds__(256) k_cg_lines(Dev d, const double *__restric
 #pragma unroll
   for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
-    for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[(int64_t)(ab * 9 + kl) * d.nnz2 + k];
+    for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[m_index(k, ab * 9 + kl)];
   for (int64_t e = 0; e < (int64_t)n * wb; ++e) fac[e * ns + is] = 0.0;
   for (int it = 0; it < d.nt; ++it) {
     const int ch = d.zchunk[it], c0 = d.chunk_sptr[ch], nsc = d.chunk_sptr[ch + 1] - c0;

@@ -844,7 +844,7 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
   // contracts it from the moments M
   L.P = B.take(P->kron_nsc > 0 ? 0 : sizeof(double) * 36 * (int64_t)P->n_sets * P->nnz2);
   L.Qc = B.take(sizeof(double) * 4 * (int64_t)std::max(P->maxact, P->kron_nsc) * P->nnzz);
-  L.M = B.take(sizeof(double) * 36 * P->nnz2);
+  L.M = B.take(sizeof(double) * 36 * ((P->nnz2 + 63) / 64 * 64));  // blocks of 64 nonzeros (m_index)
   L.Eply = B.take(sizeof(double) * 81 * P->n_ply);
   L.Ectl = B.take(P->mat_field ? sizeof(double) * 81 * (int64_t)P->n_sets * P->ns : 0);
   L.Epts = B.take(P->mat_field ? sizeof(double) * 81 * (int64_t)P->n_sets * P->ne1 * P->ne2 * ng1 * ng2 : 0);
