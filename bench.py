@@ -92,18 +92,19 @@ def _parse():
     return ap.parse_args()
 
 
-# workloads of --kernel-only: name -> (constructor in workloads.py, set mode)
-KERNEL_ONLY_WORKLOADS = {"p3_128x128_128ply": ("config_p3_128x128_128ply", "bucket"),
-                         "p2_64x64_32ply": ("config_p2_64x64_32ply", "bucket"),
-                         "adjoint_p2_96x96_64ply": ("config_adjoint_p2_96x96_64ply", "ply")}
+# workloads of --kernel-only: name -> (laminate from workloads.py, set mode)
+KERNEL_ONLY_WORKLOADS = {"p3_128x128_128ply": (lambda W: W.config_p3_128x128_128ply(), "bucket"),
+                         "p2_64x64_32ply": (lambda W: W.config_p2_64x64_32ply(), "bucket"),
+                         "adjoint_p2_96x96_64ply": (lambda W: W.config_adjoint_p2_96x96_64ply(), "ply"),
+                         "paper_p3_64x64_128ply": (lambda W: W.paper_plate(3, 64, 128), "bucket")}
 
 
 def _kernel_only(args, torch, np, L, W):
     """--steps assemblies of one workload and nothing else (no timing beyond
     the wall clock, no parity), so a profiler's counters cover just them."""
     from paper_1905_05417_amd import autotune
-    ctor, mode = KERNEL_ONLY_WORKLOADS[args.workload]
-    lam = getattr(W, ctor)()
+    make, mode = KERNEL_ONLY_WORKLOADS[args.workload]
+    lam = make(W)
     plan = L.Plan(lam, set_mode=mode, tuning=autotune.lookup(lam, "bucket"))
     C = torch.tensor(np.asarray(lam.C), device="cuda")
     th = torch.tensor(np.asarray(lam.theta), device="cuda")
