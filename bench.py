@@ -85,8 +85,9 @@ def _parse():
                     help="the sweep at degree 3 only, meshes 1x1 and 64x64, 1, 16 and 128 plies")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
-    ap.add_argument("--kernel-only", choices=("fast", "standard"), default=None,
-                    help="only run --steps assemblies (after --warmup) of one workload, for profiler counters")
+    ap.add_argument("--kernel-only", choices=("fast", "standard", "apply", "cg"), default=None,
+                    help="only run --steps assemblies, matrix-free products or CG iterations (plate clamped along "
+                         "one edge) after --warmup of them, on one workload, for profiler runs")
     ap.add_argument("--workload", choices=tuple(KERNEL_ONLY_WORKLOADS), default="p3_128x128_128ply",
                     help="the workload of --kernel-only")
     return ap.parse_args()
@@ -100,22 +101,40 @@ KERNEL_ONLY_WORKLOADS = {"p3_128x128_128ply": (lambda W: W.config_p3_128x128_128
 
 
 def _kernel_only(args, torch, np, L, W):
-    """--steps assemblies of one workload and nothing else (no timing beyond
-    the wall clock, no parity), so a profiler's counters cover just them."""
+    """--steps calls of one entry point on one workload and nothing else (no
+    timing beyond the wall clock, no parity), so a profiler's counters cover
+    just them."""
     from paper_1905_05417_amd import autotune
     make, mode = KERNEL_ONLY_WORKLOADS[args.workload]
     lam = make(W)
     plan = L.Plan(lam, set_mode=mode, tuning=autotune.lookup(lam, "bucket"))
     C = torch.tensor(np.asarray(lam.C), device="cuda")
     th = torch.tensor(np.asarray(lam.theta), device="cuda")
-    vals = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
-    fn = plan.assemble if args.kernel_only == "fast" else plan.assemble_standard
+    if args.kernel_only in ("fast", "standard"):
+        vals = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
+        fn = plan.assemble if args.kernel_only == "fast" else plan.assemble_standard
+        step = lambda: fn(C, th, out=vals)
+    elif args.kernel_only == "apply":
+        u = torch.tensor(np.random.default_rng(11).standard_normal(plan.n_rows), device="cuda")
+        y = torch.empty_like(u)
+        step = lambda: plan.apply(C, th, u, out=y)
+    else:  # one call of CG, --steps iterations (tolerance 0: no early stop)
+        fixed, b = _clamped_edge(torch, lam, plan)
+        plan.cg(C, th, b, fixed=fixed, tol=0.0, max_iter=args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.cg(C, th, b, fixed=fixed, tol=0.0, max_iter=args.steps)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+        print(json.dumps({"kernel_only": "cg", "workload": lam.name, "iterations": args.steps,
+                          "ms_per_iteration_wall": ms}), flush=True)
+        return
     for _ in range(args.warmup):
-        fn(C, th, out=vals)
+        step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        fn(C, th, out=vals)
+        step()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
     print(json.dumps({"kernel_only": args.kernel_only, "workload": lam.name, "nnz": plan.nnz, "steps": args.steps,
@@ -267,6 +286,15 @@ def _adjoint_workload(torch, np, L, W, O, steps, warmup):
     return res
 
 
+def _clamped_edge(torch, lam, plan):
+    """Dirichlet rows of every function on the first in-plane edge (xi1 = 0),
+    and a unit load on every row."""
+    n1, n2 = len(lam.k1) - lam.p1 - 1, len(lam.k2) - lam.p2 - 1
+    rows = torch.arange(plan.n_rows, device="cuda")
+    fixed = ((rows // 3) % (n1 * n2)) % n1 == 0
+    return fixed, torch.ones(plan.n_rows, dtype=torch.float64, device="cuda")
+
+
 def _apply_workload(torch, np, L, lam, plan, C, th, vals, rowptr, colind, steps, warmup):
     """y = K u on the 32-ply degree-2 plate: matrix-free (lam_apply, K never formed)
     against multiplying the assembled K (torch's CSR matrix-vector product of
@@ -280,12 +308,9 @@ def _apply_workload(torch, np, L, lam, plan, C, th, vals, rowptr, colind, steps,
     ms_spmv, _ = _time_steps(torch, lambda: torch.mv(K, u), steps, warmup, L, "apply")
     del K
     torch.cuda.empty_cache()
-    # block-Jacobi CG on the plate clamped along its first in-plane edge, unit
-    # load on every free row, to a relative residual of 1e-8
-    n1, n2 = len(lam.k1) - lam.p1 - 1, len(lam.k2) - lam.p2 - 1
-    rows = torch.arange(plan.n_rows, device="cuda")
-    fixed = ((rows // 3) % (n1 * n2)) % n1 == 0
-    b = torch.ones(plan.n_rows, dtype=torch.float64, device="cuda")
+    # preconditioned CG on the plate clamped along its first in-plane edge,
+    # unit load on every free row, to a relative residual of 1e-8
+    fixed, b = _clamped_edge(torch, lam, plan)
     plan.cg(C, th, b, fixed=fixed, tol=0.0, max_iter=5)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

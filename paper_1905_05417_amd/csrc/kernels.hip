@@ -1378,63 +1378,115 @@ __global__ void __launch_bounds__(256) k_cg_lines(Dev d, const double *__restric
       const int p0 = (i - hb > j - hb ? i - hb : j - hb) > 0 ? (i - hb > j - hb ? i - hb : j - hb) : 0;
       for (int pp = p0; pp < j; ++pp)
         sum -= fac[((int64_t)i * wb + (i - pp)) * ns + is] * fac[((int64_t)j * wb + (j - pp)) * ns + is];
-      if (i == j)
-        fac[((int64_t)i * wb) * ns + is] = sum > 0.0 ? sqrt(sum) : 1.0;  // SPD: sum > 0; guard keeps it finite
+      if (i == j)  // the diagonal slot keeps 1 / L_ii (SPD: sum > 0; the guard keeps it finite)
+        fac[((int64_t)i * wb) * ns + is] = sum > 0.0 ? 1.0 / sqrt(sum) : 1.0;
       else
-        fac[((int64_t)i * wb + (i - j)) * ns + is] = sum / fac[((int64_t)j * wb) * ns + is];
+        fac[((int64_t)i * wb + (i - j)) * ns + is] = sum * fac[((int64_t)j * wb) * ns + is];
     }
   }
 }
 
 // z = M^{-1} r on every thickness line (forward and backward substitution
-// with the banded factor); with p given, p = z too.  One thread per line.  The
-// last HB = 3Q + 2 values of each substitution stay in registers (a window
-// shifted by one per row), so a row waits on no memory round trip of its own
-// results; the factor's entries have known addresses and stream in.
+// with the banded factor, whose diagonal slots hold 1 / L_ii); with p given,
+// p = z too.  One thread per line, one wavefront per block (the lines spread
+// over as many compute units as there are wavefronts).  The substitutions are
+// chains of dependent steps, so each step's operands (its factor row or
+// column, its right-hand side) are loaded LS_AHEAD steps ahead into a ring of
+// register slots: a step waits on loads issued LS_AHEAD steps before, not on
+// its own.  The last HB = 3Q + 2 results stay in registers (a window shifted
+// by one per step).
+constexpr int LS_AHEAD = 5;
+
 template <int Q>
-__global__ void __launch_bounds__(256) k_cg_line_solve(Dev d, const double *__restrict__ fac,
-                                                       const double *__restrict__ r, double *__restrict__ z,
-                                                       double *__restrict__ p) {
+__global__ void __launch_bounds__(64) k_cg_line_solve(Dev d, const double *__restrict__ fac,
+                                                      const double *__restrict__ r, double *__restrict__ z,
+                                                      double *__restrict__ p) {
   constexpr int HB = 3 * Q + 2, WB = HB + 1;
   const int is = blockIdx.x * blockDim.x + threadIdx.x;
   if (is >= d.ns) return;
   const int n = 3 * d.nt;
   const int64_t ns = d.ns;
   auto row = [&](int i) { return 3 * ((int64_t)(i / 3) * ns + is) + i % 3; };
-  double win[HB];  // win[HB - c] = y[i - c] for c = 1..HB (zeros before the first row)
+  // slot: [0] 1 / L_ii, [c] the band entry at distance c (c = 1..HB), [WB] the right-hand side.
+  // Loads past either end read the last (first) row instead (in bounds, never used), so the
+  // loads carry no branch and the compiler keeps them in flight.
+  double sl[LS_AHEAD][WB + 1];
+  double win[HB];
+  // L y = r (y kept in z); band entries before the first row are zero in the factor
+  auto fwd_load = [&](int i, double *o) {
+    const int ic = i < n ? i : n - 1;
+    const double *Li = fac + (int64_t)ic * WB * ns + is;
 #pragma unroll
-  for (int c = 0; c < HB; ++c) win[c] = 0.0;
-  for (int i = 0; i < n; ++i) {  // L y = r (y kept in z)
-    const double *Li = fac + (int64_t)i * WB * ns + is;
-    double sum = r[row(i)];
+    for (int c = 0; c <= HB; ++c) o[c] = Li[c * ns];
+    o[WB] = r[row(ic)];
+  };
+  auto fwd_step = [&](int i, const double *o) {
+    double sum = o[WB];
 #pragma unroll
-    for (int c = 1; c <= HB; ++c)
-      if (i - c >= 0) sum -= Li[c * ns] * win[HB - c];
-    const double y = sum / Li[0];
+    for (int c = 1; c <= HB; ++c) sum -= o[c] * win[HB - c];
+    const double y = sum * o[0];
 #pragma unroll
     for (int c = 0; c + 1 < HB; ++c) win[c] = win[c + 1];
     win[HB - 1] = y;
     z[row(i)] = y;
+  };
+#pragma unroll
+  for (int c = 0; c < HB; ++c) win[c] = 0.0;  // win[HB - c] = y[i - c] for c = 1..HB
+#pragma unroll
+  for (int j = 0; j < LS_AHEAD; ++j) fwd_load(j, sl[j]);
+  const int nfull = n / LS_AHEAD * LS_AHEAD;
+  for (int i0 = 0; i0 < nfull; i0 += LS_AHEAD) {
+#pragma unroll
+    for (int j = 0; j < LS_AHEAD; ++j) {
+      fwd_step(i0 + j, sl[j]);
+      fwd_load(i0 + j + LS_AHEAD, sl[j]);
+    }
   }
 #pragma unroll
-  for (int c = 0; c < HB; ++c) win[c] = 0.0;  // win[c - 1] = z[i + c] for c = 1..HB (zeros past the last)
-  for (int i = n - 1; i >= 0; --i) {  // L^T z = y
-    double sum = z[row(i)];
+  for (int j = 0; j < LS_AHEAD; ++j)
+    if (nfull + j < n) fwd_step(nfull + j, sl[j]);
+  // L^T z = y: column i of L below the diagonal is L[i + c][c], c = 1..HB (zero past the last row)
+  auto bwd_load = [&](int i, double *o) {
+    const int ic = i >= 0 ? i : 0;
+    o[0] = fac[(int64_t)ic * WB * ns + is];
 #pragma unroll
-    for (int c = 1; c <= HB; ++c)
-      if (i + c < n) sum -= fac[((int64_t)(i + c) * WB + c) * ns + is] * win[c - 1];
-    const double v = sum / fac[(int64_t)i * WB * ns + is];
+    for (int c = 1; c <= HB; ++c) {
+      const int rc = ic + c < n ? ic + c : n - 1;
+      const double v = fac[((int64_t)rc * WB + c) * ns + is];
+      o[c] = ic + c < n ? v : 0.0;
+    }
+    o[WB] = z[row(ic)];
+  };
+  auto bwd_step = [&](int i, const double *o) {
+    double sum = o[WB];
+#pragma unroll
+    for (int c = 1; c <= HB; ++c) sum -= o[c] * win[c - 1];
+    const double v = sum * o[0];
 #pragma unroll
     for (int c = HB - 1; c > 0; --c) win[c] = win[c - 1];
     win[0] = v;
     z[row(i)] = v;
     if (p) p[row(i)] = v;
+  };
+#pragma unroll
+  for (int c = 0; c < HB; ++c) win[c] = 0.0;  // win[c - 1] = z[i + c] for c = 1..HB
+#pragma unroll
+  for (int j = 0; j < LS_AHEAD; ++j) bwd_load(n - 1 - j, sl[j]);
+  for (int i0 = n - 1; i0 >= n - nfull; i0 -= LS_AHEAD) {
+#pragma unroll
+    for (int j = 0; j < LS_AHEAD; ++j) {
+      bwd_step(i0 - j, sl[j]);
+      bwd_load(i0 - j - LS_AHEAD, sl[j]);
+    }
   }
+#pragma unroll
+  for (int j = 0; j < LS_AHEAD; ++j)
+    if (n - 1 - nfull - j >= 0) bwd_step(n - 1 - nfull - j, sl[j]);
 }
 
 void launch_line_solve(const lam_plan *pl, const Dev &d, const double *fac, const double *r, double *z, double *pv,
                        hipStream_t s) {
-  const dim3 lg((unsigned)((pl->ns + 255) / 256)), vb(256);
+  const dim3 lg((unsigned)((pl->ns + 63) / 64)), vb(64);
   switch (pl->q) {
     case 1: hipLaunchKernelGGL((k_cg_line_solve<1>), lg, vb, 0, s, d, fac, r, z, pv); break;
     case 2: hipLaunchKernelGGL((k_cg_line_solve<2>), lg, vb, 0, s, d, fac, r, z, pv); break;
