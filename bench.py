@@ -97,7 +97,10 @@ def _parse():
 KERNEL_ONLY_WORKLOADS = {"p3_128x128_128ply": (lambda W: W.config_p3_128x128_128ply(), "bucket"),
                          "p2_64x64_32ply": (lambda W: W.config_p2_64x64_32ply(), "bucket"),
                          "adjoint_p2_96x96_64ply": (lambda W: W.config_adjoint_p2_96x96_64ply(), "ply"),
-                         "paper_p3_64x64_128ply": (lambda W: W.paper_plate(3, 64, 128), "bucket")}
+                         "paper_p3_64x64_128ply": (lambda W: W.paper_plate(3, 64, 128), "bucket"),
+                         "curved_bspline_p2_64x64_32ply": (lambda W: _curved_shell_64(W), "bucket"),
+                         "nurbs_annulus_field_p2_64x64_32ply": (lambda W: _nurbs_field_64(W, __import__("numpy")),
+                                                                "bucket")}
 
 
 def _kernel_only(args, torch, np, L, W):
@@ -222,12 +225,33 @@ def _fast_workload(torch, np, L, O, lam, mode, steps, warmup, standard_steps=0):
                                     "standard")
             res["standard"] = {"ms_per_step": ms_std, "nnz_per_s": plan.nnz / (ms_std * 1e-3),
                                "speedup_fast_vs_standard": ms_std / ms_step,
+                               "roofline": _standard_roofline(lam, plan.nnz, ms_std),
                                "parity_sample_relF": _sample_parity(O, lam, plan, vals, rowptr, n_rows=50)}
         except L.LamError as e:
             res["standard"] = {"skipped": str(e)}
     del vals, rowptr, colind
     torch.cuda.empty_cache()
     return res
+
+
+def _thickness_shapes(torch, np, L, W, O, steps, warmup):
+    """Thickness discretizations beyond the benchmark plates' q = 2 (Sec. 2.4:
+    the split holds for any thickness space), on the 64x64 degree-2 in-plane
+    mesh with 16 plies [0/90]_8 of carbon: layerwise q = 3 and q = 4 (thickness
+    rows of q + 1 and, at the interfaces, 2q + 1 nonzeros: the scatter's
+    generic row body) and q = 2 with every ply split in two by a simple knot
+    (two thickness elements per ply, C1 inside the ply)."""
+    out = {}
+    for q in (3, 4):
+        lam = W.plate(2, 64, q, [0, 90] * 8, [W.material(W.CARBON)], [0] * 16, name="p2_64x64_16ply_q%d" % q)
+        lam.ng = (3, 3, q + 1)
+        out[lam.name] = _fast_workload(torch, np, L, O, lam, "bucket", steps, warmup, standard_steps=2)
+    lam = W.plate(2, 64, 2, [0, 90] * 8, [W.material(W.CARBON)], [0] * 16, name="p2_64x64_16ply_q2_two_elements_per_ply")
+    mid = 0.5 * (lam.iface[:-1] + lam.iface[1:])
+    lam.k3 = np.sort(np.concatenate([lam.k3, mid]))
+    lam.ng = (3, 3, 3)
+    out[lam.name] = _fast_workload(torch, np, L, O, lam, "bucket", steps, warmup, standard_steps=2)
+    return out
 
 
 def _adjoint_workload(torch, np, L, W, O, steps, warmup):
@@ -426,6 +450,24 @@ def _paper_sweep(torch, np, L, W, O, degrees, meshes, plies, layups, reps):
     return rows
 
 
+def _curved_shell_64(W):
+    """Curved B-spline shell, the 64x64 32-ply degree-2 plate's discretization."""
+    lam = W.curved_shell(2, 64, 2, [0, 90] * 16, [W.material(W.CARBON)], [0] * 32, name="curved_p2_64x64_32ply")
+    lam.ng = (3, 3, 3)
+    return lam
+
+
+def _nurbs_field_64(W, np):
+    """NURBS quarter annulus 64x64, 32 plies of two materials varying over the plane."""
+    lam = W.smooth_material_field(W.nurbs_annulus_shell(64, 64, 2, [0, 45, -45, 90] * 8,
+                                                        [W.material(W.CARBON), W.material(W.GLASS)],
+                                                        [(l // 8) % 2 for l in range(32)], p2=2,
+                                                        name="annulus_p2_64x64_32ply"),
+                                  np.random.default_rng(8700))
+    lam.ng = (3, 3, 3)
+    return lam
+
+
 def _shell_workloads(torch, np, L, W, O, steps, warmup):
     """Curved shells (Sec. 2.3, eq. extrusion) at the 64x64 32-ply size: a
     curved B-spline mid-surface with constant ply materials (moments by 2D
@@ -434,17 +476,9 @@ def _shell_workloads(torch, np, L, W, O, steps, warmup):
     materials vary over the plane (P of every set from the field, LDS-mode
     scatter).  Sampled parity against the oracle for each."""
     out = {}
-    cases = [("curved_bspline_p2_64x64_32ply",
-              W.curved_shell(2, 64, 2, [0, 90] * 16, [W.material(W.CARBON)], [0] * 32, name="curved_p2_64x64_32ply"),
-              True),
-             ("nurbs_annulus_field_p2_64x64_32ply",
-              W.smooth_material_field(W.nurbs_annulus_shell(64, 64, 2, [0, 45, -45, 90] * 8,
-                                                            [W.material(W.CARBON), W.material(W.GLASS)],
-                                                            [(l // 8) % 2 for l in range(32)], p2=2,
-                                                            name="annulus_p2_64x64_32ply"),
-                                      np.random.default_rng(8700)), False)]
+    cases = [("curved_bspline_p2_64x64_32ply", _curved_shell_64(W), True),
+             ("nurbs_annulus_field_p2_64x64_32ply", _nurbs_field_64(W, np), False)]
     for key, lam, std in cases:
-        lam.ng = (3, 3, 3)
         plan = L.Plan(lam, set_mode="bucket")
         rowptr, colind = plan.pattern()
         del colind
@@ -711,6 +745,8 @@ def main():
         extra["p2_64x64_32ply"] = _c2_workload(torch, np, L, W, O, args)
     if not args.no_extra:
         extra["adjoint_p2_96x96_64ply"] = _adjoint_workload(torch, np, L, W, O, max(5, args.steps // 2), args.warmup)
+    if not args.no_extra:
+        extra["thickness_shapes"] = _thickness_shapes(torch, np, L, W, O, max(5, args.steps // 2), args.warmup)
     if not args.no_extra:
         extra["shells"] = _shell_workloads(torch, np, L, W, O, max(5, args.steps // 2), args.warmup)
     if not args.no_extra and not args.no_batch:
