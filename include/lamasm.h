@@ -242,7 +242,8 @@ LAM_API lam_status lam_adjoint(const lam_plan *plan, void *ws, int64_t ws_bytes,
  * fixed: NULL, or device bytes per row (nonzero = Dirichlet row) for the
  * eliminated operator y = P K P u + (I - P) u, P the projection on the free
  * rows.  Register-mode plans with one or two set slots (every bucket and
- * per-ply plan with the automatic slot count); LAM_EUNSUP otherwise,
+ * per-ply plan with the automatic slot count) and constant materials;
+ * LAM_EUNSUP otherwise,
  * LAM_ESIZE if n_rows is not the plan's row count.  The rounding order
  * differs from multiplying the assembled K. */
 LAM_API lam_status lam_apply(const lam_plan *plan, void *ws, int64_t ws_bytes, const double *C, const double *theta,

@@ -550,11 +550,11 @@ __device__ __forceinline__ void kron_group(const Dev &d, const double *__restric
   const int k0 = d.tiles[tile], tk = d.tiles[tile + 1] - k0;
   const bool act = sig < 3 * tk;
   const int kk = act ? sig / 3 : 0, t = act ? sig - 3 * kk : 0, k = k0 + kk;
-  double mv[4][9];
+  double mv[4][9];  // the moments (not used by material-field plans, whose P is stored)
 #pragma unroll
   for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
-    for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[m_index(k, ab * 9 + kl)];
+    for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.mat_field ? 0.0 : d.M[m_index(k, ab * 9 + kl)];
   const int is = d.krow[k], sr = d.srow[is];
   const int Ls = d.srow[is + 1] - sr, off = 3 * (k - sr) + t;
   const int64_t astride = 3 * (int64_t)Ls;
@@ -581,6 +581,15 @@ __device__ __forceinline__ void kron_group(const Dev &d, const double *__restric
       const int ls = u < nsc ? d.chunk_lset[c0 + u] : ns;  // unused slots: the zero block
       if (ls == slot_set[u]) continue;  // the slot keeps its set (and P) from the previous chunk
       slot_set[u] = ls;
+      if (d.mat_field) {  // P of the slot's set from memory (zero for an unused slot)
+        const int gs = ls < ns ? d.group_set[s0 + ls] : -1;
+#pragma unroll
+        for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+            pr[u][ab][r] = gs >= 0 ? d.P[((int64_t)gs * 36 + ab * 9 + 3 * r + t) * d.nnz2 + k] : 0.0;
+        continue;
+      }
       const double *eu = le + 81 * ls;
 #pragma unroll
       for (int ab = 0; ab < 4; ++ab)

@@ -132,68 +132,78 @@ __global__ void __launch_bounds__(256) k_field_points(Dev d) {
   d.Epts[81 * pt + j] = acc;
 }
 
-// per (in-plane nonzero k, set s), k fastest: P_s[k][ab][rt] =
-// sum_e sum_g w |DF| sum_kl (G_a^i)_k (G_b^j)_l Epts[s][e][g][kl][rt], stored
-// component-major for the LDS-mode scatter
-__global__ void __launch_bounds__(256) k_p2d_field(Dev d) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= d.nnz2 * d.n_sets) return;
-  const int64_t k = idx % d.nnz2, s = idx / d.nnz2;
-  const int is = d.krow[k], js = d.kcol[k];
-  const int i1 = is % d.n1, i2 = is / d.n1, j1 = js % d.n1, j2 = js / d.n1;
-  const int2 ra = d.pe1[d.kp1[k]], rb = d.pe2[d.kp2[k]];
-  const int P1 = d.p1 + 1;
-  const int64_t npts = (int64_t)d.ne1 * d.ne2 * d.ngp;
-  double P[4][9];
+// P of every set with the material field inside (Assumption 3), element by
+// element: one block per (in-plane element e, set s) stages the element's
+// point data in LDS (the map gradient and weight, the (rational) basis values
+// and derivatives of its nb local functions, and the set's bracket
+// coefficients E_s at every point), and each thread takes local pairs (a, b)
+// and adds
+//   P_s[k(a, b)][ab][rt] += sum_g w_g |DF| sum_kl (G_a)_k (G_b)_l E_s(g)[kl][rt]
+// into the pair's in-plane nonzero k (stored component-major for the
+// LDS-mode scatter), the E reads broadcast across the block.
+// Elements of one colour (e1 mod p1 + 1, e2 mod p2 + 1) share no in-plane
+// function, so a launch per colour adds without atomics (P zeroed first).
+__global__ void __launch_bounds__(256) k_p2d_field(Dev d, int c1, int c2, int n1c, int n2c) {
+  extern __shared__ double fs[];
+  const int P1 = d.p1 + 1, P2 = d.p2 + 1, nb = P1 * P2, ngp = d.ngp;
+  const int64_t blk = blockIdx.x;
+  const int s = (int)(blk / ((int64_t)n1c * n2c));
+  const int eb = (int)(blk - (int64_t)s * n1c * n2c);
+  const int e1 = c1 + P1 * (eb % n1c), e2 = c2 + P2 * (eb / n1c);
+  const int64_t e = e1 + (int64_t)d.ne1 * e2;
+  const int64_t npts = (int64_t)d.ne1 * d.ne2 * ngp;
+  double *sG = fs, *sR = sG + 10 * ngp, *sE = sR + 3 * nb * ngp;  // [g][10], [g][nb][3], [g][81]
+  for (int x = threadIdx.x; x < 10 * ngp; x += blockDim.x) sG[x] = d.gtab[e * ngp * 10 + x];
+  for (int x = threadIdx.x; x < 3 * nb * ngp; x += blockDim.x) sR[x] = d.rtab[e * ngp * nb * 3 + x];
+  for (int x = threadIdx.x; x < 81 * ngp; x += blockDim.x) sE[x] = d.Epts[81 * (s * npts + e * ngp) + x];
+  __syncthreads();
+  const int f1 = d.e1first[e1], f2 = d.e2first[e2];
+  for (int u = threadIdx.x; u < nb * nb; u += blockDim.x) {
+    const int la = u / nb, lb = u - la * nb;
+    double P[4][9];
 #pragma unroll
-  for (int ab = 0; ab < 4; ++ab)
+    for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
-    for (int rt = 0; rt < 9; ++rt) P[ab][rt] = 0.0;
-  for (int e2 = rb.x; e2 < rb.x + rb.y; ++e2) {
-    const int f2 = d.e2first[e2];
-    for (int e1 = ra.x; e1 < ra.x + ra.y; ++e1) {
-      const int f1 = d.e1first[e1];
-      const int64_t e = e1 + (int64_t)d.ne1 * e2;
-      const int bi = (i2 - f2) * P1 + (i1 - f1), bj = (j2 - f2) * P1 + (j1 - f1);
-      for (int g = 0; g < d.ngp; ++g) {
-        const double *G = d.gtab + (e * d.ngp + g) * 10;
-        const double *ri = d.rtab + ((e * d.ngp + g) * d.nb + bi) * 3;
-        const double *rj = d.rtab + ((e * d.ngp + g) * d.nb + bj) * 3;
-        const double *E = d.Epts + 81 * (s * npts + e * d.ngp + g);
-        double vi[2][3], vj[2][3];
+      for (int rt = 0; rt < 9; ++rt) P[ab][rt] = 0.0;
+    for (int g = 0; g < ngp; ++g) {
+      const double *G = sG + 10 * g, *ri = sR + 3 * (g * nb + la), *rj = sR + 3 * (g * nb + lb);
+      const double *E = sE + 81 * g;
+      double vi[2][3], vj[2][3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          vi[0][c] = G[c * 3] * ri[1] + G[c * 3 + 1] * ri[2];
-          vi[1][c] = G[c * 3 + 2] * ri[0];
-          vj[0][c] = G[c * 3] * rj[1] + G[c * 3 + 1] * rj[2];
-          vj[1][c] = G[c * 3 + 2] * rj[0];
-        }
-        const double w = G[9];
-#pragma unroll
-        for (int kk = 0; kk < 3; ++kk)
-#pragma unroll
-          for (int ll = 0; ll < 3; ++ll) {
-            const double *Ekl = E + 9 * (kk * 3 + ll);
-            double ek[9];
-#pragma unroll
-            for (int rt = 0; rt < 9; ++rt) ek[rt] = Ekl[rt];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-              for (int b = 0; b < 2; ++b) {
-                const double m = w * vi[a][kk] * vj[b][ll];
-#pragma unroll
-                for (int rt = 0; rt < 9; ++rt) P[2 * a + b][rt] += m * ek[rt];
-              }
-          }
+      for (int c = 0; c < 3; ++c) {
+        vi[0][c] = G[c * 3] * ri[1] + G[c * 3 + 1] * ri[2];
+        vi[1][c] = G[c * 3 + 2] * ri[0];
+        vj[0][c] = G[c * 3] * rj[1] + G[c * 3 + 1] * rj[2];
+        vj[1][c] = G[c * 3 + 2] * rj[0];
       }
+      const double w = G[9];
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+        for (int ll = 0; ll < 3; ++ll) {
+          const double *Ekl = E + 9 * (kk * 3 + ll);
+          double ek[9];
+#pragma unroll
+          for (int rt = 0; rt < 9; ++rt) ek[rt] = Ekl[rt];
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+              const double m = w * vi[a][kk] * vj[b][ll];
+#pragma unroll
+              for (int rt = 0; rt < 9; ++rt) P[2 * a + b][rt] += m * ek[rt];
+            }
+        }
     }
+    // the pair's in-plane nonzero: row is = i1 + n1 i2, column js = j1 + n1 j2
+    const int i1 = f1 + la % P1, i2 = f2 + la / P1, j1 = f1 + lb % P1, j2 = f2 + lb / P1;
+    const int64_t k = d.srow[i1 + d.n1 * i2] + (int64_t)(j2 - d.a2f[i2]) * d.a1c[i1] + (j1 - d.a1f[i1]);
+    double *Po = d.P + (int64_t)s * 36 * d.nnz2 + k;
+#pragma unroll
+    for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+      for (int rt = 0; rt < 9; ++rt) Po[(int64_t)(ab * 9 + rt) * d.nnz2] += P[ab][rt];
   }
-  double *Po = d.P + s * 36 * d.nnz2 + k;
-#pragma unroll
-  for (int ab = 0; ab < 4; ++ab)
-#pragma unroll
-    for (int rt = 0; rt < 9; ++rt) Po[(int64_t)(ab * 9 + rt) * d.nnz2] = P[ab][rt];
 }
 
 // ---------------------------------------------------------------------------
@@ -1176,7 +1186,19 @@ void launch_assemble(const lam_plan *p, const Dev &d, const double *C, const dou
     hipLaunchKernelGGL(k_rotate_field, dim3((unsigned)(((int64_t)p->n_sets * p->ns + 255) / 256)), dim3(256), 0, s, d,
                        C, theta);
     hipLaunchKernelGGL(k_field_points, dim3((unsigned)((81 * npts * p->n_sets + 255) / 256)), dim3(256), 0, s, d);
-    hipLaunchKernelGGL(k_p2d_field, dim3((unsigned)((p->nnz2 * p->n_sets + 255) / 256)), dim3(256), 0, s, d);
+    {
+      const int P1 = p->p1 + 1, P2 = p->p2 + 1, nb = P1 * P2, ngp = p->ng1 * p->ng2;
+      const size_t lds = sizeof(double) * (size_t)ngp * (10 + 3 * nb + 81);
+      const int thr = std::min(256, (nb * nb + 63) / 64 * 64);
+      hipLaunchKernelGGL(k_fill_zero, dim3(2048), dim3(256), 0, s, d.P, (int64_t)p->n_sets * 36 * p->nnz2);
+      for (int c2 = 0; c2 < P2; ++c2)
+        for (int c1 = 0; c1 < P1; ++c1) {
+          const int n1c = (p->ne1 - c1 + P1 - 1) / P1, n2c = (p->ne2 - c2 + P2 - 1) / P2;
+          const int64_t nblk = (int64_t)n1c * n2c * p->n_sets;
+          if (nblk > 0)
+            hipLaunchKernelGGL(k_p2d_field, dim3((unsigned)nblk), dim3(thr), lds, s, d, c1, c2, n1c, n2c);
+        }
+    }
     hipLaunchKernelGGL(k_q1d, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, d, theta);
     void *prof = lam::profile_begin(0, stream);
     launch_kron(p, d, vals, s);
@@ -1284,7 +1306,7 @@ extern "C" LAM_API lam_status lam_apply(const lam_plan *p, void *ws, int64_t ws_
   if (st != LAM_OK) return st;
   if (!C || !theta || !u || !y) return LAM_EINVAL;
   if (n_rows != p->nrows) return LAM_ESIZE;
-  if (p->kron_nsc < 1 || p->kron_nsc > 2) return LAM_EUNSUP;
+  if (p->kron_nsc < 1 || p->kron_nsc > 2 || p->mat_field) return LAM_EUNSUP;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Dev d = make_dev(p, ws);
   launch_prep(p, d, C, theta, s);
@@ -1601,7 +1623,7 @@ extern "C" LAM_API lam_status lam_cg(const lam_plan *p, void *ws, int64_t ws_byt
   if (st != LAM_OK) return st;
   if (!C || !theta || !b || !x || !work || !iters || !rel_res || max_iter < 0 || !(tol >= 0.0)) return LAM_EINVAL;
   if (n_rows != p->nrows || work_bytes < lam_cg_work_bytes(p)) return LAM_ESIZE;
-  if (p->kron_nsc < 1 || p->kron_nsc > 2) return LAM_EUNSUP;
+  if (p->kron_nsc < 1 || p->kron_nsc > 2 || p->mat_field) return LAM_EUNSUP;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Dev d = make_dev(p, ws);
   const int64_t n = n_rows;

@@ -544,8 +544,10 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
   int nsc_cap = 2;  // fewer slots keep more waves resident; chunks reload P from cache
   if (tune && tune->set_slots > 0) nsc_cap = tune->set_slots;
   // material fields: P of every set is integrated over the plane with the
-  // field inside, stored, and read by the LDS-mode scatter
-  const bool reg_mode = P->maxact <= 8 && !P->mat_field;
+  // field inside and stored; the register-mode scatter loads it per chunk
+  // (one or two slots), the LDS-mode scatter stages it
+  const bool reg_mode = P->maxact <= (P->mat_field ? 2 : 8);
+  if (P->mat_field) nsc_cap = 2;
   int sc, tkmax = tk_target;
   int64_t qbudget = 8 * 1024, lds_budget = 80 * 1024;
   if (tune && tune->lds_kib > 0) lds_budget = std::max<int64_t>(16 * 1024, (int64_t)tune->lds_kib * 1024);
@@ -842,7 +844,7 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
   L.Ec = B.take(sizeof(double) * 81 * P->n_sets);
   // P of every set is stored only by the LDS-mode scatter; the register mode
   // contracts it from the moments M
-  L.P = B.take(P->kron_nsc > 0 ? 0 : sizeof(double) * 36 * (int64_t)P->n_sets * P->nnz2);
+  L.P = B.take(P->kron_nsc > 0 && !P->mat_field ? 0 : sizeof(double) * 36 * (int64_t)P->n_sets * P->nnz2);
   L.Qc = B.take(sizeof(double) * 4 * (int64_t)std::max(P->maxact, P->kron_nsc) * P->nnzz);
   L.M = B.take(sizeof(double) * 36 * ((P->nnz2 + 63) / 64 * 64));  // blocks of 64 nonzeros (m_index)
   L.Eply = B.take(sizeof(double) * 81 * P->n_ply);
