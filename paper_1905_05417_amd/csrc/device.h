@@ -532,18 +532,25 @@ __device__ __forceinline__ void kron_row(const double *qq, const double (&pr)[NS
 
 // Register-mode scatter of one (tile of whole in-plane rows, group of
 // consecutive thickness chunks) item with one or two set slots per chunk (every
-// bucket and per-ply plan): the block stages the group's slot-dense
-// coefficients Qd[zk][slot][ab] and the bracket coefficients of the group's
-// sets in LDS behind one barrier; then per chunk each thread (in-plane nonzero
-// k, component t) contracts P of the chunk's slots from the set-independent
-// moments M_ab[kl] and the slot's brackets E_s[kl][rt] (eq. P; P is never
-// stored) and writes the chunk's rows.  After the barrier the block issues no
-// vector load, so no wait on a load also waits for the stores in flight.
+// bucket and per-ply plan): the block stages the bracket coefficients of the
+// group's sets in LDS behind one barrier; then per chunk each thread (in-plane
+// nonzero k, component t) contracts P of the chunk's slots from the
+// set-independent moments M_ab[kl] and the slot's brackets E_s[kl][rt] (eq. P;
+// P is never stored; material-field plans load their stored P instead) and
+// writes the chunk's rows.  A row's slot-dense coefficients Qd[zk][slot][ab]
+// are the same for the whole block.  QSCALAR (qd a restrict kernel argument,
+// so the compiler can prove no store reaches it): they are read from global
+// memory through scalar loads into scalar registers, which keeps them out of
+// the vector registers and, as scalar loads are counted apart from vector
+// memory operations, waits on no store in flight.  Otherwise (the batch, whose
+// qd comes from a table) the block stages the group's coefficients in LDS.
+// After the barrier the block issues no vector load (for constant materials).
 // Block-cooperative: every thread of the block calls it with the same item
 // (it holds a barrier; threads past 3 * tile_k return after it).  lq: LDS of
-// kron_lds_q bytes of coefficients, then 81 doubles per set of the group and
-// 81 zeros.  The single-laminate scatter and the batched one both run it.
-template <int NSC>
+// kron_lds_q bytes for the coefficients (used when staged), then 81 doubles
+// per set of the group and 81 zeros.  The single-laminate scatter and the
+// batched one both run it.
+template <int NSC, bool QSCALAR>
 __device__ __forceinline__ void kron_group(const Dev &d, const double *__restrict__ qd, double *__restrict__ vals,
                                            int tile, int g, double *lq, int sig, int nthreads) {
   static_assert(NSC <= 2, "grouped scatter items keep at most two set slots");
@@ -560,13 +567,15 @@ __device__ __forceinline__ void kron_group(const Dev &d, const double *__restric
   const int64_t astride = 3 * (int64_t)Ls;
   double *le = lq + d.kron_lds_q / 8;
   const int ch0 = d.group_ptr[g], ch1 = d.group_ptr[g + 1];
-  const int zk0 = d.zrow[d.chunk_ptr[ch0]], nq = 4 * NSC * (d.zrow[d.chunk_ptr[ch1]] - zk0);
   const int s0 = d.group_sptr[g], ns = d.group_sptr[g + 1] - s0;
   for (int e = sig; e < 81 * (ns + 1); e += nthreads) {
     const int u = e / 81;
     le[e] = u < ns ? d.Escat[81 * (int64_t)d.group_set[s0 + u] + (e - 81 * u)] : 0.0;
   }
-  for (int e = sig; e < nq; e += nthreads) lq[e] = qd[4 * (int64_t)NSC * zk0 + e];
+  if constexpr (!QSCALAR) {
+    const int zk0 = d.zrow[d.chunk_ptr[ch0]], nq = 4 * NSC * (d.zrow[d.chunk_ptr[ch1]] - zk0);
+    for (int e = sig; e < nq; e += nthreads) lq[e] = qd[4 * (int64_t)NSC * zk0 + e];
+  }
   __syncthreads();
   if (!act) return;  // no barrier follows
   double pr[NSC][4][3];
@@ -605,7 +614,10 @@ __device__ __forceinline__ void kron_group(const Dev &d, const double *__restric
       const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
       double *out = vals + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
       const int64_t rstride = 3 * (int64_t)Lz * Ls;
-      const double *qz = lq + 4 * NSC * (zb - zk0);
+      // the row's coefficients are uniform over the block: read from global
+      // memory they go through scalar loads into scalar registers (and
+      // scalar loads do not wait on the vector stores in flight)
+      const double *qz = QSCALAR ? qd + 4 * NSC * (int64_t)zb : lq + 4 * NSC * (zb - d.zrow[d.chunk_ptr[ch0]]);
       switch (Lz) {  // widths 2..5 (q + 1 up to q = 4, 2q + 1 up to q = 2) fixed; 7 and 9 take the loop
         case 2: kron_row<NSC, 2>(qz, pr, out, rstride, astride); break;
         case 3: kron_row<NSC, 3>(qz, pr, out, rstride, astride); break;
@@ -618,7 +630,8 @@ __device__ __forceinline__ void kron_group(const Dev &d, const double *__restric
             for (int x = 0; x < KRON_AB; ++x) {
               acc[x][0] = acc[x][1] = acc[x][2] = 0.0;
               if (ab0 + x < Lz) {
-                const double *qq = lq + 4 * NSC * (zb + ab0 + x - zk0);
+                const double *qq = QSCALAR ? qd + 4 * NSC * (int64_t)(zb + ab0 + x)
+                                           : lq + 4 * NSC * (zb + ab0 + x - d.zrow[d.chunk_ptr[ch0]]);
 #pragma unroll
                 for (int u = 0; u < NSC; ++u) {
                   const double q0 = qq[4 * u], q1 = qq[4 * u + 1], q2 = qq[4 * u + 2], q3 = qq[4 * u + 3];

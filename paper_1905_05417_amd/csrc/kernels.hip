@@ -311,12 +311,12 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron_lds(Dev d, double *__rest
 
 // Register mode of the scatter.
 //  - one or two set slots (every bucket and per-ply plan): one block per
-//    (tile, group of chunks).  The block stages the group's slot-dense
-//    coefficients Qd[zk][slot][ab] and the bracket coefficients of the group's
-//    sets in LDS behind one barrier; then per chunk each thread contracts P of
-//    the chunk's slots for its (k, t) into registers and writes the chunk's
-//    rows.  After the barrier the block issues no vector loads, so no wait on a
-//    load also waits for the stores in flight, and the stores stream.
+//    (tile, group of chunks).  The block stages the bracket coefficients of
+//    the group's sets in LDS behind one barrier; then per chunk each thread
+//    contracts P of the chunk's slots for its (k, t) into registers and writes
+//    the chunk's rows, the rows' coefficients read through scalar loads.
+//    After the barrier the block issues no vector loads, so no wait on a load
+//    also waits for the stores in flight, and the stores stream.
 //  - four or eight slots: one block per (tile, chunk) (the planner gives each
 //    group one chunk), P of the slots in registers, coefficients in LDS.
 // P at (k, t) is contracted from the set-independent moments M_ab[kl] (one
@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron_reg(Dev d, const double *
   int tile, g;
   if (!kron_block(d, tile, g)) return;
   if constexpr (NSC <= 2) {
-    lamdev::kron_group<NSC>(d, qd, vals, tile, g, lq, (int)threadIdx.x, (int)blockDim.x);
+    lamdev::kron_group<NSC, true>(d, qd, vals, tile, g, lq, (int)threadIdx.x, (int)blockDim.x);
   } else {
     const int k0 = d.tiles[tile], tk = d.tiles[tile + 1] - k0;
     const int sig = threadIdx.x;
