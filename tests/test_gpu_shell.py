@@ -117,6 +117,25 @@ def test_material_field_fast(oracle, L, case):
         _full(oracle, L, lam, mode, ref=ref)
 
 
+@pytest.mark.parametrize("case", ["thick_element", "degree4"])
+def test_material_field_other_paths(oracle, L, case):
+    """Material fields on the two paths the benchmark shapes do not reach: one
+    element through four plies of four orientations (more than two sets act on
+    a thickness row, so the scatter stages the stored P in LDS) and in-plane
+    degree 4 (25 local functions: 625 pairs per element, more than one pass of
+    the element-wise P kernel's threads)."""
+    rng = np.random.default_rng(8250 if case == "thick_element" else 8260)
+    if case == "thick_element":
+        base = W.flat_shell(W.paper_plate(2, 3, 4, "0/45/-45/90"))
+    else:
+        base = W.curved_shell(4, 3, 1, [0, 60], [W.material(W.CARBON)], [0, 0], ne2=2, name="curved_p4")
+    lam = W.smooth_material_field(base, rng)
+    print("case", case, lam.name, flush=True)
+    ref = oracle.assemble(lam)
+    for mode in ("bucket", "ply"):
+        _full(oracle, L, lam, mode, ref=ref)
+
+
 def test_material_field_limits(L):
     lam = W.smooth_material_field(_curved(0), np.random.default_rng(8300))
     plan = L.Plan(lam, set_mode="bucket")
