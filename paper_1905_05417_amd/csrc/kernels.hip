@@ -673,6 +673,79 @@ __device__ inline void std_add(const Dev &d, double *__restrict__ vals, int e1, 
         for (int r = 0; r < 3; ++r) rowp[v][t * rstr[v] + r] = old[v][t * 3 + r] + ke[v][r * 3 + t];
 }
 
+// std_add in two halves for callers that can issue the reads early: the
+// direct block's CSR values (K_ab's entries) are read before the element
+// matrix exists (their addresses do not depend on it), so the read latency
+// overlaps the products; std_add_late then adds and writes them and does the
+// transposed block as std_add does.
+__device__ inline void std_add_early(const Dev &d, const double *__restrict__ vals, int e1, int e2, int zsp, int I,
+                                     int J, double old[4][9]) {
+  const int lane = threadIdx.x & 63, li = lane & 15, kk = lane >> 4;
+  const int P1 = d.p1 + 1, P2 = d.p2 + 1, Q1 = d.q + 1, nloc = P1 * P2 * Q1;
+  const int b = min(16 * J + li, nloc - 1);  // padded lanes read a valid entry and never write it
+  const int f1 = d.e1first[e1], f2 = d.e2first[e2], fz = d.zs_first[zsp];
+  const int j1 = f1 + b % P1, j2 = f2 + (b / P1) % P2, jt = fz + b / (P1 * P2);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int a = min(16 * I + kk + 4 * v, nloc - 1);
+    const int i1 = f1 + a % P1, i2 = f2 + (a / P1) % P2, it = fz + a / (P1 * P2);
+    int64_t rs;
+    const double *row = std_entry(d, const_cast<double *>(vals), i1, i2, it, j1, j2, jt, rs);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int t = 0; t < 3; ++t) old[v][r * 3 + t] = row[r * rs + t];
+  }
+}
+
+__device__ inline void std_add_late(const Dev &d, double *__restrict__ vals, int e1, int e2, int zsp, int I, int J,
+                                    const double ke[4][9], const double old[4][9]) {
+  const int lane = threadIdx.x & 63, li = lane & 15, kk = lane >> 4;
+  const int P1 = d.p1 + 1, P2 = d.p2 + 1, Q1 = d.q + 1, nloc = P1 * P2 * Q1;
+  const int b = 16 * J + li;
+  if (b >= nloc) return;
+  const int f1 = d.e1first[e1], f2 = d.e2first[e2], fz = d.zs_first[zsp];
+  const int j1 = f1 + b % P1, j2 = f2 + (b / P1) % P2, jt = fz + b / (P1 * P2);
+  const int nv = min(4, (nloc - 16 * I - kk + 3) / 4);
+  double *rowp[4];
+  int64_t rstr[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int a = min(16 * I + kk + 4 * v, nloc - 1);
+    const int i1 = f1 + a % P1, i2 = f2 + (a / P1) % P2, it = fz + a / (P1 * P2);
+    rowp[v] = std_entry(d, vals, i1, i2, it, j1, j2, jt, rstr[v]);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    if (v < nv)
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int t = 0; t < 3; ++t) rowp[v][r * rstr[v] + t] = old[v][r * 3 + t] + ke[v][r * 3 + t];
+  if (I == J) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int a = min(16 * I + kk + 4 * v, nloc - 1);
+    const int i1 = f1 + a % P1, i2 = f2 + (a / P1) % P2, it = fz + a / (P1 * P2);
+    rowp[v] = std_entry(d, vals, j1, j2, jt, i1, i2, it, rstr[v]);
+  }
+  double ot[4][9];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    if (v < nv)
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) ot[v][t * 3 + r] = rowp[v][t * rstr[v] + r];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    if (v < nv)
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) rowp[v][t * rstr[v] + r] = ot[v][t * 3 + r] + ke[v][r * 3 + t];
+}
+
 // tile pair u (0 <= u < tiles (tiles + 1) / 2) -> (I, J), I <= J
 __device__ inline void std_pair(int tiles, int u, int &I, int &J) {
   I = 0;
@@ -729,6 +802,8 @@ __global__ void __launch_bounds__(64 * STD_LDS_WAVES, 2) k_std3d_lds(Dev d, doub
   const int lane = threadIdx.x & 63, li = lane & 15, kk = lane >> 4;
   int I, J;
   std_pair(tiles, __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), I, J);
+  double old[4][9];  // the direct block's CSR values, read now, added after the products
+  std_add_early(d, vals, e1, e2, zsp, I, J, old);
   std_dbl4 m[9];
 #pragma unroll
   for (int e = 0; e < 9; ++e) m[e] = std_dbl4{0.0, 0.0, 0.0, 0.0};
@@ -753,7 +828,7 @@ __global__ void __launch_bounds__(64 * STD_LDS_WAVES, 2) k_std3d_lds(Dev d, doub
 #pragma unroll
     for (int e = 0; e < 9; ++e) ke[v][e] = 0.0;
   std_contract(m, d.Eply + 81 * d.zply[c], ke);
-  std_add(d, vals, e1, e2, zsp, I, J, ke);
+  std_add_late(d, vals, e1, e2, zsp, I, J, ke, old);
 }
 
 // Elements of any number of ply cells: every (element, tile pair) is a
