@@ -325,8 +325,10 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron_lds(Dev d, double *__rest
 template <int NSC>
 __global__ void __launch_bounds__(KRON_THREADS) k_kron_reg(Dev d, const double *__restrict__ qd,
                                                            double *__restrict__ vals) {
-  // LDS: slot-dense coefficients [zk - zk0][NSC][4] (kron_lds_q bytes), then
-  // bracket coefficients [81] per set of the group and one zero block (or per slot)
+  // LDS: slot-dense coefficients [zk - zk0][NSC][4] (kron_lds_q bytes; left
+  // unused by the one- and two-slot path, which reads them through scalar
+  // loads), then bracket coefficients [81] per set of the group and one zero
+  // block (or per slot)
   extern __shared__ double lq[];
   int tile, g;
   if (!kron_block(d, tile, g)) return;

@@ -287,6 +287,8 @@ class Plan:
         return out
 
     def assemble_standard(self, C, theta, out=None):
+        """The same CSR values by the standard element-by-element 3D assembly
+        (lam_assemble_standard, the comparator of Sec. 2.4)."""
         ws = self._ws()
         C, theta = self._inputs(C, theta)
         vals = torch.empty(self.nnz, dtype=torch.float64, device=self.device) if out is None else out

@@ -1,5 +1,10 @@
 """GPU parity of the standard 3D element-by-element assembly (the comparator of
-the method) against the CPU oracle, and fast vs standard on the same CSR."""
+the method) against the CPU oracle, and fast vs standard on the same CSR.
+
+The cases reach both element kernels: one ply cell per element with at most
+eight 16-wide tile pairs of local functions (the block-per-element kernel with
+the gradient table in LDS: degrees 1-3 layerwise) and the wavefront-per-pair
+kernel (degree 4, and one element through several plies)."""
 import numpy as np
 import pytest
 import torch
