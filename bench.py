@@ -103,6 +103,17 @@ KERNEL_ONLY_WORKLOADS = {"p3_128x128_128ply": (lambda W: W.config_p3_128x128_128
                                                                 "bucket")}
 
 
+def _calibration_copy(torch, mib):
+    """One plain device copy of mib MiB (its counters scale the FETCH_SIZE and
+    WRITE_SIZE of the other kernels of the same profiled run)."""
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    return 8 * n
+
+
 def _kernel_only(args, torch, np, L, W):
     """--steps calls of one entry point on one workload and nothing else (no
     timing beyond the wall clock, no parity), so a profiler's counters cover
@@ -140,8 +151,11 @@ def _kernel_only(args, torch, np, L, W):
         step()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
-    print(json.dumps({"kernel_only": args.kernel_only, "workload": lam.name, "nnz": plan.nnz, "steps": args.steps,
-                      "warmup": args.warmup, "ms_per_step_wall": ms}), flush=True)
+    out = {"kernel_only": args.kernel_only, "workload": lam.name, "nnz": plan.nnz, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step_wall": ms}
+    if args.calibrate_copy_mib:
+        out["calibration_copy_bytes"] = _calibration_copy(torch, args.calibrate_copy_mib)
+    print(json.dumps(out), flush=True)
 
 
 def _kernel_source_hash():
@@ -759,12 +773,7 @@ def main():
     out["extra"] = extra
 
     if args.calibrate_copy_mib:
-        n = args.calibrate_copy_mib * (1 << 20) // 8
-        a = torch.ones(n, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        out["calibration_copy_bytes"] = 8 * n
+        out["calibration_copy_bytes"] = _calibration_copy(torch, args.calibrate_copy_mib)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(O, W)
