@@ -544,37 +544,54 @@ __device__ __forceinline__ void kron_row(const double *qq, const double (&pr)[NS
 // the vector registers and, as scalar loads are counted apart from vector
 // memory operations, waits on no store in flight.  Otherwise (the batch, whose
 // qd comes from a table) the block stages the group's coefficients in LDS.
-// After the barrier the block issues no vector load (for constant materials).
+// After the barrier the block issues no vector load (constant materials): a
+// vector load on any path into the row loop would make every row wait for all
+// of the wave's stores in flight (loads and stores share one counter on this
+// chip).  FIELD (material fields), a separate instantiation: each slot's P is
+// read from the stored P of its set, at every set change.
 // Block-cooperative: every thread of the block calls it with the same item
 // (it holds a barrier; threads past 3 * tile_k return after it).  lq: LDS of
 // kron_lds_q bytes for the coefficients (used when staged), then 81 doubles
 // per set of the group and 81 zeros.  The single-laminate scatter and the
 // batched one both run it.
-template <int NSC, bool QSCALAR>
+// A value that is the same for the whole block, read from a plan table (the
+// tables are written before any launch and only read while kernels run)
+// through the constant address space: a scalar load, counted apart from the
+// vector memory operations (whose counter includes the stores in flight), also
+// where the compiler cannot see that the table is unwritten (the batch reads
+// its per-laminate views from memory).
+__device__ __forceinline__ int uld(const int *p, int64_t i) {
+  return reinterpret_cast<const __attribute__((address_space(4))) int *>(reinterpret_cast<uintptr_t>(p))[i];
+}
+
+template <int NSC, bool QSCALAR, bool FIELD>
 __device__ __forceinline__ void kron_group(const Dev &d, const double *__restrict__ qd, double *__restrict__ vals,
                                            int tile, int g, double *lq, int sig, int nthreads) {
   static_assert(NSC <= 2, "grouped scatter items keep at most two set slots");
-  const int k0 = d.tiles[tile], tk = d.tiles[tile + 1] - k0;
+  const int k0 = uld(d.tiles, tile), tk = uld(d.tiles, tile + 1) - k0;
   const bool act = sig < 3 * tk;
   const int kk = act ? sig / 3 : 0, t = act ? sig - 3 * kk : 0, k = k0 + kk;
-  double mv[4][9];  // the moments (not used by material-field plans, whose P is stored)
+  double mv[4][9];  // the moments (material fields read their stored P instead)
+  if constexpr (!FIELD) {
 #pragma unroll
-  for (int ab = 0; ab < 4; ++ab)
+    for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
-    for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.mat_field ? 0.0 : d.M[m_index(k, ab * 9 + kl)];
+      for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[m_index(k, ab * 9 + kl)];
+  }
   const int is = d.krow[k], sr = d.srow[is];
   const int Ls = d.srow[is + 1] - sr, off = 3 * (k - sr) + t;
   const int64_t astride = 3 * (int64_t)Ls;
   double *le = lq + d.kron_lds_q / 8;
-  const int ch0 = d.group_ptr[g], ch1 = d.group_ptr[g + 1];
-  const int s0 = d.group_sptr[g], ns = d.group_sptr[g + 1] - s0;
+  const int ch0 = uld(d.group_ptr, g), ch1 = uld(d.group_ptr, g + 1);
+  const int s0 = uld(d.group_sptr, g), ns = uld(d.group_sptr, g + 1) - s0;
+  const int zq0 = uld(d.zrow, uld(d.chunk_ptr, ch0));  // the group's first thickness nonzero
   for (int e = sig; e < 81 * (ns + 1); e += nthreads) {
     const int u = e / 81;
-    le[e] = u < ns ? d.Escat[81 * (int64_t)d.group_set[s0 + u] + (e - 81 * u)] : 0.0;
+    le[e] = u < ns ? d.Escat[81 * (int64_t)uld(d.group_set, s0 + u) + (e - 81 * u)] : 0.0;
   }
   if constexpr (!QSCALAR) {
-    const int zk0 = d.zrow[d.chunk_ptr[ch0]], nq = 4 * NSC * (d.zrow[d.chunk_ptr[ch1]] - zk0);
-    for (int e = sig; e < nq; e += nthreads) lq[e] = qd[4 * (int64_t)NSC * zk0 + e];
+    const int nq = 4 * NSC * (uld(d.zrow, uld(d.chunk_ptr, ch1)) - zq0);
+    for (int e = sig; e < nq; e += nthreads) lq[e] = qd[4 * (int64_t)NSC * zq0 + e];
   }
   __syncthreads();
   if (!act) return;  // no barrier follows
@@ -583,15 +600,15 @@ __device__ __forceinline__ void kron_group(const Dev &d, const double *__restric
 #pragma unroll
   for (int u = 0; u < NSC; ++u) slot_set[u] = -1;
   for (int ch = ch0; ch < ch1; ++ch) {
-    const int it0 = d.chunk_ptr[ch], it1 = d.chunk_ptr[ch + 1];
-    const int c0 = d.chunk_sptr[ch], nsc = d.chunk_sptr[ch + 1] - c0;
+    const int it0 = uld(d.chunk_ptr, ch), it1 = uld(d.chunk_ptr, ch + 1);
+    const int c0 = uld(d.chunk_sptr, ch), nsc = uld(d.chunk_sptr, ch + 1) - c0;
 #pragma unroll
     for (int u = 0; u < NSC; ++u) {
-      const int ls = u < nsc ? d.chunk_lset[c0 + u] : ns;  // unused slots: the zero block
+      const int ls = u < nsc ? uld(d.chunk_lset, c0 + u) : ns;  // unused slots: the zero block
       if (ls == slot_set[u]) continue;  // the slot keeps its set (and P) from the previous chunk
       slot_set[u] = ls;
-      if (d.mat_field) {  // P of the slot's set from memory (zero for an unused slot)
-        const int gs = ls < ns ? d.group_set[s0 + ls] : -1;
+      if constexpr (FIELD) {  // P of the slot's set from memory (zero for an unused slot)
+        const int gs = ls < ns ? uld(d.group_set, s0 + ls) : -1;
 #pragma unroll
         for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
@@ -611,13 +628,13 @@ __device__ __forceinline__ void kron_group(const Dev &d, const double *__restric
         }
     }
     for (int it = it0; it < it1; ++it) {
-      const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
+      const int zb = uld(d.zrow, it), Lz = uld(d.zrow, it + 1) - zb;
       double *out = vals + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
       const int64_t rstride = 3 * (int64_t)Lz * Ls;
       // the row's coefficients are uniform over the block: read from global
       // memory they go through scalar loads into scalar registers (and
       // scalar loads do not wait on the vector stores in flight)
-      const double *qz = QSCALAR ? qd + 4 * NSC * (int64_t)zb : lq + 4 * NSC * (zb - d.zrow[d.chunk_ptr[ch0]]);
+      const double *qz = QSCALAR ? qd + 4 * NSC * (int64_t)zb : lq + 4 * NSC * (zb - zq0);
       switch (Lz) {  // widths 2..5 (q + 1 up to q = 4, 2q + 1 up to q = 2) fixed; 7 and 9 take the loop
         case 2: kron_row<NSC, 2>(qz, pr, out, rstride, astride); break;
         case 3: kron_row<NSC, 3>(qz, pr, out, rstride, astride); break;
@@ -631,7 +648,7 @@ __device__ __forceinline__ void kron_group(const Dev &d, const double *__restric
               acc[x][0] = acc[x][1] = acc[x][2] = 0.0;
               if (ab0 + x < Lz) {
                 const double *qq = QSCALAR ? qd + 4 * NSC * (int64_t)(zb + ab0 + x)
-                                           : lq + 4 * NSC * (zb + ab0 + x - d.zrow[d.chunk_ptr[ch0]]);
+                                           : lq + 4 * NSC * (zb + ab0 + x - zq0);
 #pragma unroll
                 for (int u = 0; u < NSC; ++u) {
                   const double q0 = qq[4 * u], q1 = qq[4 * u + 1], q2 = qq[4 * u + 2], q3 = qq[4 * u + 3];

@@ -321,8 +321,9 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron_lds(Dev d, double *__rest
 //    group one chunk), P of the slots in registers, coefficients in LDS.
 // P at (k, t) is contracted from the set-independent moments M_ab[kl] (one
 // table for all sets) and a slot's bracket coefficients E_s[kl][rt] (eq. P):
-// P is never stored.
-template <int NSC>
+// P is never stored.  FIELD (one or two slots, materials varying over the
+// plane): P of every set is stored and read per set change instead.
+template <int NSC, bool FIELD>
 __global__ void __launch_bounds__(KRON_THREADS) k_kron_reg(Dev d, const double *__restrict__ qd,
                                                            double *__restrict__ vals) {
   // LDS: slot-dense coefficients [zk - zk0][NSC][4] (kron_lds_q bytes; left
@@ -333,7 +334,7 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron_reg(Dev d, const double *
   int tile, g;
   if (!kron_block(d, tile, g)) return;
   if constexpr (NSC <= 2) {
-    lamdev::kron_group<NSC, true>(d, qd, vals, tile, g, lq, (int)threadIdx.x, (int)blockDim.x);
+    lamdev::kron_group<NSC, true, FIELD>(d, qd, vals, tile, g, lq, (int)threadIdx.x, (int)blockDim.x);
   } else {
     const int k0 = d.tiles[tile], tk = d.tiles[tile + 1] - k0;
     const int sig = threadIdx.x;
@@ -1192,10 +1193,20 @@ void launch_kron(const lam_plan *p, const Dev &d, double *vals, hipStream_t s) {
   const size_t lds = (size_t)p->kron_lds;
   const dim3 blk(p->kron_threads);
   switch (p->kron_nsc) {
-    case 1: hipLaunchKernelGGL((k_kron_reg<1>), dim3(grid), blk, lds, s, d, d.Qc, vals); return;
-    case 2: hipLaunchKernelGGL((k_kron_reg<2>), dim3(grid), blk, lds, s, d, d.Qc, vals); return;
-    case 4: hipLaunchKernelGGL((k_kron_reg<4>), dim3(grid), blk, lds, s, d, d.Qc, vals); return;
-    case 8: hipLaunchKernelGGL((k_kron_reg<8>), dim3(grid), blk, lds, s, d, d.Qc, vals); return;
+    case 1:
+      if (p->mat_field)
+        hipLaunchKernelGGL((k_kron_reg<1, true>), dim3(grid), blk, lds, s, d, d.Qc, vals);
+      else
+        hipLaunchKernelGGL((k_kron_reg<1, false>), dim3(grid), blk, lds, s, d, d.Qc, vals);
+      return;
+    case 2:
+      if (p->mat_field)
+        hipLaunchKernelGGL((k_kron_reg<2, true>), dim3(grid), blk, lds, s, d, d.Qc, vals);
+      else
+        hipLaunchKernelGGL((k_kron_reg<2, false>), dim3(grid), blk, lds, s, d, d.Qc, vals);
+      return;
+    case 4: hipLaunchKernelGGL((k_kron_reg<4, false>), dim3(grid), blk, lds, s, d, d.Qc, vals); return;
+    case 8: hipLaunchKernelGGL((k_kron_reg<8, false>), dim3(grid), blk, lds, s, d, d.Qc, vals); return;
     default: break;
   }
   if (p->chunk_sets > 0)
