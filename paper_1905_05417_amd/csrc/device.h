@@ -511,17 +511,21 @@ template <int NSC, int LZ>
 __device__ __forceinline__ void kron_row(const double *qq, const double (&pr)[NSC][4][3], double *out,
                                          int64_t rstride, int64_t astride) {
   double acc[LZ][3];
+  // slot-outer: one slot's coefficients of every column are read together
 #pragma unroll
-  for (int x = 0; x < LZ; ++x) {
-    const double *q = qq + 4 * NSC * x;
+  for (int u = 0; u < NSC; ++u) {
+    double qv[LZ][4];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) acc[x][r] = q[0] * pr[0][0][r] + q[1] * pr[0][1][r] + q[2] * pr[0][2][r] + q[3] * pr[0][3][r];
+    for (int x = 0; x < LZ; ++x)
 #pragma unroll
-    for (int u = 1; u < NSC; ++u) {
-      const double q0 = q[4 * u], q1 = q[4 * u + 1], q2 = q[4 * u + 2], q3 = q[4 * u + 3];
+      for (int ab = 0; ab < 4; ++ab) qv[x][ab] = qq[4 * NSC * x + 4 * u + ab];
 #pragma unroll
-      for (int r = 0; r < 3; ++r) acc[x][r] += q0 * pr[u][0][r] + q1 * pr[u][1][r] + q2 * pr[u][2][r] + q3 * pr[u][3][r];
-    }
+    for (int x = 0; x < LZ; ++x)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const double v = qv[x][0] * pr[u][0][r] + qv[x][1] * pr[u][1][r] + qv[x][2] * pr[u][2][r] + qv[x][3] * pr[u][3][r];
+        acc[x][r] = u == 0 ? v : acc[x][r] + v;
+      }
   }
 #pragma unroll
   for (int r = 0; r < 3; ++r)
@@ -627,8 +631,11 @@ __device__ __forceinline__ void kron_group(const Dev &d, const double *__restric
           pr[u][ab][r] = a;
         }
     }
+    int zb = uld(d.zrow, it0), zn = uld(d.zrow, it0 + 1);
     for (int it = it0; it < it1; ++it) {
-      const int zb = uld(d.zrow, it), Lz = uld(d.zrow, it + 1) - zb;
+      // the next row's end, read a row ahead (zrow has nt + 1 entries)
+      const int zn2 = uld(d.zrow, it + 2 <= d.nt ? it + 2 : d.nt);
+      const int Lz = zn - zb;
       double *out = vals + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
       const int64_t rstride = 3 * (int64_t)Lz * Ls;
       // the row's coefficients are uniform over the block: read from global
@@ -665,6 +672,8 @@ __device__ __forceinline__ void kron_group(const Dev &d, const double *__restric
                 if (ab0 + x < Lz) out[r * rstride + (int64_t)(ab0 + x) * astride] = acc[x][r];
           }
       }
+      zb = zn;
+      zn = zn2;
     }
   }
 }
