@@ -159,8 +159,10 @@ def _kernel_only(args, torch, np, L, W):
 
 
 def _kernel_source_hash():
+    """Hash of the sources the single-laminate kernels are built from (the
+    scatter's row code is in device.h)."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "internal.h", "plan.cpp"):
+    for f in ("kernels.hip", "device.h", "internal.h", "plan.cpp"):
         with open(os.path.join(ROOT, "paper_1905_05417_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
