@@ -979,22 +979,27 @@ __global__ void __launch_bounds__(ADJ_THREADS) k_adj_stream(Dev d, const double 
   const int64_t astride = 3 * (int64_t)Ls;
   // software pipeline over row pairs: the G values of the next row are in
   // flight while a row is contracted (one row's loads alone leave the stream
-  // latency bound).  Inactive threads load their block's first nonzero (in
-  // bounds) so that the loads need no divergent branch.
+  // latency bound).  Every load is unconditional (rows past the last reload
+  // it, never used): a load on only one path would make the wait for the
+  // current row also wait for the next row's loads.  Inactive threads load
+  // their block's first nonzero (in bounds), so the loads need no divergent
+  // branch either.  RANK1 keeps the raw u values (u of the row's columns in
+  // g[a][0], of the row itself in g[0][1], g[0][2], g[1][1]) and multiplies
+  // when the row is used.
   const int js = d.kcol[k];
   auto load_row = [&](int it, double (&g)[LZ][3]) {
+    it = it < d.nt ? it : d.nt - 1;
     const int zb = d.zrow[it], Lz = d.zrow[it + 1] - zb;
     if constexpr (RANK1) {
       // G[(it, is, r), (jt, js, t)] = u[3 (it ns + is) + r] u[3 (jt ns + js) + t]
       const double *ur = src + 3 * ((int64_t)it * d.ns + is);
-      const double u0 = ur[0], u1 = ur[1], u2 = ur[2];
+      g[0][1] = ur[0];
+      g[0][2] = ur[1];
+      g[1][1] = ur[2];
 #pragma unroll
       for (int a = 0; a < LZ; ++a) {
         const int ac = a < Lz ? a : Lz - 1;  // past the row: a valid address, weighted by 0
-        const double uc = src[3 * ((int64_t)d.zcol[zb + ac] * d.ns + js) + t];
-        g[a][0] = u0 * uc;
-        g[a][1] = u1 * uc;
-        g[a][2] = u2 * uc;
+        g[a][0] = src[3 * ((int64_t)d.zcol[zb + ac] * d.ns + js) + t];
       }
     } else {
       const double *row = src + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
@@ -1008,7 +1013,20 @@ __global__ void __launch_bounds__(ADJ_THREADS) k_adj_stream(Dev d, const double 
       }
     }
   };
-  auto use_row = [&](int it, const double (&g)[LZ][3]) {
+  auto use_row = [&](int it, const double (&gin)[LZ][3]) {
+    double g[LZ][3];
+#pragma unroll
+    for (int a = 0; a < LZ; ++a) {
+      if constexpr (RANK1) {
+        g[a][0] = gin[0][1] * gin[a][0];
+        g[a][1] = gin[0][2] * gin[a][0];
+        g[a][2] = gin[1][1] * gin[a][0];
+      } else {
+        g[a][0] = gin[a][0];
+        g[a][1] = gin[a][1];
+        g[a][2] = gin[a][2];
+      }
+    }
     const double *q = qp + (int64_t)it * LZ * 8;  // padded: zeros past the row's width
 #pragma unroll
     for (int a = 0; a < LZ; ++a)
@@ -1048,12 +1066,10 @@ __global__ void __launch_bounds__(ADJ_THREADS) k_adj_stream(Dev d, const double 
   double ga[LZ][3], gb[LZ][3];
   load_row(0, ga);
   for (int it = 0; it < d.nt; it += 2) {
-    if (it + 1 < d.nt) load_row(it + 1, gb);
+    load_row(it + 1, gb);
     use_row(it, ga);
-    if (it + 1 < d.nt) {
-      if (it + 2 < d.nt) load_row(it + 2, ga);
-      use_row(it + 1, gb);
-    }
+    load_row(it + 2, ga);
+    if (it + 1 < d.nt) use_row(it + 1, gb);
   }
 }
 
