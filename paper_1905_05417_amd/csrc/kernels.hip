@@ -198,11 +198,20 @@ __global__ void __launch_bounds__(256) k_p2d_field(Dev d, int c1, int c2, int n1
     // the pair's in-plane nonzero: row is = i1 + n1 i2, column js = j1 + n1 j2
     const int i1 = f1 + la % P1, i2 = f2 + la / P1, j1 = f1 + lb % P1, j2 = f2 + lb / P1;
     const int64_t k = d.srow[i1 + d.n1 * i2] + (int64_t)(j2 - d.a2f[i2]) * d.a1c[i1] + (j1 - d.a1f[i1]);
+    // read-modify-write of the pair's 36 entries (distinct, one per component
+    // plane), nine at a time with every read of a batch issued before its
+    // first write: a read after a write also waits for that write (one counter
+    // for both), so entry by entry would serialize 36 round trips
     double *Po = d.P + (int64_t)s * 36 * d.nnz2 + k;
 #pragma unroll
-    for (int ab = 0; ab < 4; ++ab)
+    for (int ab = 0; ab < 4; ++ab) {
+      double *Pab = Po + (int64_t)(ab * 9) * d.nnz2;
+      double old[9];
 #pragma unroll
-      for (int rt = 0; rt < 9; ++rt) Po[(int64_t)(ab * 9 + rt) * d.nnz2] += P[ab][rt];
+      for (int rt = 0; rt < 9; ++rt) old[rt] = Pab[(int64_t)rt * d.nnz2];
+#pragma unroll
+      for (int rt = 0; rt < 9; ++rt) Pab[(int64_t)rt * d.nnz2] = old[rt] + P[ab][rt];
+    }
   }
 }
 
