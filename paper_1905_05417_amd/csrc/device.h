@@ -533,6 +533,15 @@ __device__ __forceinline__ void kron_row(const double *qq, const double (&pr)[NS
     for (int x = 0; x < LZ; ++x) out[r * rstride + (int64_t)x * astride] = acc[x][r];
 }
 
+// A value that is the same for the whole block, read from a plan table (the
+// tables are written before any launch and only read while kernels run)
+// through the constant address space: a scalar load, counted apart from the
+// vector memory operations (whose counter includes the stores in flight), also
+// where the compiler cannot see that the table is unwritten (the batch reads
+// its per-laminate views from memory).
+__device__ __forceinline__ int uld(const int *p, int64_t i) {
+  return reinterpret_cast<const __attribute__((address_space(4))) int *>(reinterpret_cast<uintptr_t>(p))[i];
+}
 
 // Register-mode scatter of one (tile of whole in-plane rows, group of
 // consecutive thickness chunks) item with one or two set slots per chunk (every
@@ -542,7 +551,9 @@ __device__ __forceinline__ void kron_row(const double *qq, const double (&pr)[NS
 // set-independent moments M_ab[kl] and the slot's brackets E_s[kl][rt] (eq. P;
 // P is never stored; material-field plans load their stored P instead) and
 // writes the chunk's rows.  A row's slot-dense coefficients Qd[zk][slot][ab]
-// are the same for the whole block.  QSCALAR (qd a restrict kernel argument,
+// are the same for the whole block (a row's are read slot by slot, all columns
+// of a slot together, and a row's end index a row ahead, so that a row waits
+// on one scalar load round trip).  QSCALAR (qd a restrict kernel argument,
 // so the compiler can prove no store reaches it): they are read from global
 // memory through scalar loads into scalar registers, which keeps them out of
 // the vector registers and, as scalar loads are counted apart from vector
@@ -558,16 +569,6 @@ __device__ __forceinline__ void kron_row(const double *qq, const double (&pr)[NS
 // kron_lds_q bytes for the coefficients (used when staged), then 81 doubles
 // per set of the group and 81 zeros.  The single-laminate scatter and the
 // batched one both run it.
-// A value that is the same for the whole block, read from a plan table (the
-// tables are written before any launch and only read while kernels run)
-// through the constant address space: a scalar load, counted apart from the
-// vector memory operations (whose counter includes the stores in flight), also
-// where the compiler cannot see that the table is unwritten (the batch reads
-// its per-laminate views from memory).
-__device__ __forceinline__ int uld(const int *p, int64_t i) {
-  return reinterpret_cast<const __attribute__((address_space(4))) int *>(reinterpret_cast<uintptr_t>(p))[i];
-}
-
 template <int NSC, bool QSCALAR, bool FIELD>
 __device__ __forceinline__ void kron_group(const Dev &d, const double *__restrict__ qd, double *__restrict__ vals,
                                            int tile, int g, double *lq, int sig, int nthreads) {
