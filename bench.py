@@ -85,9 +85,11 @@ def _parse():
                     help="the sweep at degree 3 only, meshes 1x1 and 64x64, 1, 16 and 128 plies")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
-    ap.add_argument("--kernel-only", choices=("fast", "standard", "apply", "cg"), default=None,
-                    help="only run --steps assemblies, matrix-free products or CG iterations (plate clamped along "
-                         "one edge) after --warmup of them, on one workload, for profiler runs")
+    ap.add_argument("--kernel-only", choices=("fast", "standard", "apply", "cg", "adjoint", "adjoint_rank1"),
+                    default=None,
+                    help="only run --steps assemblies, matrix-free products, CG iterations (plate clamped along "
+                         "one edge) or adjoints (G = u u^T on the pattern, formed beforehand or, rank1, from u) "
+                         "after --warmup of them, on one workload, for profiler runs")
     ap.add_argument("--workload", choices=tuple(KERNEL_ONLY_WORKLOADS), default="p3_128x128_128ply",
                     help="the workload of --kernel-only")
     return ap.parse_args()
@@ -132,6 +134,16 @@ def _kernel_only(args, torch, np, L, W):
         u = torch.tensor(np.random.default_rng(11).standard_normal(plan.n_rows), device="cuda")
         y = torch.empty_like(u)
         step = lambda: plan.apply(C, th, u, out=y)
+    elif args.kernel_only in ("adjoint", "adjoint_rank1"):
+        u = torch.tensor(np.random.default_rng(W.SEED_U).standard_normal(plan.n_rows), device="cuda")
+        if args.kernel_only == "adjoint":
+            rowptr, colind = plan.pattern()
+            rows = torch.repeat_interleave(torch.arange(plan.n_rows, device="cuda"), rowptr[1:] - rowptr[:-1])
+            G = u[rows] * u[colind.long()]
+            del rows, colind, rowptr
+            step = lambda: plan.adjoint(C, th, G)
+        else:
+            step = lambda: plan.adjoint_rank1(C, th, u)
     else:  # one call of CG, --steps iterations (tolerance 0: no early stop)
         fixed, b = _clamped_edge(torch, lam, plan)
         plan.cg(C, th, b, fixed=fixed, tol=0.0, max_iter=args.warmup)

@@ -44,7 +44,7 @@ struct Dev {
   const double *Escat;  // bracket coefficients of the scatter's sets: Ec, or Eply for harmonic plans
   int harm_ply;
   const int *rowply, *rowfin;
-  double *Qp, *adj_part, *adj_y, *adj_dD;
+  double *Qp, *adj_part, *adj_y, *adj_cm;  // adj_cm: per ply, T^T dL/dD T (36)
   int *status;  // lam::N_STATUS flags, set by kernels, cleared by lam_check
   // curved shells: per-point map gradients and in-plane basis (constant);
   // material fields: set brackets per in-plane function and per point (scratch)
@@ -115,7 +115,7 @@ inline Dev make_dev(const lam_plan *p, void *ws, void *sbase = nullptr) {
   d.Qp = own ? at<double>(sb, L.Qp) : nullptr;
   d.adj_part = own ? at<double>(sb, L.adj_part) : nullptr;
   d.adj_y = own ? at<double>(sb, L.adj_y) : nullptr;
-  d.adj_dD = own ? at<double>(sb, L.adj_dD) : nullptr;
+  d.adj_cm = own ? at<double>(sb, L.adj_cm) : nullptr;
   d.kron_nsc = p->kron_nsc;
   d.kron_lds_p = p->kron_lds_p;
   d.status = at<int>(ws, L.status);

@@ -65,7 +65,7 @@ struct Layout {
   // scratch: the fast assembly uses [const_bytes, fwd_end) (P only in LDS
   // mode, Eply only for harmonic plans evaluated per ply); the standard
   // assembly and the adjoint use the regions after it
-  Region D, Ec, P, Qc, M, Eply, Qp, adj_part, adj_y, adj_dD;
+  Region D, Ec, P, Qc, M, Eply, Qp, adj_part, adj_y, adj_cm;
   // material fields (fast scratch): bracket coefficients per set and in-plane
   // function, Ectl[s][is][81], and at every in-plane Gauss point, Epts[s][e][g][81]
   Region Ectl, Epts;

@@ -1106,65 +1106,78 @@ __device__ inline int voigt_pair(int i, int j) {
   return a == 0 ? (b == 1 ? 3 : 4) : 5;
 }
 
-// dT/dtheta of the Voigt stress transformation (product rule on the two R factors).
-__device__ void voigt_rotation_dtheta(double c, double s, double T[6][6]) {
-  const double R[3][3] = {{c, -s, 0.0}, {s, c, 0.0}, {0.0, 0.0, 1.0}};
-  const double dR[3][3] = {{-s, -c, 0.0}, {c, -s, 0.0}, {0.0, 0.0, 0.0}};
-  for (int I = 0; I < 6; ++I)
-    for (int J = 0; J < 6; ++J) {
-      int i = kVi[I], j = kVj[I], k = kVi[J], l = kVj[J];
-      double t = dR[i][k] * R[j][l] + R[i][k] * dR[j][l];
-      if (k != l) t += dR[i][l] * R[j][k] + R[i][l] * dR[j][k];
-      T[I][J] = t;
-    }
+// Entries of the in-plane rotation R(theta) and of dR/dtheta as functions of
+// their indices (no array indexed per thread); the Voigt stress transformation
+// and its theta derivative follow by the product rule on its two R factors.
+__device__ inline double rot_entry(int i, int k, double c, double s) {
+  return i == 2 || k == 2 ? (i == k ? 1.0 : 0.0) : (i == k ? c : (i == 0 ? -s : s));
+}
+__device__ inline double drot_entry(int i, int k, double c, double s) {
+  return i == 2 || k == 2 ? 0.0 : (i == k ? -s : (i == 0 ? -c : c));
 }
 
-// Per ply: dL/dD_l from Y_l, and dL/dtheta_l = <dL/dD_l, dT C T^T + T C dT^T>.
-__global__ void k_adj_ply(Dev d, const double *__restrict__ C, const double *__restrict__ theta,
-                          double *__restrict__ grad_theta) {
-  int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= d.n_ply) return;
-  const double *Y = d.adj_y + 81 * l;
-  double dD[6][6];
-  for (int I = 0; I < 6; ++I)
-    for (int J = 0; J < 6; ++J) dD[I][J] = 0.0;
-  for (int k = 0; k < 3; ++k)
-    for (int m = 0; m < 3; ++m)
-      for (int r = 0; r < 3; ++r)
-        for (int t = 0; t < 3; ++t) dD[voigt_pair(k, r)][voigt_pair(m, t)] += Y[(k * 3 + m) * 9 + r * 3 + t];
-  for (int I = 0; I < 6; ++I)
-    for (int J = 0; J < 6; ++J) d.adj_dD[36 * l + 6 * I + J] = dD[I][J];
-  const double c = cos(theta[l]), s = sin(theta[l]);
-  double T[6][6], dT[6][6];
-  voigt_rotation(c, s, T);
-  voigt_rotation_dtheta(c, s, dT);
-  const double *Cm = C + 36 * d.ply_mat[l];
-  // g = sum_IJ dD[I][J] (dT C T^T + T C dT^T)[I][J]
-  double g = 0.0;
-  for (int I = 0; I < 6; ++I)
-    for (int J = 0; J < 6; ++J) {
-      double a = 0.0;
-      for (int K = 0; K < 6; ++K)
-        for (int L = 0; L < 6; ++L) a += (dT[I][K] * T[J][L] + T[I][K] * dT[J][L]) * Cm[K * 6 + L];
-      g += dD[I][J] * a;
+// Per ply, one block (thread e < 36 owns the Voigt pair (I, J) = (e / 6, e % 6)):
+// dL/dD_l[I][J] sums the entries of Y_l whose index pairs map to (I, J);
+// dL/dtheta_l = <dL/dD_l, dT C T^T + T C dT^T> (a fixed-order sum over the 36
+// products); and the ply's share T_l^T dL/dD_l T_l of its material's gradient,
+// stored for k_adj_mat.
+__global__ void __launch_bounds__(64) k_adj_ply(Dev d, const double *__restrict__ C, const double *__restrict__ theta,
+                                                double *__restrict__ grad_theta) {
+  __shared__ double sT[36], sdT[36], sD[36], sW[36], sp[36];
+  const int l = blockIdx.x, e = threadIdx.x;
+  const int I = e / 6, J = e - 6 * (e / 6);
+  if (e < 36) {
+    const double c = cos(theta[l]), s = sin(theta[l]);
+    const int i = kVi[I], j = kVj[I], k = kVi[J], m = kVj[J];
+    double t = rot_entry(i, k, c, s) * rot_entry(j, m, c, s);
+    double dt = drot_entry(i, k, c, s) * rot_entry(j, m, c, s) + rot_entry(i, k, c, s) * drot_entry(j, m, c, s);
+    if (k != m) {
+      t += rot_entry(i, m, c, s) * rot_entry(j, k, c, s);
+      dt += drot_entry(i, m, c, s) * rot_entry(j, k, c, s) + rot_entry(i, m, c, s) * drot_entry(j, k, c, s);
     }
-  grad_theta[l] = g;
+    sT[e] = t;
+    sdT[e] = dt;
+    const double *Y = d.adj_y + 81 * l;
+    double a = 0.0;
+    for (int kk = 0; kk < 3; ++kk)
+      for (int mm = 0; mm < 3; ++mm)
+        for (int r = 0; r < 3; ++r)
+          for (int tt = 0; tt < 3; ++tt)
+            if (voigt_pair(kk, r) == I && voigt_pair(mm, tt) == J) a += Y[(kk * 3 + mm) * 9 + r * 3 + tt];
+    sD[e] = a;
+  }
+  __syncthreads();
+  if (e < 36) {
+    const double *Cm = C + 36 * d.ply_mat[l];
+    double a = 0.0;
+    for (int K = 0; K < 6; ++K)
+      for (int L = 0; L < 6; ++L) a += (sdT[6 * I + K] * sT[6 * J + L] + sT[6 * I + K] * sdT[6 * J + L]) * Cm[K * 6 + L];
+    sp[e] = sD[e] * a;
+    double w = 0.0;  // (dL/dD T)[I][J]
+    for (int K = 0; K < 6; ++K) w += sD[6 * I + K] * sT[6 * K + J];
+    sW[e] = w;
+  }
+  __syncthreads();
+  if (e == 0) {
+    double g = 0.0;
+    for (int q = 0; q < 36; ++q) g += sp[q];
+    grad_theta[l] = g;
+  }
+  if (e < 36) {  // (T^T dL/dD T)[A][B] with (A, B) = (I, J)
+    double cm = 0.0;
+    for (int K = 0; K < 6; ++K) cm += sT[6 * K + I] * sW[6 * K + J];
+    d.adj_cm[36 * (int64_t)l + e] = cm;
+  }
 }
 
-// dL/dC_m[A][B] = sum over the plies of material m (in order) of (T_l^T dL/dD_l T_l)[A][B].
-__global__ void k_adj_mat(Dev d, const double *__restrict__ theta, double *__restrict__ grad_C) {
+// dL/dC_m[A][B] = sum over the plies of material m (in order) of their shares.
+__global__ void k_adj_mat(Dev d, double *__restrict__ grad_C) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= 36 * d.n_mat) return;
-  const int mt = idx / 36, A = (idx % 36) / 6, B = idx % 6;
+  const int mt = idx / 36, e = idx - 36 * mt;
   double acc = 0.0;
-  for (int l = 0; l < d.n_ply; ++l) {
-    if (d.ply_mat[l] != mt) continue;
-    double T[6][6];
-    voigt_rotation(cos(theta[l]), sin(theta[l]), T);
-    const double *dD = d.adj_dD + 36 * l;
-    for (int I = 0; I < 6; ++I)
-      for (int J = 0; J < 6; ++J) acc += T[I][A] * dD[6 * I + J] * T[J][B];
-  }
+  for (int l = 0; l < d.n_ply; ++l)
+    if (d.ply_mat[l] == mt) acc += d.adj_cm[36 * (int64_t)l + e];
   grad_C[idx] = acc;
 }
 
@@ -1847,8 +1860,8 @@ void launch_adjoint(const lam_plan *p, const Dev &d, const double *C, const doub
   }
   lam::profile_end(prof, stream);
   hipLaunchKernelGGL(k_adj_reduce, dim3(81 * p->n_ply), dim3(256), 0, s, d);
-  hipLaunchKernelGGL(k_adj_ply, dim3((p->n_ply + 63) / 64), dim3(64), 0, s, d, C, theta, grad_theta);
-  hipLaunchKernelGGL(k_adj_mat, dim3((36 * p->n_mat + 63) / 64), dim3(64), 0, s, d, theta, grad_C);
+  hipLaunchKernelGGL(k_adj_ply, dim3(p->n_ply), dim3(64), 0, s, d, C, theta, grad_theta);
+  hipLaunchKernelGGL(k_adj_mat, dim3((36 * p->n_mat + 63) / 64), dim3(64), 0, s, d, grad_C);
 }
 
 }  // namespace

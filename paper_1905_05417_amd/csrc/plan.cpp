@@ -856,7 +856,7 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
   L.Qp = B.take(sizeof(double) * 8 * std::max<int64_t>(P->nnzz, (int64_t)P->nt * (2 * P->q + 1)));
   L.adj_part = B.take(sizeof(double) * 81 * (int64_t)P->n_tiles * P->n_ply);
   L.adj_y = B.take(sizeof(double) * 81 * P->n_ply);
-  L.adj_dD = B.take(sizeof(double) * 36 * P->n_ply);
+  L.adj_cm = B.take(sizeof(double) * 36 * P->n_ply);
   L.total = B.cur;
 
   P->image.assign(L.const_bytes, 0);
