@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batch_kron_grid(BatchArgs a) 
   if (j >= count) return;
   const int4 wv = a.items[first + j];
   const Dev &d = a.devs[wv.x];
-  kron_group<2, false, false>(d, d.Qc, a.vals + a.meta[wv.x].vals_off, wv.y, wv.z, lds, threadIdx.x, (int)blockDim.x);
+  kron_group<2, false>(d, d.Qc, a.vals + a.meta[wv.x].vals_off, wv.y, wv.z, lds, threadIdx.x, (int)blockDim.x);
 }
 
 // OR of every laminate's status words into *out (bit 0: a bucket set's plies

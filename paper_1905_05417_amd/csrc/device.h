@@ -507,9 +507,9 @@ constexpr int KRON_AB = 5;         // thickness columns per register block
 // compile time (no per-column predicates): value (x, r) = sum over the
 // chunk's set slots u of Qd[zk + x][u][ab] * P_u[ab][r] (eq. Km_2), the first
 // slot's product starting the sum; stores r-major, x-minor.
-template <int NSC, int LZ>
-__device__ __forceinline__ void kron_row(const double *qq, const double (&pr)[NSC][4][3], double *out,
-                                         int64_t rstride, int64_t astride) {
+template <int NSC, int LZ, class QP>
+__device__ __forceinline__ void kron_row(QP qq, const double (&pr)[NSC][4][3], double *out, int64_t rstride,
+                                         int64_t astride) {
   double acc[LZ][3];
   // slot-outer: one slot's coefficients of every column are read together
 #pragma unroll
@@ -551,25 +551,23 @@ __device__ __forceinline__ int uld(const int *p, int64_t i) {
 // set-independent moments M_ab[kl] and the slot's brackets E_s[kl][rt] (eq. P;
 // P is never stored; material-field plans load their stored P instead) and
 // writes the chunk's rows.  A row's slot-dense coefficients Qd[zk][slot][ab]
-// are the same for the whole block (a row's are read slot by slot, all columns
-// of a slot together, and a row's end index a row ahead, so that a row waits
-// on one scalar load round trip).  QSCALAR (qd a restrict kernel argument,
-// so the compiler can prove no store reaches it): they are read from global
-// memory through scalar loads into scalar registers, which keeps them out of
-// the vector registers and, as scalar loads are counted apart from vector
-// memory operations, waits on no store in flight.  Otherwise (the batch, whose
-// qd comes from a table) the block stages the group's coefficients in LDS.
-// After the barrier the block issues no vector load (constant materials): a
+// are the same for the whole block: they are read from global memory through
+// the constant address space, i.e. by scalar loads into scalar registers (also
+// for the batch, whose qd comes from a per-laminate table), which keeps them
+// out of the vector registers and, as scalar loads are counted apart from
+// vector memory operations, waits on no store in flight; a row's are read slot
+// by slot, all columns of a slot together, and its end index a row ahead, so
+// that a row waits on one scalar load round trip.  After the barrier the block issues no vector load (constant materials): a
 // vector load on any path into the row loop would make every row wait for all
 // of the wave's stores in flight (loads and stores share one counter on this
 // chip).  FIELD (material fields), a separate instantiation: each slot's P is
 // read from the stored P of its set, at every set change.
 // Block-cooperative: every thread of the block calls it with the same item
 // (it holds a barrier; threads past 3 * tile_k return after it).  lq: LDS of
-// kron_lds_q bytes for the coefficients (used when staged), then 81 doubles
-// per set of the group and 81 zeros.  The single-laminate scatter and the
+// kron_lds_q bytes (not used here; the matrix-free product stages its
+// coefficients there), then 81 doubles per set of the group and 81 zeros.  The single-laminate scatter and the
 // batched one both run it.
-template <int NSC, bool QSCALAR, bool FIELD>
+template <int NSC, bool FIELD>
 __device__ __forceinline__ void kron_group(const Dev &d, const double *__restrict__ qd, double *__restrict__ vals,
                                            int tile, int g, double *lq, int sig, int nthreads) {
   static_assert(NSC <= 2, "grouped scatter items keep at most two set slots");
@@ -589,14 +587,9 @@ __device__ __forceinline__ void kron_group(const Dev &d, const double *__restric
   double *le = lq + d.kron_lds_q / 8;
   const int ch0 = uld(d.group_ptr, g), ch1 = uld(d.group_ptr, g + 1);
   const int s0 = uld(d.group_sptr, g), ns = uld(d.group_sptr, g + 1) - s0;
-  const int zq0 = uld(d.zrow, uld(d.chunk_ptr, ch0));  // the group's first thickness nonzero
   for (int e = sig; e < 81 * (ns + 1); e += nthreads) {
     const int u = e / 81;
     le[e] = u < ns ? d.Escat[81 * (int64_t)uld(d.group_set, s0 + u) + (e - 81 * u)] : 0.0;
-  }
-  if constexpr (!QSCALAR) {
-    const int nq = 4 * NSC * (uld(d.zrow, uld(d.chunk_ptr, ch1)) - zq0);
-    for (int e = sig; e < nq; e += nthreads) lq[e] = qd[4 * (int64_t)NSC * zq0 + e];
   }
   __syncthreads();
   if (!act) return;  // no barrier follows
@@ -639,10 +632,11 @@ __device__ __forceinline__ void kron_group(const Dev &d, const double *__restric
       const int Lz = zn - zb;
       double *out = vals + 9 * d.nnz2 * (int64_t)zb + 9 * (int64_t)Lz * sr + off;
       const int64_t rstride = 3 * (int64_t)Lz * Ls;
-      // the row's coefficients are uniform over the block: read from global
-      // memory they go through scalar loads into scalar registers (and
-      // scalar loads do not wait on the vector stores in flight)
-      const double *qz = QSCALAR ? qd + 4 * NSC * (int64_t)zb : lq + 4 * NSC * (zb - zq0);
+      // the row's coefficients, uniform over the block: scalar loads through
+      // the constant address space (they do not wait on the stores in flight)
+      const auto qz =
+          reinterpret_cast<const __attribute__((address_space(4))) double *>(reinterpret_cast<uintptr_t>(qd)) +
+          4 * NSC * (int64_t)zb;
       switch (Lz) {  // widths 2..5 (q + 1 up to q = 4, 2q + 1 up to q = 2) fixed; 7 and 9 take the loop
         case 2: kron_row<NSC, 2>(qz, pr, out, rstride, astride); break;
         case 3: kron_row<NSC, 3>(qz, pr, out, rstride, astride); break;
@@ -655,8 +649,7 @@ __device__ __forceinline__ void kron_group(const Dev &d, const double *__restric
             for (int x = 0; x < KRON_AB; ++x) {
               acc[x][0] = acc[x][1] = acc[x][2] = 0.0;
               if (ab0 + x < Lz) {
-                const double *qq = QSCALAR ? qd + 4 * NSC * (int64_t)(zb + ab0 + x)
-                                           : lq + 4 * NSC * (zb + ab0 + x - zq0);
+                const auto qq = qz + 4 * NSC * (ab0 + x);
 #pragma unroll
                 for (int u = 0; u < NSC; ++u) {
                   const double q0 = qq[4 * u], q1 = qq[4 * u + 1], q2 = qq[4 * u + 2], q3 = qq[4 * u + 3];

@@ -343,7 +343,7 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron_reg(Dev d, const double *
   int tile, g;
   if (!kron_block(d, tile, g)) return;
   if constexpr (NSC <= 2) {
-    lamdev::kron_group<NSC, true, FIELD>(d, qd, vals, tile, g, lq, (int)threadIdx.x, (int)blockDim.x);
+    lamdev::kron_group<NSC, FIELD>(d, qd, vals, tile, g, lq, (int)threadIdx.x, (int)blockDim.x);
   } else {
     const int k0 = d.tiles[tile], tk = d.tiles[tile + 1] - k0;
     const int sig = threadIdx.x;
