@@ -434,7 +434,7 @@ __global__ void __launch_bounds__(KRON_THREADS) k_apply(Dev d, const double *__r
                                                         const uint8_t *__restrict__ fixed, double *__restrict__ y) {
   static_assert(NSC <= 2, "the matrix-free product keeps at most two set slots");
   // LDS: group coefficients (kron_lds_q bytes), set brackets (kron_lds_p
-  // bytes), then the shares c[APPLY_ROWS][3][blockDim]
+  // bytes), then the shares c[APPLY_ROWS][3][3 tile_k] (one slot per active thread)
   extern __shared__ double lq[];
   int tile, g;
   if (!kron_block(d, tile, g)) return;
@@ -454,7 +454,8 @@ __global__ void __launch_bounds__(KRON_THREADS) k_apply(Dev d, const double *__r
   const int zk0 = d.zrow[itg0], nq = 4 * NSC * (d.zrow[itg1] - zk0);
   const int s0 = d.group_sptr[g], ns = d.group_sptr[g + 1] - s0;
   double *le = lq + d.kron_lds_q / 8;
-  double *lc = le + d.kron_lds_p / 8;  // [APPLY_ROWS][3][nth]
+  const int ns3 = 3 * d.tile_k;          // share slots per row: the plan's widest tile
+  double *lc = le + d.kron_lds_p / 8;  // [APPLY_ROWS][3][ns3]
   for (int e = sig; e < 81 * (ns + 1); e += nth) {
     const int w = e / 81;
     le[e] = w < ns ? d.Escat[81 * (int64_t)d.group_set[s0 + w] + (e - 81 * w)] : 0.0;
@@ -505,14 +506,14 @@ __global__ void __launch_bounds__(KRON_THREADS) k_apply(Dev d, const double *__r
         for (int w = 0; w < NSC; ++w)
 #pragma unroll
           for (int ab = 0; ab < 4; ++ab) c += pr[w][ab][r] * v[w][ab];
-        lc[(3 * j + r) * nth + sig] = c;
+        if (sig < ns3) lc[(3 * j + r) * ns3 + sig] = c;
       }
     }
     __syncthreads();
     for (int o = sig; o < 3 * nrow * nb; o += nth) {
       const int j = o / (3 * nrow), rem = o - 3 * nrow * j, i = rem / 3, r = rem - 3 * i, is = is0 + i;
       const int m0 = d.srow[is] - k0, m1 = d.srow[is + 1] - k0;
-      const double *src = lc + (3 * j + r) * nth;
+      const double *src = lc + (3 * j + r) * ns3;
       double a0 = 0.0, a1 = 0.0, a2 = 0.0;
       for (int m = m0; m < m1; ++m) {
         a0 += src[3 * m];
@@ -1414,7 +1415,7 @@ void launch_prep(const lam_plan *p, const Dev &d, const double *C, const double 
 
 void launch_apply(const lam_plan *p, const Dev &d, const double *u, const uint8_t *fixed, double *y, void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t lds = (size_t)(p->kron_lds + APPLY_ROWS * 3 * sizeof(double) * p->kron_threads);
+  const size_t lds = (size_t)(p->kron_lds + APPLY_ROWS * 3 * sizeof(double) * 3 * p->tile_k);
   void *prof = lam::profile_begin(4, stream);
   if (p->kron_nsc == 1)
     hipLaunchKernelGGL((k_apply<1>), dim3(kron_grid(p)), dim3(p->kron_threads), lds, s, d, d.Qc, u, fixed, y);
