@@ -648,7 +648,10 @@ lam_status plan_create(const lam_laminate_desc *d, const lam_tuning *tune, int m
   int64_t target_blocks = 6144;
   if (tune && tune->target_blocks > 0) target_blocks = tune->target_blocks;
   const int64_t per_tile = (target_blocks + P->n_tiles - 1) / P->n_tiles;
-  const int max_rows = (int)std::max<int64_t>(1, (P->nt + per_tile - 1) / per_tile);
+  int max_rows = (int)std::max<int64_t>(1, (P->nt + per_tile - 1) / per_tile);
+  // with enough tiles to fill the chip, a piece keeps at least 8 rows (or the
+  // whole thickness): each block pays its prologue once for its rows
+  if (P->n_tiles >= 1024) max_rows = std::max(max_rows, std::min(P->nt, 8));
   {
     std::vector<int> cp(1, 0), csp(1, 0), cs;
     for (size_t c = 0; c + 1 < chunk_ptr.size(); ++c) {
