@@ -144,8 +144,9 @@ LAM_API lam_status lam_plan_create_tuned(const lam_laminate_desc *desc, const la
  * in-plane function (n_mat * n1 * n2 matrices, material-major), and ply l uses
  * C_{mat(l)}(xi) = sum_i R^i(xi) C_{mat(l), i} rotated by theta_l.
  * Limits: material fields take BUCKET or PLY sets (LAM_EUNSUP otherwise), no
- * adjoint, matrix-free product or standard assembly (LAM_EUNSUP); curved
- * shells with constant materials support every entry point except the batch.
+ * adjoint or standard assembly (LAM_EUNSUP); their matrix-free product and CG
+ * read the P of each set integrated with the field inside; curved shells with
+ * constant materials support every entry point except the batch.
  * lam_plan_create_shell returns LAM_EMAT for a non-finite control point,
  * weight or extrusion vector, a weight <= 0 or a map gradient that is
  * singular at an in-plane Gauss point. */
@@ -242,8 +243,9 @@ LAM_API lam_status lam_adjoint(const lam_plan *plan, void *ws, int64_t ws_bytes,
  * fixed: NULL, or device bytes per row (nonzero = Dirichlet row) for the
  * eliminated operator y = P K P u + (I - P) u, P the projection on the free
  * rows.  Register-mode plans with one or two set slots (every bucket and
- * per-ply plan with the automatic slot count) and constant materials;
- * LAM_EUNSUP otherwise,
+ * per-ply plan with the automatic slot count); with an in-plane material
+ * field each call first integrates every set's P with the field inside (as
+ * lam_assemble does) and the product reads it.  LAM_EUNSUP otherwise,
  * LAM_ESIZE if n_rows is not the plan's row count.  The rounding order
  * differs from multiplying the assembled K. */
 LAM_API lam_status lam_apply(const lam_plan *plan, void *ws, int64_t ws_bytes, const double *C, const double *theta,

@@ -425,10 +425,12 @@ __global__ void __launch_bounds__(KRON_THREADS) k_kron_reg(Dev d, const double *
 // entry of y belongs to exactly one block, so no atomics.
 // fixed (nullable, one byte per row): Dirichlet elimination, y = P K P u +
 // (I - P) u with P the projection on the free rows (fixed entries of u read
-// as 0, fixed rows of y copy u).
+// as 0, fixed rows of y copy u).  FIELD (in-plane material fields): each
+// slot's P is read from the stored P of its set instead of formed from the
+// moments, as in the scatter.
 constexpr int APPLY_ROWS = 8;
 
-template <int NSC>
+template <int NSC, bool FIELD>
 __global__ void __launch_bounds__(KRON_THREADS) k_apply(Dev d, const double *__restrict__ qd,
                                                         const double *__restrict__ u,
                                                         const uint8_t *__restrict__ fixed, double *__restrict__ y) {
@@ -442,11 +444,13 @@ __global__ void __launch_bounds__(KRON_THREADS) k_apply(Dev d, const double *__r
   const int sig = threadIdx.x, nth = blockDim.x;
   const bool act = sig < 3 * tk;
   const int kk = act ? sig / 3 : 0, t = act ? sig - 3 * kk : 0, k = k0 + kk;
-  double mv[4][9];
+  double mv[4][9];  // the moments (material fields read their stored P instead)
+  if constexpr (!FIELD) {
 #pragma unroll
-  for (int ab = 0; ab < 4; ++ab)
+    for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
-    for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[m_index(k, ab * 9 + kl)];
+      for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[m_index(k, ab * 9 + kl)];
+  }
   const int js = d.kcol[k];
   const int is0 = d.krow[k0], nrow = d.krow[k0 + tk - 1] - is0 + 1;  // the tile's in-plane rows
   const int ch0 = d.group_ptr[g], ch1 = d.group_ptr[g + 1];
@@ -474,7 +478,17 @@ __global__ void __launch_bounds__(KRON_THREADS) k_apply(Dev d, const double *__r
         const int c0 = d.chunk_sptr[ch], nsc = d.chunk_sptr[ch + 1] - c0;
 #pragma unroll
         for (int w = 0; w < NSC; ++w) {
-          const double *ew = le + 81 * (w < nsc ? d.chunk_lset[c0 + w] : ns);  // unused slots: zeros
+          const int ls = w < nsc ? d.chunk_lset[c0 + w] : ns;  // unused slots: the zero block
+          if constexpr (FIELD) {
+            const int gs = ls < ns ? d.group_set[s0 + ls] : -1;
+#pragma unroll
+            for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+              for (int r = 0; r < 3; ++r)
+                pr[w][ab][r] = act && gs >= 0 ? d.P[((int64_t)gs * 36 + ab * 9 + 3 * r + t) * d.nnz2 + k] : 0.0;
+            continue;
+          }
+          const double *ew = le + 81 * ls;
 #pragma unroll
           for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
@@ -1303,30 +1317,35 @@ extern "C" LAM_API lam_status lam_pattern(const lam_plan *p, const void *ws, int
 namespace {
 
 // The launches of the fast assembly (Sec. 3) on the device view d.
+// Material fields: the rotated field at the in-plane Gauss points, P of every
+// set integrated element by element with the field inside (one launch per
+// element colour: elements of a colour share no in-plane function), and the
+// 1D coefficients.  The scatter and the matrix-free product read P.
+void launch_prep_field(const lam_plan *p, const Dev &d, const double *C, const double *theta, hipStream_t s) {
+  const int64_t nq = p->nnzz * (p->kron_nsc > 0 ? p->kron_nsc : p->maxact);
+  const int64_t npts = (int64_t)p->ne1 * p->ne2 * p->ng1 * p->ng2;
+  hipLaunchKernelGGL(k_rotate_field, dim3((unsigned)(((int64_t)p->n_sets * p->ns + 255) / 256)), dim3(256), 0, s, d,
+                     C, theta);
+  hipLaunchKernelGGL(k_field_points, dim3((unsigned)((81 * npts * p->n_sets + 255) / 256)), dim3(256), 0, s, d);
+  const int P1 = p->p1 + 1, P2 = p->p2 + 1, nb = P1 * P2, ngp = p->ng1 * p->ng2;
+  const size_t lds = sizeof(double) * (size_t)ngp * (10 + 3 * nb + 81);
+  const int thr = std::min(256, (nb * nb + 63) / 64 * 64);
+  hipLaunchKernelGGL(k_fill_zero, dim3(2048), dim3(256), 0, s, d.P, (int64_t)p->n_sets * 36 * p->nnz2);
+  for (int c2 = 0; c2 < P2; ++c2)
+    for (int c1 = 0; c1 < P1; ++c1) {
+      const int n1c = (p->ne1 - c1 + P1 - 1) / P1, n2c = (p->ne2 - c2 + P2 - 1) / P2;
+      const int64_t nblk = (int64_t)n1c * n2c * p->n_sets;
+      if (nblk > 0) hipLaunchKernelGGL(k_p2d_field, dim3((unsigned)nblk), dim3(thr), lds, s, d, c1, c2, n1c, n2c);
+    }
+  hipLaunchKernelGGL(k_q1d, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, d, theta);
+}
+
 void launch_assemble(const lam_plan *p, const Dev &d, const double *C, const double *theta, double *vals,
                      void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   int64_t nq = p->nnzz * (p->kron_nsc > 0 ? p->kron_nsc : p->maxact);
   if (p->mat_field) {
-    // material fields: P of every set from the field at the Gauss points, LDS-mode scatter
-    const int64_t npts = (int64_t)p->ne1 * p->ne2 * p->ng1 * p->ng2;
-    hipLaunchKernelGGL(k_rotate_field, dim3((unsigned)(((int64_t)p->n_sets * p->ns + 255) / 256)), dim3(256), 0, s, d,
-                       C, theta);
-    hipLaunchKernelGGL(k_field_points, dim3((unsigned)((81 * npts * p->n_sets + 255) / 256)), dim3(256), 0, s, d);
-    {
-      const int P1 = p->p1 + 1, P2 = p->p2 + 1, nb = P1 * P2, ngp = p->ng1 * p->ng2;
-      const size_t lds = sizeof(double) * (size_t)ngp * (10 + 3 * nb + 81);
-      const int thr = std::min(256, (nb * nb + 63) / 64 * 64);
-      hipLaunchKernelGGL(k_fill_zero, dim3(2048), dim3(256), 0, s, d.P, (int64_t)p->n_sets * 36 * p->nnz2);
-      for (int c2 = 0; c2 < P2; ++c2)
-        for (int c1 = 0; c1 < P1; ++c1) {
-          const int n1c = (p->ne1 - c1 + P1 - 1) / P1, n2c = (p->ne2 - c2 + P2 - 1) / P2;
-          const int64_t nblk = (int64_t)n1c * n2c * p->n_sets;
-          if (nblk > 0)
-            hipLaunchKernelGGL(k_p2d_field, dim3((unsigned)nblk), dim3(thr), lds, s, d, c1, c2, n1c, n2c);
-        }
-    }
-    hipLaunchKernelGGL(k_q1d, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, d, theta);
+    launch_prep_field(p, d, C, theta, s);
     void *prof = lam::profile_begin(0, stream);
     launch_kron(p, d, vals, s);
     lam::profile_end(prof, stream);
@@ -1406,6 +1425,10 @@ namespace {
 // The set tensors and the moments and 1D coefficients the register-mode
 // scatter and the matrix-free product read.
 void launch_prep(const lam_plan *p, const Dev &d, const double *C, const double *theta, hipStream_t s) {
+  if (p->mat_field) {
+    launch_prep_field(p, d, C, theta, s);
+    return;
+  }
   const int64_t nq = p->nnzz * p->kron_nsc;
   const int nb_m = (int)((p->nnz2 + 255) / 256), nb_q = (int)((nq + 3) / 4);
   hipLaunchKernelGGL(k_rotate, dim3((std::max(p->n_sets, p->n_ply) + 63) / 64), dim3(64), 0, s, d, C, theta);
@@ -1417,10 +1440,15 @@ void launch_apply(const lam_plan *p, const Dev &d, const double *u, const uint8_
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t lds = (size_t)(p->kron_lds + APPLY_ROWS * 3 * sizeof(double) * 3 * p->tile_k);
   void *prof = lam::profile_begin(4, stream);
-  if (p->kron_nsc == 1)
-    hipLaunchKernelGGL((k_apply<1>), dim3(kron_grid(p)), dim3(p->kron_threads), lds, s, d, d.Qc, u, fixed, y);
+  const dim3 grid(kron_grid(p)), blk(p->kron_threads);
+  if (p->kron_nsc == 1 && p->mat_field)
+    hipLaunchKernelGGL((k_apply<1, true>), grid, blk, lds, s, d, d.Qc, u, fixed, y);
+  else if (p->kron_nsc == 1)
+    hipLaunchKernelGGL((k_apply<1, false>), grid, blk, lds, s, d, d.Qc, u, fixed, y);
+  else if (p->mat_field)
+    hipLaunchKernelGGL((k_apply<2, true>), grid, blk, lds, s, d, d.Qc, u, fixed, y);
   else
-    hipLaunchKernelGGL((k_apply<2>), dim3(kron_grid(p)), dim3(p->kron_threads), lds, s, d, d.Qc, u, fixed, y);
+    hipLaunchKernelGGL((k_apply<2, false>), grid, blk, lds, s, d, d.Qc, u, fixed, y);
   lam::profile_end(prof, stream);
 }
 
@@ -1433,7 +1461,7 @@ extern "C" LAM_API lam_status lam_apply(const lam_plan *p, void *ws, int64_t ws_
   if (st != LAM_OK) return st;
   if (!C || !theta || !u || !y) return LAM_EINVAL;
   if (n_rows != p->nrows) return LAM_ESIZE;
-  if (p->kron_nsc < 1 || p->kron_nsc > 2 || p->mat_field) return LAM_EUNSUP;
+  if (p->kron_nsc < 1 || p->kron_nsc > 2) return LAM_EUNSUP;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Dev d = make_dev(p, ws);
   launch_prep(p, d, C, theta, s);
@@ -1464,11 +1492,11 @@ constexpr int CG_CHECK = 8;
 // (jt, t), from the split (eq. Km_2) at the in-plane diagonal nonzero k_d of
 // is: sum over row it's set slots u and ab of Qc[(it, jt)][u][ab] P_u[k_d][ab][r][t],
 // P_u = sum_kl M_ab[kl][k_d] E_u[kl] (the register-mode scatter's moments and
-// brackets).  Fixed components take a unit row and column.  The lower band
+// brackets; with FIELD, material fields, the stored P of the slot's set).  Fixed components take a unit row and column.  The lower band
 // (row i = 3 it + r, column i - c for c = 0..3q+2) is stored at
 // fac[(i (3q + 3) + c) ns + is] (consecutive lines on consecutive addresses)
 // and overwritten by its Cholesky factor.  One thread per line.
-template <int NSC>
+template <int NSC, bool FIELD>
 __global__ void __launch_bounds__(256) k_cg_lines(Dev d, const double *__restrict__ qd,
                                                   const uint8_t *__restrict__ fixed, double *__restrict__ fac) {
   const int is = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1478,17 +1506,28 @@ __global__ void __launch_bounds__(256) k_cg_lines(Dev d, const double *__restric
   const int i1 = is % d.n1, i2 = is / d.n1;
   const int64_t k = d.srow[is] + (int64_t)(i2 - d.a2f[i2]) * d.a1c[i1] + (i1 - d.a1f[i1]);
   double mv[4][9];
+  if constexpr (!FIELD) {
 #pragma unroll
-  for (int ab = 0; ab < 4; ++ab)
+    for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
-    for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[m_index(k, ab * 9 + kl)];
+      for (int kl = 0; kl < 9; ++kl) mv[ab][kl] = d.M[m_index(k, ab * 9 + kl)];
+  }
   for (int64_t e = 0; e < (int64_t)n * wb; ++e) fac[e * ns + is] = 0.0;
   for (int it = 0; it < d.nt; ++it) {
     const int ch = d.zchunk[it], c0 = d.chunk_sptr[ch], nsc = d.chunk_sptr[ch + 1] - c0;
     double pu[NSC][4][9];  // P of the row's slots at the diagonal in-plane nonzero
 #pragma unroll
     for (int u = 0; u < NSC; ++u) {
-      const double *E = d.Escat + 81 * (int64_t)(u < nsc ? d.chunk_set[c0 + u] : d.chunk_set[c0]);
+      const int gs = u < nsc ? d.chunk_set[c0 + u] : d.chunk_set[c0];
+      if constexpr (FIELD) {
+#pragma unroll
+        for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+          for (int rt = 0; rt < 9; ++rt)
+            pu[u][ab][rt] = u < nsc ? d.P[((int64_t)gs * 36 + ab * 9 + rt) * d.nnz2 + k] : 0.0;
+        continue;
+      }
+      const double *E = d.Escat + 81 * (int64_t)gs;
 #pragma unroll
       for (int ab = 0; ab < 4; ++ab)
 #pragma unroll
@@ -1750,7 +1789,7 @@ extern "C" LAM_API lam_status lam_cg(const lam_plan *p, void *ws, int64_t ws_byt
   if (st != LAM_OK) return st;
   if (!C || !theta || !b || !x || !work || !iters || !rel_res || max_iter < 0 || !(tol >= 0.0)) return LAM_EINVAL;
   if (n_rows != p->nrows || work_bytes < lam_cg_work_bytes(p)) return LAM_ESIZE;
-  if (p->kron_nsc < 1 || p->kron_nsc > 2 || p->mat_field) return LAM_EUNSUP;
+  if (p->kron_nsc < 1 || p->kron_nsc > 2) return LAM_EUNSUP;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Dev d = make_dev(p, ws);
   const int64_t n = n_rows;
@@ -1758,10 +1797,14 @@ extern "C" LAM_API lam_status lam_cg(const lam_plan *p, void *ws, int64_t ws_byt
   double *part = fac + cg_factor_doubles(p), *scal = part + 2 * CG_PARTS;
   const dim3 vg((unsigned)((n + 255) / 256)), lg((unsigned)((p->ns + 255) / 256)), vb(256);
   launch_prep(p, d, C, theta, s);
-  if (p->kron_nsc == 1)
-    hipLaunchKernelGGL((k_cg_lines<1>), lg, vb, 0, s, d, d.Qc, fixed, fac);
+  if (p->kron_nsc == 1 && p->mat_field)
+    hipLaunchKernelGGL((k_cg_lines<1, true>), lg, vb, 0, s, d, d.Qc, fixed, fac);
+  else if (p->kron_nsc == 1)
+    hipLaunchKernelGGL((k_cg_lines<1, false>), lg, vb, 0, s, d, d.Qc, fixed, fac);
+  else if (p->mat_field)
+    hipLaunchKernelGGL((k_cg_lines<2, true>), lg, vb, 0, s, d, d.Qc, fixed, fac);
   else
-    hipLaunchKernelGGL((k_cg_lines<2>), lg, vb, 0, s, d, d.Qc, fixed, fac);
+    hipLaunchKernelGGL((k_cg_lines<2, false>), lg, vb, 0, s, d, d.Qc, fixed, fac);
   launch_apply(p, d, x, fixed, q, stream);
   hipLaunchKernelGGL(k_cg_init, vg, vb, 0, s, n, b, q, fixed, r);
   launch_line_solve(p, d, fac, r, z, pv, s);

@@ -409,10 +409,14 @@ def linear_material_field(lam: Laminate, C1: np.ndarray) -> Laminate:
     return out
 
 
-def smooth_material_field(lam: Laminate, rng: np.random.Generator, amp=0.3) -> Laminate:
+def smooth_material_field(lam: Laminate, rng: np.random.Generator, amp=0.3, sym=0.02) -> Laminate:
     """Seeded in-plane variation of every material: each in-plane function's
     6x6 is the material's scaled by 1 + amp * (a smooth random function of
-    its Greville point), plus a small seeded symmetric perturbation."""
+    its Greville point), plus a seeded symmetric perturbation of entries up to
+    a few times sym * max |C| (which can make a 6x6 indefinite: shear moduli
+    are far below that).  sym = 0 keeps every control tensor a positive
+    multiple of the material, so the field (a nonnegative partition of unity
+    of them) and K stay positive definite."""
     import copy
     out = copy.copy(lam)
     g1, g2 = greville(lam.p1, lam.k1), greville(lam.p2, lam.k2)
@@ -423,7 +427,7 @@ def smooth_material_field(lam: Laminate, rng: np.random.Generator, amp=0.3) -> L
         a, b, c = rng.uniform(0, 2 * np.pi, size=3)
         f = 1.0 + amp * np.sin(2 * X + a) * np.cos(3 * Y + b) + 0.5 * amp * np.sin(X + Y + c)
         E = rng.standard_normal((6, 6))
-        E = 0.02 * np.abs(C0[m]).max() * (E + E.T)
+        E = sym * np.abs(C0[m]).max() * (E + E.T)
         fields.append(f.ravel()[:, None, None] * C0[m][None] + np.sin(5 * X + c).ravel()[:, None, None] * E[None])
     out.C = np.stack(fields)
     out.mat_field = True

@@ -7,7 +7,7 @@ With constant ply materials the in-plane moments become 2D Gauss sums with
 the per-point map gradient and (rational) basis, and the scatter, the
 matrix-free product, the adjoint and the standard assembly run on them
 unchanged; with a material field every set's P is integrated with the field
-inside and read by the LDS-mode scatter.
+inside and read by the scatter, the matrix-free product and CG's line factors.
 
 Bar: patterns bit-exact; values within relative Frobenius and max-abs error
 1e-12 (max-abs relative to max |K|); products 1e-12; gradients 1e-10.
@@ -137,16 +137,78 @@ def test_material_field_other_paths(oracle, L, case):
 
 
 def test_material_field_limits(L):
+    """Refused for material fields: the standard assembly, the adjoint,
+    harmonic sets, and the product on an LDS-mode plan (more than two sets on
+    a thickness row)."""
     lam = W.smooth_material_field(_curved(0), np.random.default_rng(8300))
     plan = L.Plan(lam, set_mode="bucket")
     C, th = _mats(lam)
     for call in (lambda: plan.assemble_standard(C, th),
-                 lambda: plan.adjoint(C, th, torch.zeros(plan.nnz, dtype=torch.float64, device="cuda")),
-                 lambda: plan.apply(C, th, torch.zeros(plan.n_rows, dtype=torch.float64, device="cuda"))):
+                 lambda: plan.adjoint(C, th, torch.zeros(plan.nnz, dtype=torch.float64, device="cuda"))):
         with pytest.raises(L.LamError):
             call()
     with pytest.raises(L.LamError):
         L.Plan(lam, set_mode="harmonic9")
+    thick = W.smooth_material_field(W.flat_shell(W.paper_plate(2, 3, 4, "0/45/-45/90")), np.random.default_rng(8310))
+    tp = L.Plan(thick, set_mode="bucket")
+    Ct, tht = _mats(thick)
+    with pytest.raises(L.LamError):
+        tp.apply(Ct, tht, torch.zeros(tp.n_rows, dtype=torch.float64, device="cuda"))
+
+
+def _clamped_rows(lam, n_rows):
+    """Rows of the functions on the first in-plane edge (i1 = 0): all
+    thickness functions and components there are fixed."""
+    n1 = len(lam.k1) - lam.p1 - 1
+    n2 = len(lam.k2) - lam.p2 - 1
+    rows = np.arange(n_rows)
+    return ((rows // 3) % (n1 * n2)) % n1 == 0
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_material_field_product_and_cg(oracle, L, case):
+    """Material fields on curved and rational shells: y = K u and the
+    Dirichlet-eliminated product against the oracle's K (relative 1e-12) for
+    the anisotropically perturbed field, and CG for the clamped shell under a
+    positive definite field (the same field without the perturbation, which
+    can make a control tensor indefinite) to a recurrence residual of 1e-12
+    with the normwise backward error of x against the oracle's K_ff below
+    1e-12."""
+    rng = np.random.default_rng(8350 + case)
+    base = [_curved(0), W.nurbs_annulus_shell(3, 2, 2, [0, 90], [W.material(W.CARBON)], [0, 0], name="annulus"),
+            _curved(1)][case]
+    lam = W.smooth_material_field(base, rng)
+    lam_pd = W.smooth_material_field(base, np.random.default_rng(8360 + case), sym=0.0)
+    rp, ci, v = oracle.assemble(lam)
+    n = len(rp) - 1
+    K = oracle.to_scipy(rp, ci, v, n)
+    Kpd = oracle.to_scipy(*oracle.assemble(lam_pd), n)
+    fixed = _clamped_rows(lam, n)
+    free = ~fixed
+    fx = torch.tensor(fixed, device="cuda")
+    C, th = _mats(lam)
+    Cp, thp = _mats(lam_pd)
+    for mode in ("bucket", "ply"):
+        plan = L.Plan(lam, set_mode=mode)
+        u = rng.standard_normal(n)
+        y = plan.apply(C, th, torch.tensor(u, device="cuda")).cpu().numpy()
+        e_y = float(np.linalg.norm(y - K @ u) / np.linalg.norm(K @ u))
+        yf = plan.apply(C, th, torch.tensor(u, device="cuda"), fixed=fx).cpu().numpy()
+        yfr = np.where(free, K @ np.where(free, u, 0.0), u)
+        e_yf = float(np.linalg.norm(yf - yfr) / np.linalg.norm(yfr))
+        pp = L.Plan(lam_pd, set_mode=mode)
+        b = rng.standard_normal(n)
+        x, iters, res = pp.cg(Cp, thp, torch.tensor(b, device="cuda"), fixed=fx, tol=1e-12, max_iter=50 * n)
+        x = x.cpu().numpy()
+        Kff = Kpd[free][:, free]
+        r = Kff @ x[free] - b[free]
+        e_cg = float(np.linalg.norm(r) / (np.sqrt(Kff.multiply(Kff).sum()) * np.linalg.norm(x[free]) +
+                                          np.linalg.norm(b[free])))
+        print("  %s %s n %d: apply rel %.2e, eliminated %.2e, cg %d iterations residual %.2e backward error %.2e"
+              % (lam.name, mode, n, e_y, e_yf, iters, res, e_cg), flush=True)
+        assert e_y <= TOL and e_yf <= TOL
+        assert res <= 1e-12 and e_cg <= 1e-12
+        assert np.abs(x[fixed]).max() == 0.0
 
 
 def test_curved_shell_product_and_adjoint(oracle, L):
@@ -172,7 +234,7 @@ def test_curved_shell_product_and_adjoint(oracle, L):
     assert ry <= TOL and eG <= GTOL and eU <= GTOL
 
 
-def _sampled(oracle, L, lam, mode, n_rand=600, tuning=None):
+def _sampled(oracle, L, lam, mode, n_rand=600, tuning=None, product=False):
     plan = L.Plan(lam, set_mode=mode, tuning=tuning)
     print("case", lam.name, mode, "nnz", plan.nnz, flush=True)
     rowptr, colind = plan.pattern()
@@ -191,6 +253,13 @@ def _sampled(oracle, L, lam, mode, n_rand=600, tuning=None):
     print("  rows %d relF %.3e relmax %.3e" % (len(rows), relF, relM), flush=True)
     assert relF <= TOL and relM <= TOL
     plan.check()
+    if product:  # the same rows of y = K u
+        u_np = rng.standard_normal(plan.n_rows)
+        y = plan.apply(C, th, torch.tensor(u_np, device="cuda")).cpu().numpy()[rows]
+        yr = np.add.reduceat(ref * u_np[col], ptr[:-1])
+        rel = float(np.linalg.norm(y - yr) / np.linalg.norm(yr))
+        print("  product rows rel %.3e" % rel, flush=True)
+        assert rel <= TOL
 
 
 def test_full_size_curved_shell_sampled(oracle, L):
@@ -205,4 +274,4 @@ def test_full_size_nurbs_field_sampled(oracle, L):
     lam = W.nurbs_annulus_shell(48, 32, 2, [0, 45, -45, 90] * 4, [W.material(W.CARBON), W.material(W.GLASS)],
                                 [(l // 4) % 2 for l in range(16)], p2=2, name="annulus_48x32_16ply")
     lam = W.smooth_material_field(lam, np.random.default_rng(8600))
-    _sampled(oracle, L, lam, "bucket", n_rand=300)
+    _sampled(oracle, L, lam, "bucket", n_rand=300, product=True)
