@@ -232,6 +232,17 @@ def _sample_parity(oracle, lam, plan, vals, rowptr, n_rows=200, seed=3):
     return float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
 
 
+def _sample_product_parity(oracle, lam, plan, y, u_np, n_rows=50, seed=5):
+    """Relative error of sampled rows of y = K u against the oracle's rows of K times u."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    rows = np.unique(rng.choice(plan.n_rows, size=n_rows, replace=False))
+    ptr, col, ref = oracle.assemble_rows(lam, rows)
+    yr = np.add.reduceat(ref * u_np[col], ptr[:-1])
+    yg = y.cpu().numpy()[rows]
+    return float(np.linalg.norm(yg - yr) / np.linalg.norm(yr))
+
+
 def _fast_workload(torch, np, L, O, lam, mode, steps, warmup, standard_steps=0):
     """Fast assembly of another plate: nnz/s, scatter roofline, sampled parity."""
     from paper_1905_05417_amd import autotune
@@ -501,8 +512,10 @@ def _shell_workloads(torch, np, L, W, O, steps, warmup):
     curved B-spline mid-surface with constant ply materials (moments by 2D
     Gauss sums with the per-point map gradient, then the register-mode
     scatter), its standard assembly, and a NURBS quarter annulus whose two
-    materials vary over the plane (P of every set from the field, LDS-mode
-    scatter).  Sampled parity against the oracle for each."""
+    materials vary over the plane (P of every set integrated with the field
+    inside, read by the register-mode scatter).  For both, the matrix-free
+    product y = K u (for the field, each call integrates P again before the
+    product kernel).  Sampled parity against the oracle for each."""
     out = {}
     cases = [("curved_bspline_p2_64x64_32ply", _curved_shell_64(W), True),
              ("nurbs_annulus_field_p2_64x64_32ply", _nurbs_field_64(W, np), False)]
@@ -518,6 +531,13 @@ def _shell_workloads(torch, np, L, W, O, steps, warmup):
                "scatter_ms": ms_k, "scatter_hbm_frac": 8.0 * plan.nnz / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS,
                "parity_sample_relF": _sample_parity(O, lam, plan, vals, rowptr, n_rows=100)}
         plan.check()
+        u_np = np.random.default_rng(12).standard_normal(plan.n_rows)
+        u = torch.tensor(u_np, device="cuda")
+        y = torch.empty_like(u)
+        ms_a, ms_ak = _time_steps(torch, lambda: plan.apply(C, th, u, out=y), steps, warmup, L, "apply")
+        rec["product"] = {"ms_per_apply": ms_a, "kernel_ms": ms_ak,
+                          "parity_sample_rel": _sample_product_parity(O, lam, plan, y, u_np, n_rows=50)}
+        del u, y
         if std:
             ms_std, _ = _time_steps(torch, lambda: plan.assemble_standard(C, th, out=vals), 3, 1, L, "standard")
             rec["standard"] = {"ms_per_step": ms_std, "speedup_fast_vs_standard": ms_std / ms,
