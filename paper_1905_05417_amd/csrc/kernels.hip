@@ -467,6 +467,14 @@ __global__ void __launch_bounds__(KRON_THREADS) k_apply(Dev d, const double *__r
   for (int e = sig; e < nq; e += nth) lq[e] = qd[4 * (int64_t)NSC * zk0 + e];
   __syncthreads();
   double pr[NSC][4][3];
+  // material fields: group-local set of each slot's P, so that a slot whose
+  // set the previous chunk also had (the planner keeps it in place) is not
+  // read again.  Not for constant materials: there P is a few FMAs from
+  // registers and LDS, and the tracking registers cost the two-slot kernel a
+  // wave per SIMD (167 -> 182 VGPRs; the 64x64 32-ply product 0.25 -> 0.32 ms).
+  int slot_set[NSC];
+#pragma unroll
+  for (int w = 0; w < NSC; ++w) slot_set[w] = -1;
   int ch = ch0 - 1, ch_end = itg0;  // chunk of the current row; its last row + 1
   for (int b0 = itg0; b0 < itg1; b0 += APPLY_ROWS) {  // block-uniform trip counts and barriers
     const int nb = itg1 - b0 < APPLY_ROWS ? itg1 - b0 : APPLY_ROWS;
@@ -480,6 +488,8 @@ __global__ void __launch_bounds__(KRON_THREADS) k_apply(Dev d, const double *__r
         for (int w = 0; w < NSC; ++w) {
           const int ls = w < nsc ? d.chunk_lset[c0 + w] : ns;  // unused slots: the zero block
           if constexpr (FIELD) {
+            if (ls == slot_set[w]) continue;  // the slot keeps its set (and P) from the previous chunk
+            slot_set[w] = ls;
             const int gs = ls < ns ? d.group_set[s0 + ls] : -1;
 #pragma unroll
             for (int ab = 0; ab < 4; ++ab)
