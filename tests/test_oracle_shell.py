@@ -223,3 +223,31 @@ def test_gradients_refuse_material_fields(oracle):
     lam = W.linear_material_field(_shells()[0], np.zeros((2, 6, 6)))
     with pytest.raises(ValueError):
         oracle.grad_D_uu(lam, np.ones(lam.n_rows))
+
+
+def test_smooth_field_generator_definiteness(oracle):
+    """The seeded field generator: without its symmetric perturbation every
+    control tensor is a positive multiple of its material, so K of a clamped
+    shell is positive definite (the oracle's K has a positive diagonal and a
+    successful Cholesky on the free rows); the default perturbation, which the
+    assembly parity tests use, can make a control tensor indefinite."""
+    import scipy.linalg
+    base = W.curved_shell(2, 3, 2, [0, 60, -30], [W.material(W.CARBON), W.material(W.GLASS)], [0, 1, 0], ne2=2,
+                          name="curved_p2")
+    pd = W.smooth_material_field(base, np.random.default_rng(8360), sym=0.0)
+    C0 = np.asarray(base.C)
+    for m in range(C0.shape[0]):
+        ratio = np.asarray(pd.C)[m] / C0[m][None]
+        nz = C0[m] != 0
+        # every control tensor is a single positive multiple of the material
+        assert np.allclose(ratio[:, nz], ratio[:, nz][:, :1], rtol=1e-12) and (ratio[:, nz] > 0).all()
+    rp, ci, v = oracle.assemble(pd)
+    n = len(rp) - 1
+    K = oracle.to_scipy(rp, ci, v, n).toarray()
+    n1, n2 = len(pd.k1) - pd.p1 - 1, len(pd.k2) - pd.p2 - 1
+    free = ((np.arange(n) // 3) % (n1 * n2)) % n1 != 0
+    Kff = K[np.ix_(free, free)]
+    assert (np.diag(Kff) > 0).all()
+    scipy.linalg.cholesky(Kff)  # raises if not positive definite
+    ev = np.linalg.eigvalsh(np.asarray(W.smooth_material_field(base, np.random.default_rng(8350)).C))
+    assert ev.min() < 0  # the default perturbation: indefinite control tensors occur
