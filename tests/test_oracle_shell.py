@@ -237,10 +237,12 @@ def test_smooth_field_generator_definiteness(oracle):
     pd = W.smooth_material_field(base, np.random.default_rng(8360), sym=0.0)
     C0 = np.asarray(base.C)
     for m in range(C0.shape[0]):
-        ratio = np.asarray(pd.C)[m] / C0[m][None]
         nz = C0[m] != 0
+        Cm = np.asarray(pd.C)[m].reshape(-1, 36)
+        assert (Cm[:, ~nz.ravel()] == 0).all()
+        ratio = Cm[:, nz.ravel()] / C0[m][nz][None]
         # every control tensor is a single positive multiple of the material
-        assert np.allclose(ratio[:, nz], ratio[:, nz][:, :1], rtol=1e-12) and (ratio[:, nz] > 0).all()
+        assert np.allclose(ratio, ratio[:, :1], rtol=1e-12) and (ratio > 0).all()
     rp, ci, v = oracle.assemble(pd)
     n = len(rp) - 1
     K = oracle.to_scipy(rp, ci, v, n).toarray()
