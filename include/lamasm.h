@@ -321,7 +321,9 @@ LAM_API lam_status lam_batch_info(const lam_batch *batch, int32_t *n_waves, int6
  * its nonzeros and rows, and its offsets into C_all and theta_all (doubles). */
 LAM_API lam_status lam_batch_laminate(const lam_batch *batch, int32_t i, int32_t *wave, int64_t *vals_offset,
                                       int64_t *nnz, int64_t *n_rows, int64_t *C_offset, int64_t *theta_offset);
-/* Copies every plan's tables and the work queues to ws; synchronizes stream. */
+/* Copies every plan's tables, the per-laminate device views and descriptors and the
+ * per-wave work lists (one item per block of each of a wave's launches: set and 1D
+ * prep, 2D moments, scatter) to ws; synchronizes stream. */
 LAM_API lam_status lam_batch_upload(const lam_batch *batch, void *ws, int64_t ws_bytes, void *stream);
 /* CSR pattern of laminate i, as lam_pattern. */
 LAM_API lam_status lam_batch_pattern(const lam_batch *batch, const void *ws, int64_t ws_bytes, int32_t i,
